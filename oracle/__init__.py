@@ -1,0 +1,190 @@
+"""CPU oracle for the AAR solver: plain FP64 C (``aar_oracle.c``) behind ctypes.
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the slow, obviously correct
+reference the GPU solver is checked against.  Only ``tests/``, the package
+smoke check and the benchmark's CPU-baseline leg may import it; the solver
+never does, and it shares no code with the GPU path.
+
+Every function cites the part of the paper (arXiv:1606.08740) it follows;
+the readings taken where the paper is silent are listed at the top of
+``aar_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "aar_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, NOT_CONVERGED, BREAKDOWN, BAD_ARG = 0, 1, 2, -1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP) into oracle/liboracle.so."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("h", ctypes.c_double * 3), ("bc", ctypes.c_int32 * 3),
+                ("radius", ctypes.c_int32), ("diffusion", ctypes.c_double),
+                ("shift", ctypes.c_double), ("velocity", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        pp = ctypes.POINTER(_Problem)
+        lib.oracle_fd_weights.argtypes = [ctypes.c_int, dp]
+        lib.oracle_apply.argtypes = [pp, dp, dp]
+        lib.oracle_diagonal.argtypes = [pp, dp]
+        lib.oracle_jacobi_eigen.argtypes = [ctypes.c_int, dp, dp]
+        lib.oracle_pinv_solve.argtypes = [ctypes.c_int, dp, dp, dp]
+        lib.oracle_pinv_solve.restype = ctypes.c_int
+        lib.oracle_aar_solve.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_double, ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_int64), dp, dp, ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_int64)]
+        lib.oracle_aar_solve.restype = ctypes.c_int
+        lib.oracle_relative_residual.argtypes = [pp, dp, dp]
+        lib.oracle_relative_residual.restype = ctypes.c_double
+        lib.oracle_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class _Bound:
+    """A ctypes problem struct plus the arrays it points into (kept alive)."""
+
+    def __init__(self, prob):
+        self.vel = None if prob.velocity is None else _f64(prob.velocity)
+        s = _Problem()
+        s.n = (ctypes.c_int32 * 3)(*[int(v) for v in prob.n])
+        s.h = (ctypes.c_double * 3)(*[float(v) for v in prob.h])
+        s.bc = (ctypes.c_int32 * 3)(*[int(v) for v in prob.bc])
+        s.radius = int(prob.radius)
+        s.diffusion = float(prob.diffusion)
+        s.shift = float(prob.shift)
+        s.velocity = None if self.vel is None else self.vel.ctypes.data
+        self.s = s
+        self.size = int(prob.n[0]) * int(prob.n[1]) * int(prob.n[2])
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+
+def fd_weights(r: int) -> np.ndarray:
+    """Order-2r central second-difference weights w_0..w_r (the paper's
+    sixth-order discretization, Secs. 3.2-3.3, is r = 3)."""
+    w = np.zeros(7)
+    _load().oracle_fd_weights(int(r), _ptr(w))
+    return w[: r + 1].copy()
+
+
+def apply(prob, x) -> np.ndarray:
+    """y = A x for the finite-difference operator of `prob` (Eq. 1)."""
+    b = _Bound(prob)
+    x = _f64(x)
+    y = np.empty(b.size)
+    _load().oracle_apply(b.ref, _ptr(x), _ptr(y))
+    return y
+
+
+def diagonal(prob) -> np.ndarray:
+    """D = diag(A): the Jacobi preconditioner M = D (Sec. 2, AAJ special case)."""
+    b = _Bound(prob)
+    d = np.empty(b.size)
+    _load().oracle_diagonal(b.ref, _ptr(d))
+    return d
+
+
+def jacobi_eigen(S) -> tuple:
+    """Cyclic Jacobi eigendecomposition of a symmetric matrix: (eigenvalues, V)."""
+    S = _f64(S).copy()
+    l = S.shape[0]
+    V = np.empty((l, l))
+    _load().oracle_jacobi_eigen(l, _ptr(S), _ptr(V))
+    return np.diag(S).copy(), V
+
+
+def pinv_solve(G, c) -> tuple:
+    """gamma = pinv(F^T F) F^T f given G = F^T F and c = F^T f (Eq. 3 with the
+    Moore-Penrose pseudoinverse, Sec. 3.2).  Returns (gamma, rank)."""
+    G = _f64(G)
+    c = _f64(c)
+    l = c.shape[0]
+    g = np.zeros(max(l, 1))
+    rank = _load().oracle_pinv_solve(l, _ptr(G), _ptr(c), _ptr(g))
+    return g[:l].copy(), rank
+
+
+def aar_solve(prob, b, x0=None, omega=0.6, beta=0.6, m=7, p=6, tol=1e-10, max_iter=1_000_000,
+              trace_cap: int = 0) -> dict:
+    """Jacobi-preconditioned AAR (Eqs. 2-6) in FP64.
+
+    Returns a dict with x, status, iterations, relres (last measured
+    ||b - A x_k|| / ||b||) and, when trace_cap > 0, `trace`: one row per
+    Anderson step [k, r_k, ||f_k||, ||f_k - F_k gamma_k||, rank].
+    """
+    bd = _Bound(prob)
+    b = _f64(b)
+    x = np.zeros(bd.size) if x0 is None else _f64(x0).copy()
+    it = ctypes.c_int64(0)
+    rr = ctypes.c_double(0.0)
+    tl = ctypes.c_int64(0)
+    tr = np.zeros((max(trace_cap, 1), 5))
+    st = _load().oracle_aar_solve(bd.ref, _ptr(b), _ptr(x), float(omega), float(beta), int(m), int(p),
+                                  float(tol), int(max_iter), ctypes.byref(it), ctypes.byref(rr),
+                                  _ptr(tr) if trace_cap > 0 else None, int(trace_cap),
+                                  ctypes.byref(tl))
+    out = {"x": x, "status": st, "iterations": it.value, "relres": rr.value}
+    if trace_cap > 0:
+        out["trace"] = tr[: tl.value].copy()
+    return out
+
+
+def relative_residual(prob, b, x) -> float:
+    """||b - A x|| / ||b|| in FP64 with the oracle's own operator (Sec. 2)."""
+    bd = _Bound(prob)
+    return float(_load().oracle_relative_residual(bd.ref, _ptr(_f64(b)), _ptr(_f64(x))))
+
+
+def threads() -> int:
+    """OpenMP threads the oracle runs with."""
+    return int(_load().oracle_threads())
+
+
+def solve_workload_params(params) -> dict:
+    """Keyword arguments of aar_solve taken from an inputs.Params."""
+    return dict(omega=params.omega, beta=params.beta, m=params.m, p=params.p, tol=params.tol,
+                max_iter=params.max_iter)
+
+
+__all__ = ["build", "fd_weights", "apply", "diagonal", "jacobi_eigen", "pinv_solve", "aar_solve",
+           "relative_residual", "threads", "solve_workload_params",
+           "OK", "NOT_CONVERGED", "BREAKDOWN", "BAD_ARG"]
+

@@ -1,0 +1,292 @@
+"""Seeded synthetic inputs for the AAR stencil workloads.
+
+This module holds random-number generation and input synthesis only:
+right-hand sides, velocity fields, instance sizes and shifts, and the plain
+description of each workload (grid, spacing, boundary conditions, stencil
+radius, solver parameters).  None of the solver's arithmetic lives here: no
+finite-difference weights, no operator, no preconditioner, no AAR step.  Both
+the CPU oracle's tests and the GPU path draw their inputs from here, so the
+two sides always see bit-identical data.
+
+Random numbers come from a counter-based SplitMix64 (Steele, Lea and Flood,
+"Fast splittable pseudorandom number generators", OOPSLA 2014): element i of
+stream (seed, stream) is mix64(key + (i + 1) * 0x9E3779B97F4A7C15), where
+key = mix64(seed * 0x9E3779B97F4A7C15 ^ (stream + 1) * 0xD1B54A32D192ED03).
+Uniforms take the top 53 bits; normals use the Box-Muller transform on
+consecutive pairs.
+
+The paper's own workloads (electron densities and pseudocharges of aluminium
+supercells for the Poisson equation, Eq. 8; the orbital-free DFT Helmholtz
+kernel equation, Eq. 7; Matrix Market systems, Sec. 3.1) are not available.
+The generators below stand in for them with the same structure: smooth
+periodic charge distributions with zero mean, shifted periodic Helmholtz
+operators, and nonsymmetric (upwinded convection-diffusion) operators.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_STREAM_MUL = 0xD1B54A32D192ED03
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+_MASK64 = (1 << 64) - 1
+
+BC_ZERO_DIRICHLET = 0
+BC_PERIODIC = 1
+
+
+def _mix64(z: np.ndarray) -> np.ndarray:
+    z = (z ^ (z >> np.uint64(30))) * _M1
+    z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def _mix64_int(z: int) -> int:
+    z &= _MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    return z ^ (z >> 31)
+
+
+def stream_key(seed: int, stream: int) -> int:
+    """64-bit key of stream `stream` under `seed`."""
+    return _mix64_int((seed * 0x9E3779B97F4A7C15) ^ ((stream + 1) * _STREAM_MUL))
+
+
+def splitmix64(key: int, count: int, start: int = 0) -> np.ndarray:
+    """Counter-based SplitMix64 outputs for counters start+1 .. start+count."""
+    with np.errstate(over="ignore"):
+        ctr = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+        z = np.uint64(key & _MASK64) + ctr * _GOLDEN
+        return _mix64(z)
+
+
+def uniform(seed: int, stream: int, count: int) -> np.ndarray:
+    """U[0,1) doubles from the top 53 bits."""
+    z = splitmix64(stream_key(seed, stream), count)
+    return (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def normal(seed: int, stream: int, count: int) -> np.ndarray:
+    """N(0,1) doubles by Box-Muller on consecutive uniform pairs."""
+    pairs = (count + 1) // 2
+    u = uniform(seed, stream, 2 * pairs)
+    u1 = 1.0 - u[0::2]                      # (0, 1]: log is finite
+    u2 = u[1::2]
+    rad = np.sqrt(-2.0 * np.log(u1))
+    ang = 2.0 * np.pi * u2
+    out = np.empty(2 * pairs)
+    out[0::2] = rad * np.cos(ang)
+    out[1::2] = rad * np.sin(ang)
+    return out[:count]
+
+
+# --------------------------------------------------------------------------
+# Workload descriptions
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class Problem:
+    """One linear system -a*Lap_h(u) + v.grad_h(u) + sigma*u = b on a 3D grid.
+
+    Unknowns are stored with x fastest: index i + n0*(j + n1*k).  With zero
+    Dirichlet boundaries grid point i sits at (i+1)*h; with periodic
+    boundaries at i*h.  `radius` r selects the order-2r central second
+    difference; `velocity` (planar [vx|vy|vz], radius 1 only) adds first-order
+    upwind convection.
+    """
+    n: tuple
+    h: tuple
+    bc: tuple
+    radius: int
+    diffusion: float = 1.0
+    shift: float = 0.0
+    velocity: Optional[np.ndarray] = None
+
+    @property
+    def size(self) -> int:
+        return int(self.n[0]) * int(self.n[1]) * int(self.n[2])
+
+
+@dataclasses.dataclass
+class Params:
+    """AAR parameters: omega, beta (Eq. 3), history m (Eqs. 4-5), period p,
+    tolerance on ||b - A x|| / ||b||, cap on iterations, precision mode."""
+    omega: float = 0.6
+    beta: float = 0.6
+    m: int = 7
+    p: int = 6
+    tol: float = 1e-10
+    max_iter: int = 1_000_000
+    precision: int = 0          # 0 fp64, 1 mixed fp32, 2 mixed fp32 + bf16 history
+    inner_tol: float = 1e-5
+    max_outer: int = 30
+    flags: int = 0
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    problems: list
+    b: list
+    x0: list
+    params: Params
+
+
+def dirichlet_poisson_problem(n: int) -> Problem:
+    h = 1.0 / (n + 1)
+    return Problem(n=(n, n, n), h=(h, h, h), bc=(BC_ZERO_DIRICHLET,) * 3, radius=1)
+
+
+def dirichlet_poisson_7pt(n: int = 32, seed: int = 1, tol: float = 1e-8) -> Workload:
+    """3D Poisson, 7-point, zero Dirichlet, h = 1/(n+1), b ~ N(0,1) i.i.d., x0 = 0."""
+    prob = dirichlet_poisson_problem(n)
+    b = normal(seed, 0, prob.size)
+    return Workload(f"dirichlet_poisson_7pt_{n}^3", [prob], [b], [np.zeros(prob.size)],
+                    Params(omega=0.6, beta=0.6, m=7, p=6, tol=tol))
+
+
+def gaussian_charges(n: int, seed: int, count: int = 64, width_cells: float = 2.0) -> np.ndarray:
+    """Sum of `count` Gaussian charges on the periodic unit cube minus its mean.
+
+    Grid point i sits at i/n.  Charge q has centre c_q ~ U[0,1)^3, sign
+    s_q = +-1 (fair coin) and width w = width_cells/n; its value at a point is
+    s_q * exp(-d^2 / (2 w^2)) with d the minimum-image distance.  The sum is
+    computed in FP64 and its FP64 mean is subtracted (a periodic Poisson
+    right-hand side must integrate to zero).  This stands in for the
+    electron-plus-pseudocharge density of the paper's periodic Poisson
+    problem (Eq. 8).
+    """
+    u = uniform(seed, 1, 4 * count).reshape(count, 4)
+    centres = u[:, :3]
+    signs = np.where(u[:, 3] < 0.5, -1.0, 1.0)
+    w = width_cells / n
+    grid = np.arange(n) / n
+    b = np.zeros((n, n, n))
+    for q in range(count):
+        prof = []
+        for ax in range(3):
+            d = grid - centres[q, ax]
+            d -= np.round(d)                 # minimum image on the unit period
+            prof.append(np.exp(-d * d / (2.0 * w * w)))
+        # layout [k][j][i]: i (axis 0) fastest
+        b += signs[q] * (prof[2][:, None, None] * prof[1][None, :, None] * prof[0][None, None, :])
+    b -= b.mean()
+    return b.reshape(-1)
+
+
+def periodic_problem(n: int, radius: int, shift: float = 0.0) -> Problem:
+    h = 1.0 / n
+    return Problem(n=(n, n, n), h=(h, h, h), bc=(BC_PERIODIC,) * 3, radius=radius, shift=shift)
+
+
+def periodic_poisson_charges(n: int = 192, seed: int = 2, radius: int = 6, tol: float = 1e-10,
+                             precision: int = 0) -> Workload:
+    """Periodic Poisson, order-2r central FD (37-point at r=6), Gaussian charges rhs."""
+    prob = periodic_problem(n, radius)
+    b = gaussian_charges(n, seed)
+    return Workload(f"periodic_poisson_r{radius}_{n}^3", [prob], [b], [np.zeros(prob.size)],
+                    Params(omega=0.6, beta=0.6, m=7, p=6, tol=tol, precision=precision))
+
+
+def convection_field(n: int, seed: int, modes: int = 8, peclet: float = 0.5) -> np.ndarray:
+    """Smooth random velocity on the Dirichlet grid, planar [vx|vy|vz].
+
+    Component c is sum_q a_cq sin(2 pi k_cq . x + phi_cq) with a ~ N(0,1),
+    k uniform over {-2..2}^3 minus the zero vector, phi ~ U[0, 2 pi).  The
+    field is scaled so that the peak cell Peclet number max |v_c| h / 2
+    (diffusion 1) equals `peclet`.  Points sit at (i+1) h, h = 1/(n+1).
+    """
+    h = 1.0 / (n + 1)
+    kvecs = np.array([(a, b, c) for c in range(-2, 3) for b in range(-2, 3) for a in range(-2, 3)
+                      if (a, b, c) != (0, 0, 0)], dtype=np.float64)
+    amp = normal(seed, 2, 3 * modes).reshape(3, modes)
+    pick = uniform(seed, 3, 3 * modes).reshape(3, modes)
+    phase = 2.0 * np.pi * uniform(seed, 4, 3 * modes).reshape(3, modes)
+    x = (np.arange(n) + 1.0) * h
+    X = x[None, None, :]
+    Y = x[None, :, None]
+    Z = x[:, None, None]
+    v = np.zeros((3, n, n, n))
+    for c in range(3):
+        for q in range(modes):
+            kv = kvecs[min(int(pick[c, q] * len(kvecs)), len(kvecs) - 1)]
+            v[c] += amp[c, q] * np.sin(2.0 * np.pi * (kv[0] * X + kv[1] * Y + kv[2] * Z) + phase[c, q])
+    scale = peclet * 2.0 / (h * np.abs(v).max())
+    return (v * scale).reshape(-1)
+
+
+def convection_diffusion_upwind(n: int = 128, seed: int = 4, tol: float = 1e-10,
+                                precision: int = 1) -> Workload:
+    """-Lap u + v.grad u = b, 7-point + first-order upwind, zero Dirichlet, b ~ U(-1,1)."""
+    prob = dirichlet_poisson_problem(n)
+    prob.velocity = convection_field(n, seed)
+    b = 2.0 * uniform(seed, 0, prob.size) - 1.0
+    return Workload(f"convection_diffusion_upwind_{n}^3", [prob], [b], [np.zeros(prob.size)],
+                    Params(omega=0.6, beta=0.6, m=10, p=4, tol=tol, precision=precision))
+
+
+def batched_helmholtz(count: int = 512, seed: int = 5, nmin: int = 16, nmax: int = 96,
+                      radius: int = 4, shift_max: float = 10.0, tol: float = 1e-10,
+                      precision: int = 1) -> Workload:
+    """`count` periodic shifted Helmholtz systems -Lap u + sigma u = b, order 2r.
+
+    Edge n_i ~ U{nmin..nmax}, h_i = 1/n_i, sigma_i ~ U(0, shift_max),
+    b_i ~ N(0,1) i.i.d.  A real, positive-shift stand-in for the paper's
+    periodic Helmholtz problem (Eq. 7), which is solved many times over in
+    the applications that motivate the method.
+    """
+    u = uniform(seed, 1, 2 * count).reshape(count, 2)
+    probs, bs, xs = [], [], []
+    for i in range(count):
+        n = nmin + min(int(u[i, 0] * (nmax - nmin + 1)), nmax - nmin)
+        sigma = shift_max * u[i, 1]
+        if sigma == 0.0:
+            sigma = shift_max * 2.0 ** -53
+        prob = periodic_problem(n, radius, shift=sigma)
+        probs.append(prob)
+        bs.append(normal(seed, 100 + i, prob.size))
+        xs.append(np.zeros(prob.size))
+    return Workload(f"batched_helmholtz_r{radius}_{count}x[{nmin}..{nmax}]^3", probs, bs, xs,
+                    Params(omega=0.6, beta=0.6, m=7, p=6, tol=tol, precision=precision))
+
+
+def workload(index: int, **kw) -> Workload:
+    """The five evaluation workloads, 1-based, at full size unless overridden."""
+    if index == 1:
+        return dirichlet_poisson_7pt(**kw)
+    if index == 2:
+        return periodic_poisson_charges(**kw)
+    if index == 3:
+        kw.setdefault("n", 256)
+        kw.setdefault("seed", 3)
+        kw.setdefault("precision", 1)
+        return periodic_poisson_charges(**kw)
+    if index == 4:
+        return convection_diffusion_upwind(**kw)
+    if index == 5:
+        return batched_helmholtz(**kw)
+    raise ValueError(f"no workload {index}")
+
+
+def random_vector(seed: int, stream: int, count: int) -> np.ndarray:
+    """Plain N(0,1) test vector."""
+    return normal(seed, stream, count)
+
+
+def problem_size_bytes(prob: Problem, elem: int = 8) -> int:
+    return prob.size * elem
+
+
+__all__ = [
+    "BC_ZERO_DIRICHLET", "BC_PERIODIC", "Problem", "Params", "Workload",
+    "stream_key", "splitmix64", "uniform", "normal", "random_vector",
+    "gaussian_charges", "convection_field",
+    "dirichlet_poisson_problem", "periodic_problem",
+    "dirichlet_poisson_7pt", "periodic_poisson_charges", "convection_diffusion_upwind",
+    "batched_helmholtz", "workload",
+]
+
