@@ -1,0 +1,158 @@
+/*
+ * aar.h — C ABI of the MI355X (gfx950) Alternating Anderson-Richardson solver.
+ *
+ * Method: Suryanarayana, Pratapa and Pask, "Alternating Anderson-Richardson
+ * method: an efficient alternative to preconditioned Krylov methods for
+ * large, sparse linear systems", arXiv:1606.08740.  The solver applies the
+ * fixed-point iteration x_{k+1} = x_k + B_k f_k of Sec. 2, Eqs. 2-3, with the
+ * left-preconditioned residual f_k = M^{-1}(b - A x_k) (Eq. 6) and the Jacobi
+ * preconditioner M = diag(A) (Sec. 2, the AAJ special case; Secs. 3.2-3.3):
+ *   - Richardson, B_k = omega I, when (k+1)/p is not a natural number;
+ *   - Anderson, B_k = beta I - (X_k + beta F_k)(F_k^T F_k)^+ F_k^T, when it is,
+ *     with X_k, F_k the last m iterate and residual differences (Eqs. 4-5)
+ *     and (.)^+ the Moore-Penrose pseudoinverse (Sec. 3.2).
+ * Convergence, ||b - A x_k||_2 / ||b||_2 < tol, is tested at Anderson steps
+ * only (Sec. 2, text after Eq. 6).  The iteration count reported is the
+ * number of residual evaluations k+1, a multiple of p on convergence.
+ *
+ * The operator is a finite-difference stencil on a 3D grid (the paper's
+ * Poisson and Helmholtz problems, Eqs. 7-8, use sixth-order central
+ * differences on a uniform grid):
+ *   A u = -a Lap_h u + v . grad_h u + sigma u
+ * with the order-2r central second difference along each axis (weights of
+ * the standard central formula) and optional first-order upwind convection.
+ *
+ * Conventions for every entry point:
+ *   - All functions are extern "C", never throw, and return aar_status.
+ *   - A negative status means nothing was computed and no output was
+ *     written; aar_last_error() then describes the problem (thread-local).
+ *   - A positive status (not converged, breakdown) means x holds the last
+ *     iterate, whose residual is reported.
+ *   - Vector arguments b, x, y are caller-owned FP64 device pointers,
+ *     contiguous, one value per grid point in the order i + n0*(j + n1*k).
+ *   - Work runs on the HIP stream given at creation; the solve calls return
+ *     after their results have reached the host.
+ *   - A solver handle is not thread-safe; use one handle per stream.
+ */
+#ifndef AAR_H
+#define AAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct aar_solver_t *aar_solver;
+
+typedef enum {
+    AAR_OK = 0,                 /* converged: x_k with r_k < tol                        */
+    AAR_NOT_CONVERGED = 1,      /* max_iter (or max_outer) reached                      */
+    AAR_BREAKDOWN = 2,          /* NaN or Inf in the residual or the Gram matrix        */
+    AAR_ERR_INVALID_ARG = -1,   /* bad pointer, size or parameter                       */
+    AAR_ERR_UNSUPPORTED = -2,   /* valid request outside what the library implements    */
+    AAR_ERR_DEVICE = -3,        /* HIP runtime error                                    */
+    AAR_ERR_OUT_OF_MEMORY = -4  /* device allocation failed                             */
+} aar_status;
+
+enum { AAR_BC_ZERO_DIRICHLET = 0, AAR_BC_PERIODIC = 1 };
+
+/* Arithmetic of the iteration.
+ *   AAR_FP64: every step in FP64.
+ *   AAR_MIXED_FP32: FP32 sweeps, history and Gram products (accumulated in
+ *     FP64), FP64 m x m solve, and an outer FP64 iterative refinement:
+ *     r = b - A x (FP64), inner FP32 AAR on A d = r/||r|| to inner_tol,
+ *     x += ||r|| d, until ||b - A x|| / ||b|| < tol.
+ *   AAR_MIXED_FP32_BF16HIST: as AAR_MIXED_FP32 with the history columns
+ *     stored in bfloat16 (round to nearest even). */
+enum { AAR_FP64 = 0, AAR_MIXED_FP32 = 1, AAR_MIXED_FP32_BF16HIST = 2 };
+
+enum {
+    AAR_FLAG_RECORD_RESIDUALS = 1, /* keep r_k of every Anderson step (aar_residual_log)        */
+    AAR_FLAG_NO_GRAPH = 4,         /* launch kernels one by one instead of replaying HIP graphs */
+    AAR_FLAG_NO_AUTOTUNE = 8       /* use the default tile shape instead of timing candidates   */
+};
+
+/* One linear system. */
+typedef struct {
+    int32_t n[3];            /* grid points per axis (>= 1)                                  */
+    double h[3];             /* grid spacing per axis (> 0)                                   */
+    int32_t bc[3];           /* AAR_BC_* per axis; periodic axes need n >= 2*radius + 1      */
+    int32_t radius;          /* r in 1..6: order-2r central second difference, 6r+1 points   */
+    double diffusion;        /* a (> 0)                                                      */
+    double shift;            /* sigma (>= 0)                                                 */
+    const double *velocity;  /* NULL, or device FP64 planar [vx | vy | vz] (3 N values);     */
+                             /* radius must be 1; copied at creation                         */
+} aar_problem;
+
+typedef struct {
+    double omega;            /* Richardson relaxation (Eq. 3)                    paper: 0.6  */
+    double beta;             /* Anderson relaxation (Eq. 3)                      paper: 0.6  */
+    int32_t m;               /* history length, 1..32 (Eqs. 4-5)                 paper: 9    */
+    int32_t p;               /* Anderson every p iterations, >= 1                paper: 8    */
+    double tol;              /* on ||b - A x|| / ||b||, > 0                                  */
+    int64_t max_iter;        /* cap on iterations (inner iterations in mixed mode), >= 1    */
+    int32_t precision;       /* AAR_FP64 / AAR_MIXED_FP32 / AAR_MIXED_FP32_BF16HIST          */
+    double inner_tol;        /* mixed: inner FP32 tolerance (0 selects 1e-5)                 */
+    int32_t max_outer;       /* mixed: cap on refinement steps (0 selects 30)                */
+    uint32_t flags;          /* AAR_FLAG_*                                                   */
+} aar_params;
+
+typedef struct {
+    int32_t status;          /* aar_status of this instance                                  */
+    int32_t outer_steps;     /* refinement steps (mixed), 0 in FP64 mode                     */
+    int64_t iterations;      /* residual evaluations (all inner ones in mixed mode)          */
+    double rel_residual;     /* last measured ||b - A x|| / ||b|| (FP64 in mixed mode)       */
+} aar_result;
+
+/* Create a solver for `count` systems sharing `params`.  Validates the
+ * descriptions, allocates the device workspace (history ring, partial sums,
+ * descriptors), copies velocities, and picks tile shapes.  hip_stream is a
+ * hipStream_t (NULL: the default stream).  *out receives the handle. */
+aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t count,
+                      const aar_params *params, void *hip_stream);
+
+/* Solve system 0 (count must be 1).  x holds x_0 on entry and the answer on
+ * return; b is read only.  r receives the outcome (may be NULL). */
+aar_status aar_solve(aar_solver s, const double *b, double *x, aar_result *r);
+
+/* Solve all `count` systems.  System i reads b + offsets[i] and updates
+ * x + offsets[i] (offsets: count + 1 host int64 values, offsets[i+1] -
+ * offsets[i] equal to that system's size).  results[i] (host, count entries)
+ * receives each outcome; the return value is the worst status. */
+aar_status aar_solve_batched(aar_solver s, const double *b, double *x, const int64_t *offsets,
+                             aar_result *results);
+
+/* y = A x in FP64 for system `instance` (a check of the operator). */
+aar_status aar_apply(aar_solver s, int32_t instance, const double *x, double *y);
+
+/* Copy up to `cap` recorded Anderson-step residuals r_k of system `instance`
+ * from the last solve (needs AAR_FLAG_RECORD_RESIDUALS) into host `out`;
+ * *count receives the number recorded.  In mixed mode these are the inner
+ * residuals of the last refinement step. */
+aar_status aar_residual_log(aar_solver s, int32_t instance, double *out, int64_t cap,
+                            int64_t *count);
+
+/* Device bytes aar_create would allocate for these arguments. */
+aar_status aar_workspace_bytes(const aar_problem *problems, int32_t count, const aar_params *params,
+                               size_t *bytes);
+
+/* Release the handle and its device memory (NULL is accepted). */
+aar_status aar_destroy(aar_solver s);
+
+/* Description of the last error on this thread ("" if none). */
+const char *aar_last_error(void);
+
+/* Kernel timing for measurement: when enabled, the solver brackets every
+ * Richardson sweep launch with HIP events on its stream (graphs are not used
+ * while enabled) and accumulates their durations.  aar_sweep_time returns
+ * the total milliseconds and launch count since the last reset. */
+aar_status aar_set_timing(aar_solver s, int32_t enable);
+aar_status aar_sweep_time(aar_solver s, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AAR_H */

@@ -1,0 +1,211 @@
+// Internal device-side definitions shared by the solver's HIP sources.
+//
+// Data layout in HBM (per system):
+//   x        two ping-pong copies (Richardson sweeps read one, write the other)
+//   b        right-hand side
+//   fring    m+1 slots of f_j = D^{-1}(b - A x_j); slot j mod (m+1) holds f_j
+//   dxring   q = floor(m/p) slots of the Anderson increments x_{k+1} - x_k
+//   fcur     f_k of the Anderson step in the bulk precision (bf16 history only)
+// All vectors are x-fastest, one value per grid point: i + n0*(j + n1*k).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aar {
+
+constexpr int kTX = 64;        // tile width along x: one wave64 row
+constexpr int kWY = 4;         // waves per workgroup, stacked along y
+constexpr int kThreads = kTX * kWY;
+constexpr int kMaxRadius = 6;
+constexpr int kMaxM = 32;      // history columns
+constexpr int kMaxSlots = kMaxM + 1;
+constexpr int kFastGramM = 12; // per-thread Gram accumulators up to this m
+constexpr int kXcds = 8;       // MI355X: workgroups are dealt round-robin to 8 XCDs
+
+// Per-system run state, written only by single-workgroup kernels.
+enum : int32_t {
+    kRunning = 0,
+    kConverged = 1,
+    kBreakdown = 2,
+    kStagnated = 3,
+    kMaxIter = 4,
+};
+
+struct alignas(64) InstState {
+    int64_t cycle;          // completed Anderson cycles (p iterations each)
+    int64_t iters;          // iterations at termination
+    int64_t max_iter;       // iteration cap of this run
+    double tol;             // tolerance of this run
+    int32_t status;
+    int32_t rank;           // rank kept by the last pseudoinverse
+    double nb;              // ||b||_2
+    double last_r;          // last measured ||b - A x_k|| / ||b||
+    double best_r;          // stagnation tracking (inner solves)
+    int32_t since_best;
+    int32_t log_count;
+    // update plan of the current Anderson step, x_{k+1} = x_k + sum alpha_t f_t + sum delta_a dx_a
+    int32_t nf;             // number of f slots used (l + 1); the last one is f_k
+    int32_t nd;             // number of dx slots used
+    int32_t wslot;          // dx slot receiving x_{k+1} - x_k (-1: none kept)
+    int32_t pad0;
+    int32_t fslot[kMaxSlots];
+    int32_t dslot[kMaxM];
+    double alpha[kMaxSlots];
+    double delta[kMaxM];
+};
+
+// bfloat16 storage: the upper half of an IEEE float, rounded to nearest even.
+struct bf16_t {
+    uint16_t bits;
+};
+
+template <typename H> struct Hist;
+template <> struct Hist<double> {
+    __device__ static inline double load(const double *p, int64_t i) { return p[i]; }
+    __device__ static inline void store(double *p, int64_t i, double v) { p[i] = v; }
+};
+template <> struct Hist<float> {
+    __device__ static inline float load(const float *p, int64_t i) { return p[i]; }
+    __device__ static inline void store(float *p, int64_t i, float v) { p[i] = v; }
+};
+template <> struct Hist<bf16_t> {
+    __device__ static inline float load(const bf16_t *p, int64_t i)
+    {
+        return __uint_as_float(((uint32_t)p[i].bits) << 16);
+    }
+    __device__ static inline void store(bf16_t *p, int64_t i, float v)
+    {
+        uint32_t u = __float_as_uint(v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) {           // NaN stays a (quiet) NaN
+            p[i].bits = (uint16_t)((u >> 16) | 0x40u);
+            return;
+        }
+        u += 0x7fffu + ((u >> 16) & 1u);                 // round to nearest, ties to even
+        p[i].bits = (uint16_t)(u >> 16);
+    }
+};
+
+// Operator description passed by value to the stencil kernels.
+template <typename T> struct StencilDev {
+    int32_t n0, n1, n2;
+    int32_t per0, per1, per2;   // 1: periodic axis, 0: zero Dirichlet
+    T c0[kMaxRadius + 1];       // -a w_s / h_0^2, s = 1..r (index 0 unused)
+    T c1[kMaxRadius + 1];
+    T c2[kMaxRadius + 1];
+    T sigma;
+    T diag;                     // diag(A) without convection: sigma - 2 sum_axes sum_s c[s]
+    T inv_diag;
+    T ih0, ih1, ih2;            // 1/h per axis (upwind convection)
+    const T *vel;               // planar [vx|vy|vz] or nullptr
+    int64_t N;
+};
+
+enum StencilMode : int {
+    kSweep = 0,   // f = D^-1 (b - A x); out = x + omega f; ring <- f
+    kFk = 1,      // f_k = D^-1 (b - A x); ring <- f_k; partial += ||b - A x||^2
+    kResid = 2,   // out = b - A x; partial += ||b - A x||^2
+    kApply = 3,   // out = A x
+};
+
+template <typename T> struct StencilArgs {
+    StencilDev<T> st;
+    const T *x;
+    const T *b;
+    T *out;
+    void *fring;            // H-typed ring base
+    T *fcur;                // kFk: f_k copy in T when the ring is bf16
+    double *partial;        // one double per workgroup
+    const InstState *state; // kSweep / kFk: run state for early exit and slot index
+    int64_t slot_stride;    // elements per ring slot
+    int32_t j;              // position within the cycle (0..p-1)
+    int32_t p;
+    int32_t nslots;         // m + 1
+    int32_t cz;             // z planes per workgroup
+    int32_t tiles_x, tiles_y, tiles_z;
+    T omega;
+};
+
+struct GramArgs {
+    const void *fring;
+    double *partial;        // [gridDim.x][ne]
+    const InstState *state;
+    int64_t N;
+    int64_t slot_stride;
+    int32_t m, p, nslots;
+    int32_t ne;             // m(m+1)/2 + m
+};
+
+struct LsqArgs {
+    InstState *state;
+    const double *rho_partial;   // from the kFk stencil pass
+    int32_t rho_blocks;
+    const double *gram_partial;  // from the Gram pass
+    int32_t gram_blocks;
+    int32_t ne;
+    int32_t m, p, nslots, q;     // q: dx ring slots (0: none kept)
+    double omega, beta;
+    double rcond;                // pseudoinverse threshold factor (times l * lambda_max)
+    int32_t stagnation_window;   // 0: off
+    double stagnation_factor;    // best_r must fall below factor * best_r within the window
+    double *log;                 // residual log or nullptr
+    int64_t log_cap;
+};
+
+template <typename T> struct UpdateArgs {
+    const T *xin;
+    T *xout;
+    const void *fring;
+    const T *fcur;          // non-null: use instead of the ring slot for f_k
+    T *dxring;
+    const InstState *state;
+    int64_t N;
+    int64_t slot_stride;
+};
+
+// Workgroup index -> logical tile index so that each XCD (and its L2) gets a
+// contiguous range of tiles: neighbouring tiles share halos through L2.
+__device__ inline int xcd_tile(int b, int nb)
+{
+    int xcd = b % kXcds, idx = b / kXcds;
+    int per = nb / kXcds, rem = nb % kXcds;
+    return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch helpers (implemented in the .hip sources)
+// ---------------------------------------------------------------------------
+enum class Prec : int { F64 = 0, F32 = 1, F32_BF16 = 2 };
+
+struct TileShape {
+    int ry;      // y rows per thread (tile height = kWY * ry)
+    int cz;      // z planes per workgroup
+};
+
+// Stencil pass; T is double for Prec::F64 and float otherwise; history type
+// follows prec.  Returns hipSuccess or the launch error.
+hipError_t launch_stencil_f64(int mode, Prec hist, int radius, bool conv, const TileShape &ts,
+                              StencilArgs<double> a, int *blocks_out, hipStream_t s);
+hipError_t launch_stencil_f32(int mode, Prec hist, int radius, bool conv, const TileShape &ts,
+                              StencilArgs<float> a, int *blocks_out, hipStream_t s);
+void stencil_grid(int n0, int n1, int n2, const TileShape &ts, int *tx, int *ty, int *tz, int *blocks);
+
+hipError_t launch_gram(Prec prec, const GramArgs &a, int blocks, hipStream_t s);
+hipError_t launch_lsq(const LsqArgs &a, hipStream_t s);
+hipError_t launch_update(Prec prec, const UpdateArgs<double> *a64, const UpdateArgs<float> *a32, int blocks,
+                         hipStream_t s);
+hipError_t launch_norm_partial(bool f64, const void *v, int64_t N, double *partial, int blocks, hipStream_t s);
+hipError_t launch_init_state(InstState *st, const double *partial, int blocks, int64_t max_iter, double tol,
+                             hipStream_t s);
+hipError_t launch_finish_norm(double *out, const double *partial, int blocks, hipStream_t s);
+hipError_t launch_cast_f64_to_f32(const double *in, float *out, int64_t N, const double *scale_inv_of,
+                                  hipStream_t s);
+hipError_t launch_zero_f32(float *v, int64_t N, hipStream_t s);
+hipError_t launch_correct(double *x, const float *d, const double *scale, int64_t N, hipStream_t s);
+hipError_t launch_copy_f64(const double *in, double *out, int64_t N, hipStream_t s);
+hipError_t launch_cast_f64_f32_plain(const double *in, float *out, int64_t N, hipStream_t s);
+hipError_t launch_zero_f64(double *v, int64_t N, hipStream_t s);
+
+int stream_blocks(int64_t N);
+
+}  // namespace aar

@@ -1,0 +1,944 @@
+// Host driver and C ABI of the AAR solver (include/aar.h).
+//
+// A solve runs whole AAR cycles on the GPU: p-1 fused Richardson sweeps,
+// the Anderson-step residual pass, the Gram products, the one-workgroup
+// least-squares solve and the streamed update (Sec. 2, Eqs. 2-6).  All
+// control decisions (convergence, breakdown, iteration cap, inner-solve
+// stagnation) are taken on the device by the least-squares kernel and kept
+// in a small state record; every kernel of a cycle reads that record and
+// returns at once when the system is done, so the host only replays a
+// captured graph of several cycles and polls the status between replays,
+// one graph behind.
+//
+// Mixed precision wraps the FP32 iteration in FP64 iterative refinement:
+// r = b - A x (FP64), inner FP32 AAR on A d = r / ||r||, x += ||r|| d.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/aar.h"
+#include "aar_device.h"
+
+using namespace aar;
+
+namespace {
+
+thread_local std::string g_error;
+
+aar_status fail(aar_status st, const std::string &msg)
+{
+    g_error = msg;
+    return st;
+}
+
+#define AAR_HIP(expr)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(e_ == hipErrorOutOfMemory ? AAR_ERR_OUT_OF_MEMORY : AAR_ERR_DEVICE,     \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                     \
+    } while (0)
+
+// Order-2r central second-difference weights, unit spacing: w_s for s = 1..r
+// by the product form 2 (-1)^{s+1} / s^2 * prod_{t=1..s} (r-t+1)/(r+t) of the
+// standard central formula; w_0 = -2 sum_s w_s makes the rule exact on
+// constants.
+void central_weights(int r, double *w)
+{
+    double sum = 0.0;
+    for (int s = 1; s <= r; ++s) {
+        double prod = 1.0;
+        for (int t = 1; t <= s; ++t)
+            prod *= (double)(r - t + 1) / (double)(r + t);
+        const double v = 2.0 * prod / ((double)s * s);
+        w[s] = (s & 1) ? v : -v;
+        sum += w[s];
+    }
+    w[0] = -2.0 * sum;
+}
+
+struct Operator {
+    aar_problem prob;
+    int64_t N = 0;
+    double c[3][kMaxRadius + 1] = {};
+    double diag = 0.0;    // without convection
+    double *vel64 = nullptr;
+    float *vel32 = nullptr;
+};
+
+template <typename T> StencilDev<T> make_stencil(const Operator &op, const T *vel)
+{
+    StencilDev<T> st;
+    std::memset(&st, 0, sizeof(st));
+    st.n0 = op.prob.n[0];
+    st.n1 = op.prob.n[1];
+    st.n2 = op.prob.n[2];
+    st.per0 = op.prob.bc[0] == AAR_BC_PERIODIC;
+    st.per1 = op.prob.bc[1] == AAR_BC_PERIODIC;
+    st.per2 = op.prob.bc[2] == AAR_BC_PERIODIC;
+    for (int s = 0; s <= kMaxRadius; ++s) {
+        st.c0[s] = (T)op.c[0][s];
+        st.c1[s] = (T)op.c[1][s];
+        st.c2[s] = (T)op.c[2][s];
+    }
+    st.sigma = (T)op.prob.shift;
+    st.diag = (T)op.diag;
+    st.inv_diag = (T)(1.0 / op.diag);
+    st.ih0 = (T)(1.0 / op.prob.h[0]);
+    st.ih1 = (T)(1.0 / op.prob.h[1]);
+    st.ih2 = (T)(1.0 / op.prob.h[2]);
+    st.vel = vel;
+    st.N = op.N;
+    return st;
+}
+
+TileShape default_tile(int radius, bool fp64)
+{
+    TileShape ts;
+    if (radius <= 2) {
+        ts.ry = 4;
+        ts.cz = 32;
+    } else if (fp64) {
+        ts.ry = 2;
+        ts.cz = 16;
+    } else {
+        ts.ry = 4;
+        ts.cz = 16;
+    }
+    return ts;
+}
+
+// Buffers and launch arguments of the AAR iteration in precision T.
+template <typename T> struct Path {
+    Prec hist = Prec::F64;
+    T *xa = nullptr, *xb = nullptr, *b = nullptr, *fcur = nullptr, *dx = nullptr;
+    void *fring = nullptr;
+    int64_t N = 0, slot_stride = 0;
+    TileShape ts{};
+    StencilDev<T> st{};
+    int radius = 1;
+    bool conv = false;
+    int rho_blocks = 0, gram_blocks = 0, upd_blocks = 0;
+};
+
+size_t hist_bytes(Prec p)
+{
+    return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2);
+}
+
+}  // namespace
+
+struct aar_solver_t {
+    aar_params params{};
+    std::vector<Operator> ops;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    int device = 0;
+    int q = 0;              // dx ring slots
+    int ne = 0;             // Gram entries
+    int64_t maxN = 0;
+    bool mixed = false;
+    Prec hist = Prec::F64;
+    std::vector<void *> allocations;
+
+    // device workspace (sized for the largest system)
+    InstState *state = nullptr;
+    double *part_rho = nullptr, *part_gram = nullptr, *part_norm = nullptr;
+    double *scal = nullptr;       // [0] ||r|| of the refinement, [1] ||b|| (FP64)
+    double *log = nullptr;
+    int64_t log_cap = 0;
+    Path<double> p64;
+    Path<float> p32;
+    double *x64 = nullptr, *b64 = nullptr, *r64 = nullptr;   // refinement vectors (mixed)
+
+    // graphs (single system)
+    hipGraphExec_t graph = nullptr;
+    int graph_cycles = 0;
+    int graph_instance = -1;
+
+    // pinned status mailbox
+    int32_t *host_status = nullptr;
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
+
+    // sweep timing
+    bool timing = false;
+    std::vector<hipEvent_t> tev;
+    std::vector<int64_t> tcycle;
+    size_t tused = 0;
+    double t_total_ms = 0.0;
+    int64_t t_launches = 0;
+
+    std::vector<int64_t> last_log_count;
+    int last_instance = 0;
+
+    template <typename T> T *alloc(size_t count, aar_status *st)
+    {
+        void *p = nullptr;
+        if (count == 0)
+            count = 1;
+        hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            *st = fail(e == hipErrorOutOfMemory ? AAR_ERR_OUT_OF_MEMORY : AAR_ERR_DEVICE,
+                       std::string("hipMalloc: ") + hipGetErrorString(e));
+            return nullptr;
+        }
+        allocations.push_back(p);
+        return static_cast<T *>(p);
+    }
+
+    ~aar_solver_t()
+    {
+        if (graph)
+            (void)hipGraphExecDestroy(graph);
+        for (void *p : allocations)
+            (void)hipFree(p);
+        if (host_status)
+            (void)hipHostFree(host_status);
+        for (hipEvent_t e : poll_ev)
+            if (e)
+                (void)hipEventDestroy(e);
+        for (hipEvent_t e : tev)
+            (void)hipEventDestroy(e);
+        if (capture_stream)
+            (void)hipStreamDestroy(capture_stream);
+    }
+};
+
+namespace {
+
+aar_status validate_params(const aar_params *pa)
+{
+    if (!pa)
+        return fail(AAR_ERR_INVALID_ARG, "params is NULL");
+    if (pa->m < 1 || pa->m > kMaxM)
+        return fail(AAR_ERR_INVALID_ARG, "m must be in 1..32");
+    if (pa->p < 1)
+        return fail(AAR_ERR_INVALID_ARG, "p must be >= 1");
+    if (!(pa->tol > 0.0) || !std::isfinite(pa->tol))
+        return fail(AAR_ERR_INVALID_ARG, "tol must be positive and finite");
+    if (pa->max_iter < 1)
+        return fail(AAR_ERR_INVALID_ARG, "max_iter must be >= 1");
+    if (!std::isfinite(pa->omega) || !std::isfinite(pa->beta))
+        return fail(AAR_ERR_INVALID_ARG, "omega and beta must be finite");
+    if (pa->precision < AAR_FP64 || pa->precision > AAR_MIXED_FP32_BF16HIST)
+        return fail(AAR_ERR_INVALID_ARG, "unknown precision");
+    if (!(pa->inner_tol >= 0.0) || pa->inner_tol >= 1.0 || pa->max_outer < 0)
+        return fail(AAR_ERR_INVALID_ARG, "inner_tol must be in [0, 1) and max_outer >= 0");
+    return AAR_OK;
+}
+
+aar_status validate_problem(const aar_problem &pr, int idx)
+{
+    const std::string at = " (system " + std::to_string(idx) + ")";
+    for (int a = 0; a < 3; ++a) {
+        if (pr.n[a] < 1)
+            return fail(AAR_ERR_INVALID_ARG, "n must be >= 1" + at);
+        if (!(pr.h[a] > 0.0) || !std::isfinite(pr.h[a]))
+            return fail(AAR_ERR_INVALID_ARG, "h must be positive and finite" + at);
+        if (pr.bc[a] != AAR_BC_ZERO_DIRICHLET && pr.bc[a] != AAR_BC_PERIODIC)
+            return fail(AAR_ERR_INVALID_ARG, "unknown boundary condition" + at);
+    }
+    if (pr.radius < 1 || pr.radius > kMaxRadius)
+        return fail(AAR_ERR_INVALID_ARG, "radius must be in 1..6" + at);
+    if (!(pr.diffusion > 0.0) || !std::isfinite(pr.diffusion))
+        return fail(AAR_ERR_INVALID_ARG, "diffusion must be positive and finite" + at);
+    if (!(pr.shift >= 0.0) || !std::isfinite(pr.shift))
+        return fail(AAR_ERR_INVALID_ARG, "shift must be non-negative and finite" + at);
+    if (pr.velocity && pr.radius != 1)
+        return fail(AAR_ERR_UNSUPPORTED, "convection needs radius 1" + at);
+    for (int a = 0; a < 3; ++a)
+        if (pr.bc[a] == AAR_BC_PERIODIC && pr.n[a] < 2 * pr.radius + 1)
+            return fail(AAR_ERR_UNSUPPORTED, "periodic axis shorter than the stencil (n < 2r+1)" + at);
+    const int64_t N = (int64_t)pr.n[0] * pr.n[1] * pr.n[2];
+    if (N > ((int64_t)1 << 40))
+        return fail(AAR_ERR_UNSUPPORTED, "grid too large" + at);
+    return AAR_OK;
+}
+
+Operator build_operator(const aar_problem &pr)
+{
+    Operator op;
+    op.prob = pr;
+    op.N = (int64_t)pr.n[0] * pr.n[1] * pr.n[2];
+    double w[kMaxRadius + 1];
+    central_weights(pr.radius, w);
+    double sum = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        for (int s = 1; s <= pr.radius; ++s) {
+            op.c[a][s] = -pr.diffusion * w[s] / (pr.h[a] * pr.h[a]);
+            sum += op.c[a][s];
+        }
+    }
+    op.diag = pr.shift - 2.0 * sum;
+    return op;
+}
+
+struct Sizes {
+    int64_t maxN = 0;
+    int max_stencil_blocks = 0;
+    int gram_blocks = 0;
+    int q = 0, ne = 0;
+    size_t bytes = 0;
+    int64_t log_cap = 0;
+};
+
+Sizes compute_sizes(const aar_problem *probs, int count, const aar_params *pa)
+{
+    Sizes z;
+    const bool mixed = pa->precision != AAR_FP64;
+    const Prec hist = pa->precision == AAR_FP64 ? Prec::F64
+                      : pa->precision == AAR_MIXED_FP32 ? Prec::F32 : Prec::F32_BF16;
+    int64_t vel_total = 0;
+    for (int i = 0; i < count; ++i) {
+        const aar_problem &pr = probs[i];
+        const int64_t N = (int64_t)pr.n[0] * pr.n[1] * pr.n[2];
+        z.maxN = std::max(z.maxN, N);
+        for (int f64 = 0; f64 < 2; ++f64) {
+            TileShape ts = default_tile(pr.radius, f64 == 1);
+            int tx, ty, tz, blocks;
+            stencil_grid(pr.n[0], pr.n[1], pr.n[2], ts, &tx, &ty, &tz, &blocks);
+            z.max_stencil_blocks = std::max(z.max_stencil_blocks, blocks);
+        }
+        if (pr.velocity)
+            vel_total += 3 * N;
+    }
+    z.gram_blocks = stream_blocks(z.maxN);
+    z.q = pa->m / pa->p;
+    z.ne = pa->m * (pa->m + 1) / 2 + pa->m;
+    const int64_t N = z.maxN;
+    const int slots = pa->m + 1;
+    size_t b = 0;
+    b += sizeof(InstState) * (size_t)count;
+    b += sizeof(double) * ((size_t)z.max_stencil_blocks + (size_t)z.gram_blocks * z.ne + z.gram_blocks + 8);
+    if (!mixed) {
+        b += sizeof(double) * (size_t)N * (3 + slots + z.q);
+        b += sizeof(double) * (size_t)vel_total;
+    } else {
+        b += sizeof(float) * (size_t)N * (3 + z.q);
+        b += hist_bytes(hist) * (size_t)N * slots;
+        if (hist == Prec::F32_BF16)
+            b += sizeof(float) * (size_t)N;
+        b += sizeof(double) * (size_t)N * 3;
+        b += (sizeof(double) + sizeof(float)) * (size_t)vel_total;
+    }
+    if (pa->flags & AAR_FLAG_RECORD_RESIDUALS) {
+        z.log_cap = std::min<int64_t>(pa->max_iter / pa->p + 2, (int64_t)1 << 22);
+        b += sizeof(double) * (size_t)z.log_cap;
+    }
+    z.bytes = b;
+    return z;
+}
+
+// ---------------------------------------------------------------------------
+// Enqueue one AAR cycle in precision T on stream s.
+// ---------------------------------------------------------------------------
+template <typename T> struct Launch;
+template <> struct Launch<double> {
+    static hipError_t stencil(int mode, const Path<double> &P, StencilArgs<double> a, hipStream_t s)
+    {
+        return launch_stencil_f64(mode, P.hist, P.radius, P.conv, P.ts, a, nullptr, s);
+    }
+};
+template <> struct Launch<float> {
+    static hipError_t stencil(int mode, const Path<float> &P, StencilArgs<float> a, hipStream_t s)
+    {
+        return launch_stencil_f32(mode, P.hist, P.radius, P.conv, P.ts, a, nullptr, s);
+    }
+};
+
+template <typename T>
+hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStream_t s, int64_t cycle_tag)
+{
+    const aar_params &pa = S->params;
+    StencilArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.st = P.st;
+    a.b = P.b;
+    a.fring = P.fring;
+    a.state = S->state;
+    a.slot_stride = P.slot_stride;
+    a.p = pa.p;
+    a.nslots = pa.m + 1;
+    a.omega = (T)pa.omega;
+    hipError_t e;
+    for (int j = 0; j < pa.p - 1; ++j) {
+        a.j = j;
+        a.x = (j & 1) ? P.xb : P.xa;
+        a.out = (j & 1) ? P.xa : P.xb;
+        if (S->timing) {
+            if (S->tused + 2 > S->tev.size()) {
+                for (int t = 0; t < 64; ++t) {
+                    hipEvent_t ev;
+                    if ((e = hipEventCreate(&ev)) != hipSuccess)
+                        return e;
+                    S->tev.push_back(ev);
+                }
+            }
+            if ((e = hipEventRecord(S->tev[S->tused], s)) != hipSuccess)
+                return e;
+        }
+        if ((e = Launch<T>::stencil(kSweep, P, a, s)) != hipSuccess)
+            return e;
+        if (S->timing) {
+            if ((e = hipEventRecord(S->tev[S->tused + 1], s)) != hipSuccess)
+                return e;
+            S->tcycle.push_back(cycle_tag * pa.p + j);
+            S->tused += 2;
+        }
+    }
+    const int jk = pa.p - 1;
+    T *xk = (jk & 1) ? P.xb : P.xa;
+    a.j = jk;
+    a.x = xk;
+    a.out = nullptr;
+    a.fcur = P.fcur;
+    a.partial = S->part_rho;
+    if ((e = Launch<T>::stencil(kFk, P, a, s)) != hipSuccess)
+        return e;
+
+    GramArgs g;
+    g.fring = P.fring;
+    g.partial = S->part_gram;
+    g.state = S->state;
+    g.N = P.N;
+    g.slot_stride = P.slot_stride;
+    g.m = pa.m;
+    g.p = pa.p;
+    g.nslots = pa.m + 1;
+    g.ne = S->ne;
+    if ((e = launch_gram(P.hist, g, P.gram_blocks, s)) != hipSuccess)
+        return e;
+
+    LsqArgs l;
+    l.state = S->state;
+    l.rho_partial = S->part_rho;
+    l.rho_blocks = P.rho_blocks;
+    l.gram_partial = S->part_gram;
+    l.gram_blocks = P.gram_blocks;
+    l.ne = S->ne;
+    l.m = pa.m;
+    l.p = pa.p;
+    l.nslots = pa.m + 1;
+    l.q = S->q;
+    l.omega = pa.omega;
+    l.beta = pa.beta;
+    l.rcond = std::ldexp(1.0, -52);
+    l.stagnation_window = inner ? 8 : 0;
+    l.stagnation_factor = 0.9;
+    l.log = S->log;
+    l.log_cap = S->log_cap;
+    if ((e = launch_lsq(l, s)) != hipSuccess)
+        return e;
+
+    UpdateArgs<T> u;
+    u.xin = xk;
+    u.xout = P.xa;
+    u.fring = P.fring;
+    u.fcur = P.fcur;
+    u.dxring = P.dx;
+    u.state = S->state;
+    u.N = P.N;
+    u.slot_stride = P.slot_stride;
+    if constexpr (std::is_same<T, double>::value)
+        return launch_update(P.hist, &u, nullptr, P.upd_blocks, s);
+    else
+        return launch_update(P.hist, nullptr, &u, P.upd_blocks, s);
+}
+
+constexpr int kGraphCycles = 4;
+
+// Run cycles until the device state leaves kRunning (or every cycle up to
+// max_iter has been issued).  The final state is copied to *out.
+template <typename T>
+aar_status run_cycles(aar_solver_t *S, const Path<T> &P, int64_t max_iter, bool inner, bool use_graph,
+                      InstState *out)
+{
+    const int p = S->params.p;
+    const int64_t needed = (max_iter + p - 1) / p;
+    hipStream_t s = S->stream;
+    if (use_graph && S->graph == nullptr) {
+        AAR_HIP(hipStreamBeginCapture(S->capture_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int c = 0; c < kGraphCycles && e == hipSuccess; ++c)
+            e = enqueue_cycle<T>(S, P, inner, S->capture_stream, 0);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(S->capture_stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return fail(AAR_ERR_DEVICE, std::string("graph capture: ") +
+                                            hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        hipError_t e3 = hipGraphInstantiate(&S->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        AAR_HIP(e3);
+        S->graph_cycles = kGraphCycles;
+    }
+    int64_t issued = 0;
+    int inflight = 0, slot = 0;
+    while (issued < needed) {
+        if (use_graph) {
+            AAR_HIP(hipGraphLaunch(S->graph, s));
+            issued += S->graph_cycles;
+        } else {
+            for (int c = 0; c < kGraphCycles && issued < needed; ++c, ++issued) {
+                hipError_t e = enqueue_cycle<T>(S, P, inner, s, issued);
+                if (e != hipSuccess)
+                    return fail(AAR_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+            }
+        }
+        AAR_HIP(hipMemcpyAsync(&S->host_status[slot], &S->state->status, sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+        AAR_HIP(hipEventRecord(S->poll_ev[slot], s));
+        slot ^= 1;
+        ++inflight;
+        if (inflight == 2) {
+            AAR_HIP(hipEventSynchronize(S->poll_ev[slot]));
+            --inflight;
+            if (S->host_status[slot] != kRunning)
+                break;
+        }
+    }
+    AAR_HIP(hipStreamSynchronize(s));
+    AAR_HIP(hipMemcpy(out, S->state, sizeof(InstState), hipMemcpyDeviceToHost));
+    if (S->timing) {
+        // count only sweeps that did work: cycles up to the last one that ran
+        const int64_t last_k = out->status == kMaxIter || out->status == kRunning
+                                   ? max_iter - 1
+                                   : out->iters - 1;
+        for (size_t t = 0; t < S->tcycle.size(); ++t) {
+            if (S->tcycle[t] > last_k)
+                continue;
+            float ms = 0.0f;
+            AAR_HIP(hipEventElapsedTime(&ms, S->tev[2 * t], S->tev[2 * t + 1]));
+            S->t_total_ms += ms;
+            S->t_launches += 1;
+        }
+        S->tcycle.clear();
+        S->tused = 0;
+    }
+    return AAR_OK;
+}
+
+aar_status status_of(const InstState &st)
+{
+    switch (st.status) {
+    case kConverged:
+        return AAR_OK;
+    case kBreakdown:
+        return AAR_BREAKDOWN;
+    default:
+        return AAR_NOT_CONVERGED;
+    }
+}
+
+// Point Path<T> at the workspace for system `idx`.
+template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool f64)
+{
+    const Operator &op = S->ops[idx];
+    P.N = op.N;
+    P.radius = op.prob.radius;
+    P.conv = op.prob.velocity != nullptr;
+    P.ts = default_tile(op.prob.radius, f64);
+    int tx, ty, tz, blocks;
+    stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], P.ts, &tx, &ty, &tz, &blocks);
+    P.rho_blocks = blocks;
+    P.gram_blocks = stream_blocks(op.N);
+    P.upd_blocks = stream_blocks(op.N);
+    P.slot_stride = op.N;
+    if constexpr (std::is_same<T, double>::value)
+        P.st = make_stencil<double>(op, op.vel64);
+    else
+        P.st = make_stencil<float>(op, op.vel32);
+}
+
+// x (length N, FP64 device) on entry x0, on exit the answer of system idx.
+aar_status solve_one(aar_solver_t *S, int idx, const double *b, double *x, aar_result *res)
+{
+    const aar_params &pa = S->params;
+    const Operator &op = S->ops[idx];
+    const int64_t N = op.N;
+    hipStream_t s = S->stream;
+    const bool use_graph = !(pa.flags & AAR_FLAG_NO_GRAPH) && !S->timing && S->ops.size() == 1;
+    if (S->graph && S->graph_instance != idx) {
+        (void)hipGraphExecDestroy(S->graph);
+        S->graph = nullptr;
+    }
+    S->graph_instance = idx;
+    S->last_instance = idx;
+    aar_result r{};
+    InstState st{};
+
+    if (!S->mixed) {
+        Path<double> &P = S->p64;
+        bind_path(S, P, idx, true);
+        AAR_HIP(hipMemcpyAsync(P.b, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        AAR_HIP(hipMemcpyAsync(P.xa, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        const int nb_blocks = stream_blocks(N);
+        AAR_HIP(launch_norm_partial(true, P.b, N, S->part_norm, nb_blocks, s));
+        AAR_HIP(launch_init_state(S->state, S->part_norm, nb_blocks, pa.max_iter, pa.tol, s));
+        AAR_HIP(hipMemcpyAsync(&st, S->state, sizeof(InstState), hipMemcpyDeviceToHost, s));
+        AAR_HIP(hipStreamSynchronize(s));
+        if (st.nb == 0.0) {
+            AAR_HIP(launch_zero_f64(x, N, s));
+            AAR_HIP(hipStreamSynchronize(s));
+            r.status = AAR_OK;
+            if (res)
+                *res = r;
+            S->last_log_count[idx] = 0;
+            return AAR_OK;
+        }
+        aar_status e = run_cycles<double>(S, P, pa.max_iter, false, use_graph, &st);
+        if (e != AAR_OK)
+            return e;
+        // where x ended: after j sweeps of a cycle it is in xb when j is odd
+        const int64_t done = (st.status == kMaxIter || st.status == kRunning) ? pa.max_iter : st.iters;
+        const int64_t j = (done - 1) % pa.p;     // last iteration's position in its cycle
+        const bool anderson_last = (st.status == kMaxIter || st.status == kRunning) && j == pa.p - 1;
+        const double *xf;
+        if (st.status == kConverged || st.status == kBreakdown)
+            xf = ((pa.p - 1) & 1) ? P.xb : P.xa;     // x_k of the Anderson step
+        else if (anderson_last)
+            xf = P.xa;                              // the last iteration was an update
+        else
+            xf = ((j + 1) & 1) ? P.xb : P.xa;       // after j+1 sweeps of the cycle
+        AAR_HIP(hipMemcpyAsync(x, xf, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        AAR_HIP(hipStreamSynchronize(s));
+        r.status = status_of(st);
+        r.iterations = (st.status == kMaxIter || st.status == kRunning) ? pa.max_iter : st.iters;
+        r.rel_residual = st.last_r;
+        r.outer_steps = 0;
+        S->last_log_count[idx] = st.log_count;
+        if (res)
+            *res = r;
+        return (aar_status)r.status;
+    }
+
+    // ---- mixed precision: FP64 refinement around FP32 AAR ----
+    Path<float> &P = S->p32;
+    bind_path(S, P, idx, false);
+    Path<double> R64;
+    bind_path(S, R64, idx, true);
+    AAR_HIP(hipMemcpyAsync(S->b64, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    AAR_HIP(hipMemcpyAsync(S->x64, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    const int nb_blocks = stream_blocks(N);
+    AAR_HIP(launch_norm_partial(true, S->b64, N, S->part_norm, nb_blocks, s));
+    AAR_HIP(launch_finish_norm(S->scal + 1, S->part_norm, nb_blocks, s));
+    double host_scal[2];
+    AAR_HIP(hipMemcpyAsync(host_scal, S->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    AAR_HIP(hipStreamSynchronize(s));
+    const double nb = host_scal[1];
+    if (nb == 0.0) {
+        AAR_HIP(launch_zero_f64(x, N, s));
+        AAR_HIP(hipStreamSynchronize(s));
+        r.status = AAR_OK;
+        if (res)
+            *res = r;
+        S->last_log_count[idx] = 0;
+        return AAR_OK;
+    }
+    const double inner_tol = pa.inner_tol > 0.0 ? pa.inner_tol : 1e-5;
+    const int max_outer = pa.max_outer > 0 ? pa.max_outer : 30;
+    int64_t used = 0;
+    int outer = 0;
+    aar_status final = AAR_NOT_CONVERGED;
+    double rel = 0.0;
+    for (;;) {
+        // r = b - A x in FP64 and its norm
+        StencilArgs<double> ra;
+        std::memset(&ra, 0, sizeof(ra));
+        ra.st = R64.st;
+        ra.x = S->x64;
+        ra.b = S->b64;
+        ra.out = S->r64;
+        ra.partial = S->part_rho;
+        AAR_HIP(launch_stencil_f64(kResid, Prec::F64, R64.radius, R64.conv, R64.ts, ra, nullptr, s));
+        AAR_HIP(launch_finish_norm(S->scal, S->part_rho, R64.rho_blocks, s));
+        AAR_HIP(hipMemcpyAsync(host_scal, S->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        AAR_HIP(hipStreamSynchronize(s));
+        rel = host_scal[0] / nb;
+        if (!std::isfinite(rel)) {
+            final = AAR_BREAKDOWN;
+            break;
+        }
+        if (rel < pa.tol) {
+            final = AAR_OK;
+            break;
+        }
+        if (outer >= max_outer || used >= pa.max_iter) {
+            final = AAR_NOT_CONVERGED;
+            break;
+        }
+        // inner FP32 AAR on A d = r / ||r||, d_0 = 0
+        AAR_HIP(launch_cast_f64_to_f32(S->r64, P.b, N, S->scal, s));
+        AAR_HIP(launch_zero_f32(P.xa, N, s));
+        AAR_HIP(launch_norm_partial(false, P.b, N, S->part_norm, nb_blocks, s));
+        const int64_t budget = pa.max_iter - used;
+        AAR_HIP(launch_init_state(S->state, S->part_norm, nb_blocks, budget, inner_tol, s));
+        aar_status e = run_cycles<float>(S, P, budget, true, use_graph, &st);
+        if (e != AAR_OK)
+            return e;
+        if (st.status == kBreakdown) {
+            final = AAR_BREAKDOWN;
+            used += st.iters;
+            break;
+        }
+        const int64_t done = (st.status == kMaxIter || st.status == kRunning) ? budget : st.iters;
+        used += done;
+        const int64_t j = (done - 1) % pa.p;
+        const bool anderson_last = (st.status == kMaxIter || st.status == kRunning) && j == pa.p - 1;
+        const float *df;
+        if (st.status == kConverged || st.status == kStagnated)
+            df = ((pa.p - 1) & 1) ? P.xb : P.xa;
+        else if (anderson_last)
+            df = P.xa;
+        else
+            df = ((j + 1) & 1) ? P.xb : P.xa;
+        AAR_HIP(launch_correct(S->x64, df, S->scal, N, s));
+        ++outer;
+    }
+    AAR_HIP(hipMemcpyAsync(x, S->x64, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    AAR_HIP(hipStreamSynchronize(s));
+    r.status = final;
+    r.iterations = used;
+    r.outer_steps = outer;
+    r.rel_residual = rel;
+    S->last_log_count[idx] = st.log_count;
+    if (res)
+        *res = r;
+    return final;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *aar_last_error(void)
+{
+    return g_error.c_str();
+}
+
+aar_status aar_workspace_bytes(const aar_problem *problems, int32_t count, const aar_params *params,
+                               size_t *bytes)
+{
+    if (!problems || count < 1 || !bytes)
+        return fail(AAR_ERR_INVALID_ARG, "problems, count or bytes invalid");
+    aar_status st = validate_params(params);
+    if (st != AAR_OK)
+        return st;
+    for (int i = 0; i < count; ++i)
+        if ((st = validate_problem(problems[i], i)) != AAR_OK)
+            return st;
+    *bytes = compute_sizes(problems, count, params).bytes;
+    return AAR_OK;
+}
+
+aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t count, const aar_params *params,
+                      void *hip_stream)
+{
+    g_error.clear();
+    if (!out)
+        return fail(AAR_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!problems || count < 1)
+        return fail(AAR_ERR_INVALID_ARG, "problems is NULL or count < 1");
+    aar_status st = validate_params(params);
+    if (st != AAR_OK)
+        return st;
+    for (int i = 0; i < count; ++i)
+        if ((st = validate_problem(problems[i], i)) != AAR_OK)
+            return st;
+
+    std::unique_ptr<aar_solver_t> S(new aar_solver_t());
+    S->params = *params;
+    S->stream = (hipStream_t)hip_stream;
+    S->mixed = params->precision != AAR_FP64;
+    S->hist = params->precision == AAR_FP64 ? Prec::F64
+              : params->precision == AAR_MIXED_FP32 ? Prec::F32 : Prec::F32_BF16;
+    AAR_HIP(hipGetDevice(&S->device));
+    AAR_HIP(hipStreamCreateWithFlags(&S->capture_stream, hipStreamNonBlocking));
+    AAR_HIP(hipHostMalloc((void **)&S->host_status, 2 * sizeof(int32_t), hipHostMallocDefault));
+    for (auto &e : S->poll_ev)
+        AAR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+
+    const Sizes z = compute_sizes(problems, count, params);
+    S->maxN = z.maxN;
+    S->q = z.q;
+    S->ne = z.ne;
+    S->last_log_count.assign(count, 0);
+    const int64_t N = z.maxN;
+    const int slots = params->m + 1;
+
+    st = AAR_OK;
+    S->state = S->alloc<InstState>(1, &st);
+    S->part_rho = S->alloc<double>(z.max_stencil_blocks, &st);
+    S->part_gram = S->alloc<double>((size_t)z.gram_blocks * z.ne, &st);
+    S->part_norm = S->alloc<double>(z.gram_blocks, &st);
+    S->scal = S->alloc<double>(8, &st);
+    if (st != AAR_OK)
+        return st;
+    if (z.log_cap > 0) {
+        S->log_cap = z.log_cap;
+        S->log = S->alloc<double>(z.log_cap, &st);
+    }
+    if (!S->mixed) {
+        Path<double> &P = S->p64;
+        P.hist = Prec::F64;
+        P.xa = S->alloc<double>(N, &st);
+        P.xb = S->alloc<double>(N, &st);
+        P.b = S->alloc<double>(N, &st);
+        P.fring = S->alloc<double>((size_t)N * slots, &st);
+        P.dx = S->q > 0 ? S->alloc<double>((size_t)N * S->q, &st) : nullptr;
+    } else {
+        Path<float> &P = S->p32;
+        P.hist = S->hist;
+        P.xa = S->alloc<float>(N, &st);
+        P.xb = S->alloc<float>(N, &st);
+        P.b = S->alloc<float>(N, &st);
+        if (S->hist == Prec::F32_BF16) {
+            P.fring = S->alloc<bf16_t>((size_t)N * slots, &st);
+            P.fcur = S->alloc<float>(N, &st);
+        } else {
+            P.fring = S->alloc<float>((size_t)N * slots, &st);
+        }
+        P.dx = S->q > 0 ? S->alloc<float>((size_t)N * S->q, &st) : nullptr;
+        S->x64 = S->alloc<double>(N, &st);
+        S->b64 = S->alloc<double>(N, &st);
+        S->r64 = S->alloc<double>(N, &st);
+    }
+    if (st != AAR_OK)
+        return st;
+
+    for (int i = 0; i < count; ++i) {
+        Operator op = build_operator(problems[i]);
+        if (problems[i].velocity) {
+            op.vel64 = S->alloc<double>(3 * op.N, &st);
+            if (st != AAR_OK)
+                return st;
+            AAR_HIP(hipMemcpyAsync(op.vel64, problems[i].velocity, sizeof(double) * 3 * op.N,
+                                   hipMemcpyDeviceToDevice, S->stream));
+            if (S->mixed) {
+                op.vel32 = S->alloc<float>(3 * op.N, &st);
+                if (st != AAR_OK)
+                    return st;
+                AAR_HIP(launch_cast_f64_f32_plain(op.vel64, op.vel32, 3 * op.N, S->stream));
+            }
+        }
+        S->ops.push_back(op);
+    }
+    AAR_HIP(hipStreamSynchronize(S->stream));
+    *out = S.release();
+    return AAR_OK;
+}
+
+aar_status aar_destroy(aar_solver s)
+{
+    if (!s)
+        return AAR_OK;
+    (void)hipStreamSynchronize(s->stream);
+    delete s;
+    return AAR_OK;
+}
+
+aar_status aar_solve(aar_solver s, const double *b, double *x, aar_result *r)
+{
+    g_error.clear();
+    if (!s || !b || !x)
+        return fail(AAR_ERR_INVALID_ARG, "solver, b or x is NULL");
+    if (s->ops.size() != 1)
+        return fail(AAR_ERR_INVALID_ARG, "aar_solve needs a solver created with count == 1");
+    return solve_one(s, 0, b, x, r);
+}
+
+aar_status aar_solve_batched(aar_solver s, const double *b, double *x, const int64_t *offsets,
+                             aar_result *results)
+{
+    g_error.clear();
+    if (!s || !b || !x || !offsets || !results)
+        return fail(AAR_ERR_INVALID_ARG, "solver, b, x, offsets or results is NULL");
+    const int count = (int)s->ops.size();
+    for (int i = 0; i < count; ++i) {
+        if (offsets[i] < 0 || offsets[i + 1] - offsets[i] != s->ops[i].N)
+            return fail(AAR_ERR_INVALID_ARG, "offsets do not match the system sizes (system " +
+                                                 std::to_string(i) + ")");
+    }
+    aar_status worst = AAR_OK;
+    for (int i = 0; i < count; ++i) {
+        aar_status st = solve_one(s, i, b + offsets[i], x + offsets[i], &results[i]);
+        if (st < 0)
+            return st;
+        if (st > worst)
+            worst = st;
+    }
+    return worst;
+}
+
+aar_status aar_apply(aar_solver s, int32_t instance, const double *x, double *y)
+{
+    g_error.clear();
+    if (!s || !x || !y)
+        return fail(AAR_ERR_INVALID_ARG, "solver, x or y is NULL");
+    if (instance < 0 || instance >= (int)s->ops.size())
+        return fail(AAR_ERR_INVALID_ARG, "instance out of range");
+    Path<double> P;
+    bind_path(s, P, instance, true);
+    StencilArgs<double> a;
+    std::memset(&a, 0, sizeof(a));
+    a.st = P.st;
+    a.x = x;
+    a.out = y;
+    AAR_HIP(launch_stencil_f64(kApply, Prec::F64, P.radius, P.conv, P.ts, a, nullptr, s->stream));
+    AAR_HIP(hipStreamSynchronize(s->stream));
+    return AAR_OK;
+}
+
+aar_status aar_residual_log(aar_solver s, int32_t instance, double *out, int64_t cap, int64_t *count)
+{
+    g_error.clear();
+    if (!s || !count || (cap > 0 && !out))
+        return fail(AAR_ERR_INVALID_ARG, "solver, out or count invalid");
+    if (instance < 0 || instance >= (int)s->ops.size())
+        return fail(AAR_ERR_INVALID_ARG, "instance out of range");
+    if (!s->log)
+        return fail(AAR_ERR_INVALID_ARG, "solver created without AAR_FLAG_RECORD_RESIDUALS");
+    if (instance != s->last_instance && s->ops.size() > 1)
+        return fail(AAR_ERR_UNSUPPORTED, "only the last solved system's log is kept");
+    const int64_t have = std::min<int64_t>(s->last_log_count[instance], s->log_cap);
+    *count = have;
+    const int64_t n = std::min(have, cap);
+    if (n > 0)
+        AAR_HIP(hipMemcpy(out, s->log, sizeof(double) * n, hipMemcpyDeviceToHost));
+    return AAR_OK;
+}
+
+aar_status aar_set_timing(aar_solver s, int32_t enable)
+{
+    if (!s)
+        return fail(AAR_ERR_INVALID_ARG, "solver is NULL");
+    s->timing = enable != 0;
+    s->t_total_ms = 0.0;
+    s->t_launches = 0;
+    s->tcycle.clear();
+    s->tused = 0;
+    return AAR_OK;
+}
+
+aar_status aar_sweep_time(aar_solver s, double *total_ms, int64_t *launches)
+{
+    if (!s || !total_ms || !launches)
+        return fail(AAR_ERR_INVALID_ARG, "argument is NULL");
+    *total_ms = s->t_total_ms;
+    *launches = s->t_launches;
+    return AAR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,310 @@
+// Stencil passes of the AAR iteration on gfx950.
+//
+// One kernel template covers the four passes that apply the operator:
+//   kSweep  the Richardson iteration of Eq. 3 (first case) fused with the
+//           Jacobi-preconditioned residual of Eq. 6 and the history write:
+//           f_j = D^{-1}(b - A x_j), x_{j+1} = x_j + omega f_j, ring <- f_j;
+//   kFk     the residual of an Anderson step: ring <- f_k, and the partial
+//           sums of ||b - A x_k||^2 for the convergence test (Sec. 2);
+//   kResid  r = b - A x and ||r||^2 (FP64 iterative refinement);
+//   kApply  y = A x.
+//
+// The operator is A u = -a Lap_h u + v . grad_h u + sigma u with order-2r
+// central differences per axis, written in difference form
+//   sum_s c_s [(u_{i+s} - u_i) + (u_{i-s} - u_i)],  c_s = -a w_s / h^2,
+// which equals the usual weighted sum because w_0 = -2 sum_s w_s, and keeps
+// A 1 = sigma 1 exact in FP32 (the near-null constant mode of the shifted
+// periodic problems).  Upwind convection (radius 1): v (u_i - u_{i-1}) / h for
+// v > 0, else v (u_{i+1} - u_i) / h.
+//
+// Tiling (2.5D): a workgroup of 64 x 4 threads owns a 64 x (4 RY) tile of one
+// xy-plane and marches through `cz` planes along z.  Each thread keeps its
+// column's 2r+1 z-values in registers (a queue advanced once per plane), and
+// the current plane plus an r-wide halo sits in LDS for the x and y taps.  So
+// every interior value is fetched from global memory once per pass; halos
+// are re-fetched from L2.  Tiles are assigned so that each XCD works on a
+// contiguous block of tiles (shared halos stay in its L2).
+#include "aar_device.h"
+
+namespace aar {
+
+__device__ inline int wrap_index(int g, int n)
+{
+    g %= n;
+    return g < 0 ? g + n : g;
+}
+
+// Value at (gx, gy, gz) under the boundary rule of each axis.
+template <typename T>
+__device__ inline T load_bc(const T *__restrict__ x, int gx, int gy, int gz, const StencilDev<T> &st)
+{
+    if (gx < 0 || gx >= st.n0) {
+        if (!st.per0)
+            return T(0);
+        gx = wrap_index(gx, st.n0);
+    }
+    if (gy < 0 || gy >= st.n1) {
+        if (!st.per1)
+            return T(0);
+        gy = wrap_index(gy, st.n1);
+    }
+    if (gz < 0 || gz >= st.n2) {
+        if (!st.per2)
+            return T(0);
+        gz = wrap_index(gz, st.n2);
+    }
+    return x[gx + (int64_t)st.n0 * (gy + (int64_t)st.n1 * gz)];
+}
+
+template <typename T> __device__ inline T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    return v;
+}
+
+template <typename T, typename H, int R, bool CONV, int MODE, int RY>
+__global__ __launch_bounds__(kThreads) void k_stencil(const StencilArgs<T> a)
+{
+    constexpr int TY = kWY * RY;
+    constexpr int LX = kTX + 2 * R;
+    constexpr int LY = TY + 2 * R;
+    __shared__ T sh[LY][LX];
+    __shared__ double red[kWY];
+
+    const StencilDev<T> &st = a.st;
+    int64_t k = 0;
+    if constexpr (MODE == kSweep || MODE == kFk) {
+        const InstState *s = a.state;
+        if (s->status != kRunning)
+            return;
+        k = s->cycle * a.p + a.j;
+        if (k >= s->max_iter)
+            return;
+    }
+
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int tid = tx + kTX * ty;
+    int lin = xcd_tile(blockIdx.x, gridDim.x);
+    const int bx = lin % a.tiles_x;
+    lin /= a.tiles_x;
+    const int by = lin % a.tiles_y;
+    const int bz = lin / a.tiles_y;
+    const int x0 = bx * kTX, y0 = by * TY;
+    const int z0 = bz * a.cz;
+    const int z1 = min(z0 + a.cz, st.n2);
+    const int gx = x0 + tx;
+    const int64_t plane = (int64_t)st.n0 * st.n1;
+
+    H *fout = nullptr;
+    if constexpr (MODE == kSweep || MODE == kFk)
+        fout = reinterpret_cast<H *>(a.fring) + (int64_t)(k % a.nslots) * a.slot_stride;
+
+    // z-queue: q[ry][d] = x at plane z - R + d of this thread's column
+    T q[RY][2 * R + 1];
+#pragma unroll
+    for (int ry = 0; ry < RY; ++ry) {
+        const int gy = y0 + ty + ry * kWY;
+#pragma unroll
+        for (int d = 0; d < 2 * R; ++d)
+            q[ry][d] = load_bc(a.x, gx, gy, z0 - R + d, st);
+    }
+
+    double acc = 0.0;
+    constexpr int kHaloRows = 2 * R * LX;
+    constexpr int kHalo = kHaloRows + TY * 2 * R;
+
+    for (int z = z0; z < z1; ++z) {
+#pragma unroll
+        for (int ry = 0; ry < RY; ++ry)
+            q[ry][2 * R] = load_bc(a.x, gx, y0 + ty + ry * kWY, z + R, st);
+
+        __syncthreads();   // previous plane's taps have been read
+#pragma unroll
+        for (int ry = 0; ry < RY; ++ry)
+            sh[R + ty + ry * kWY][R + tx] = q[ry][R];
+        for (int h = tid; h < kHalo; h += kThreads) {
+            int ly, lx;
+            if (h < kHaloRows) {
+                const int r = h / LX;
+                lx = h - r * LX;
+                ly = r < R ? r : r + TY;
+            } else {
+                const int t = h - kHaloRows;
+                const int c = t % (2 * R);
+                ly = R + t / (2 * R);
+                lx = c < R ? c : c + kTX;
+            }
+            sh[ly][lx] = load_bc(a.x, x0 + lx - R, y0 + ly - R, z, st);
+        }
+        __syncthreads();
+
+#pragma unroll
+        for (int ry = 0; ry < RY; ++ry) {
+            const int gy = y0 + ty + ry * kWY;
+            const int lx = R + tx, ly = R + ty + ry * kWY;
+            const T c = q[ry][R];
+            T ax = st.sigma * c;
+#pragma unroll
+            for (int s = 1; s <= R; ++s) {
+                ax += st.c0[s] * ((sh[ly][lx + s] - c) + (sh[ly][lx - s] - c));
+                ax += st.c1[s] * ((sh[ly + s][lx] - c) + (sh[ly - s][lx] - c));
+                ax += st.c2[s] * ((q[ry][R + s] - c) + (q[ry][R - s] - c));
+            }
+            const bool valid = gx < st.n0 && gy < st.n1;
+            if (!valid)
+                continue;
+            const int64_t id = gx + (int64_t)st.n0 * gy + plane * z;
+            T dg = st.diag;
+            if constexpr (CONV) {
+                const T v0 = st.vel[id], v1 = st.vel[st.N + id], v2 = st.vel[2 * st.N + id];
+                ax += v0 > T(0) ? -v0 * st.ih0 * (sh[ly][lx - 1] - c) : v0 * st.ih0 * (sh[ly][lx + 1] - c);
+                ax += v1 > T(0) ? -v1 * st.ih1 * (sh[ly - 1][lx] - c) : v1 * st.ih1 * (sh[ly + 1][lx] - c);
+                ax += v2 > T(0) ? -v2 * st.ih2 * (q[ry][R - 1] - c) : v2 * st.ih2 * (q[ry][R + 1] - c);
+                dg += fabs(v0) * st.ih0 + fabs(v1) * st.ih1 + fabs(v2) * st.ih2;
+            }
+            if constexpr (MODE == kApply) {
+                a.out[id] = ax;
+            } else {
+                const T res = a.b[id] - ax;
+                if constexpr (MODE == kResid) {
+                    a.out[id] = res;
+                    acc += (double)res * (double)res;
+                } else {
+                    const T f = CONV ? res / dg : res * st.inv_diag;
+                    Hist<H>::store(fout, id, f);
+                    if constexpr (MODE == kSweep) {
+                        a.out[id] = c + a.omega * f;
+                    } else {
+                        if (a.fcur)
+                            a.fcur[id] = f;
+                        acc += (double)res * (double)res;
+                    }
+                }
+            }
+        }
+
+#pragma unroll
+        for (int ry = 0; ry < RY; ++ry)
+#pragma unroll
+            for (int d = 0; d < 2 * R; ++d)
+                q[ry][d] = q[ry][d + 1];
+    }
+
+    if constexpr (MODE == kFk || MODE == kResid) {
+        acc = wave_sum(acc);
+        if (tx == 0)
+            red[ty] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int w = 0; w < kWY; ++w)
+                s += red[w];
+            a.partial[blockIdx.x] = s;
+        }
+    }
+}
+
+void stencil_grid(int n0, int n1, int n2, const TileShape &ts, int *tx, int *ty, int *tz, int *blocks)
+{
+    const int TY = kWY * ts.ry;
+    *tx = (n0 + kTX - 1) / kTX;
+    *ty = (n1 + TY - 1) / TY;
+    *tz = (n2 + ts.cz - 1) / ts.cz;
+    *blocks = *tx * *ty * *tz;
+}
+
+template <typename T, typename H, int R, bool CONV, int MODE, int RY>
+static hipError_t launch_one(StencilArgs<T> a, const TileShape &ts, int *blocks_out, hipStream_t s)
+{
+    int tx, ty, tz, blocks;
+    stencil_grid(a.st.n0, a.st.n1, a.st.n2, ts, &tx, &ty, &tz, &blocks);
+    a.tiles_x = tx;
+    a.tiles_y = ty;
+    a.tiles_z = tz;
+    a.cz = ts.cz;
+    if (blocks_out)
+        *blocks_out = blocks;
+    hipLaunchKernelGGL((k_stencil<T, H, R, CONV, MODE, RY>), dim3(blocks), dim3(kTX, kWY), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, typename H, int R, bool CONV, int MODE>
+static hipError_t launch_ry(StencilArgs<T> a, const TileShape &ts, int *blocks_out, hipStream_t s)
+{
+    switch (ts.ry) {
+    case 1:
+        return launch_one<T, H, R, CONV, MODE, 1>(a, ts, blocks_out, s);
+    case 2:
+        return launch_one<T, H, R, CONV, MODE, 2>(a, ts, blocks_out, s);
+    case 4:
+        return launch_one<T, H, R, CONV, MODE, 4>(a, ts, blocks_out, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, typename H, int MODE>
+static hipError_t launch_radius(int radius, bool conv, StencilArgs<T> a, const TileShape &ts, int *blocks_out,
+                                hipStream_t s)
+{
+    if (conv) {
+        if (radius != 1)
+            return hipErrorInvalidValue;
+        return launch_ry<T, H, 1, true, MODE>(a, ts, blocks_out, s);
+    }
+    switch (radius) {
+    case 1:
+        return launch_ry<T, H, 1, false, MODE>(a, ts, blocks_out, s);
+    case 2:
+        return launch_ry<T, H, 2, false, MODE>(a, ts, blocks_out, s);
+    case 3:
+        return launch_ry<T, H, 3, false, MODE>(a, ts, blocks_out, s);
+    case 4:
+        return launch_ry<T, H, 4, false, MODE>(a, ts, blocks_out, s);
+    case 5:
+        return launch_ry<T, H, 5, false, MODE>(a, ts, blocks_out, s);
+    case 6:
+        return launch_ry<T, H, 6, false, MODE>(a, ts, blocks_out, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_stencil_f64(int mode, Prec hist, int radius, bool conv, const TileShape &ts,
+                              StencilArgs<double> a, int *blocks_out, hipStream_t s)
+{
+    if (hist != Prec::F64)
+        return hipErrorInvalidValue;
+    switch (mode) {
+    case kSweep:
+        return launch_radius<double, double, kSweep>(radius, conv, a, ts, blocks_out, s);
+    case kFk:
+        return launch_radius<double, double, kFk>(radius, conv, a, ts, blocks_out, s);
+    case kResid:
+        return launch_radius<double, double, kResid>(radius, conv, a, ts, blocks_out, s);
+    case kApply:
+        return launch_radius<double, double, kApply>(radius, conv, a, ts, blocks_out, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_stencil_f32(int mode, Prec hist, int radius, bool conv, const TileShape &ts,
+                              StencilArgs<float> a, int *blocks_out, hipStream_t s)
+{
+    if (mode == kSweep || mode == kFk) {
+        const bool bf = hist == Prec::F32_BF16;
+        if (mode == kSweep)
+            return bf ? launch_radius<float, bf16_t, kSweep>(radius, conv, a, ts, blocks_out, s)
+                      : launch_radius<float, float, kSweep>(radius, conv, a, ts, blocks_out, s);
+        return bf ? launch_radius<float, bf16_t, kFk>(radius, conv, a, ts, blocks_out, s)
+                  : launch_radius<float, float, kFk>(radius, conv, a, ts, blocks_out, s);
+    }
+    if (mode == kApply)
+        return launch_radius<float, float, kApply>(radius, conv, a, ts, blocks_out, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace aar

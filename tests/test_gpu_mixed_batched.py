@@ -1,0 +1,78 @@
+"""GPU parity of the mixed-precision path (FP32 AAR inside FP64 iterative
+refinement) and of the batched entry point, against the FP64 CPU oracle.
+
+The mixed path does not reproduce the oracle's iterates (it iterates in
+FP32 on refinement corrections), so parity is on the answer: the oracle's
+own FP64 operator must confirm ||b - A x|| / ||b|| < tol, and x must agree
+with the oracle's FP64 solution within the conditioning bound.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1606_08740_amd import aar, inputs
+from tests.gpu_util import gpu_solve, rel_err, say, to_dev, mean_free
+
+pytestmark = pytest.mark.gpu
+
+MIXED_CASES = [
+    ("c1_32_dirichlet", lambda: inputs.workload(1, tol=1e-10), None),
+    ("periodic_r6_40", lambda: inputs.workload(3, n=40), "mean_free"),
+    ("upwind_24", lambda: inputs.workload(4, n=24), None),
+    ("helmholtz_r4_28_small_shift", lambda: inputs.Workload(
+        "h", [inputs.periodic_problem(28, 4, shift=0.05)], [inputs.normal(9, 0, 28 ** 3)], [None],
+        inputs.Params(tol=1e-10, precision=1)), None),
+]
+
+
+@pytest.mark.parametrize("name,make,cmp", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
+def test_mixed_reaches_fp64_tolerance(name, make, cmp):
+    w = make()
+    prob, b, prm = w.problems[0], w.b[0], w.params
+    prm.precision = aar.AAR_MIXED_FP32
+    say(f"mixed {name} n={prob.n}")
+    x, res, _ = gpu_solve(prob, prm, b)
+    assert res["status"] == aar.AAR_OK, res
+    assert res["outer_steps"] >= 1
+    rr = oracle.relative_residual(prob, b, x)
+    assert rr < prm.tol
+    ref = oracle.aar_solve(prob, b, m=prm.m, p=prm.p, tol=prm.tol)
+    a, r = (mean_free(x), mean_free(ref["x"])) if cmp == "mean_free" else (x, ref["x"])
+    assert rel_err(a, r) < 1e-6
+
+
+def test_batched_matches_solo_oracle():
+    probs = [inputs.periodic_problem(n, 4, shift=s) for n, s in [(16, 3.0), (23, 0.5), (17, 9.0), (30, 1.5)]]
+    probs.append(inputs.dirichlet_poisson_problem(21))
+    bs = [inputs.normal(40 + i, 0, p.size) for i, p in enumerate(probs)]
+    prm = inputs.Params(tol=1e-10, precision=0)
+    say("batched fp64 5 systems")
+    s = aar.Solver(probs, prm)
+    b = to_dev(np.concatenate(bs))
+    x = to_dev(np.zeros(sum(p.size for p in probs)))
+    res = s.solve_batched(b, x)
+    xs = x.cpu().numpy()
+    s.close()
+    for i, (p, bi) in enumerate(zip(probs, bs)):
+        xi = xs[s.offsets[i]: s.offsets[i + 1]]
+        ref = oracle.aar_solve(p, bi, m=prm.m, p=prm.p, tol=prm.tol)
+        assert res[i]["status"] == aar.AAR_OK
+        assert abs(res[i]["iterations"] - ref["iterations"]) <= prm.p
+        assert oracle.relative_residual(p, bi, xi) < prm.tol
+        assert rel_err(xi, ref["x"]) < 1e-6
+
+
+def test_batched_mixed_matches_solo():
+    probs = [inputs.periodic_problem(n, 4, shift=s) for n, s in [(18, 2.0), (25, 0.3), (16, 7.0)]]
+    bs = [inputs.normal(60 + i, 0, p.size) for i, p in enumerate(probs)]
+    prm = inputs.Params(tol=1e-10, precision=1)
+    say("batched mixed 3 systems")
+    s = aar.Solver(probs, prm)
+    x = to_dev(np.zeros(sum(p.size for p in probs)))
+    res = s.solve_batched(to_dev(np.concatenate(bs)), x)
+    xs = x.cpu().numpy()
+    s.close()
+    for i, (p, bi) in enumerate(zip(probs, bs)):
+        xi = xs[s.offsets[i]: s.offsets[i + 1]]
+        assert res[i]["status"] == aar.AAR_OK
+        assert oracle.relative_residual(p, bi, xi) < prm.tol
