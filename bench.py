@@ -1,0 +1,167 @@
+"""Benchmark of the MI355X AAR solver: solves/s at 1e-10 relative residual.
+
+A step is one complete AAR solve (every stage of the iteration: fused
+Richardson sweeps, Anderson residual and Gram reduction, pseudoinverse
+solve, update; plus FP64 refinement in mixed mode) of one seeded synthetic
+system whose right-hand side and solver workspace are already resident in
+HBM.  Default workload: periodic Poisson, 192^3 grid, 12th-order central
+differences (37-point stencil), 64 Gaussian charges minus their mean,
+Jacobi preconditioner, omega = beta = 0.6, m = 7, p = 6, tol 1e-10, FP64.
+The same grid is also solved in mixed precision (FP32 iteration inside FP64
+refinement) and reported beside it with the speedup over FP64.
+
+Prints one JSON line.  `roofline` covers the dominant kernel (the fused
+Richardson sweep): algorithmic bytes per launch (read x and b, write x and
+f: 4 values per grid point) over the mean launch time measured with HIP
+events on the solver's stream.  `cpu_baseline` times the CPU oracle on a
+bounded number of iterations of the same system and scales to solves/s with
+the oracle's own iteration count.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "AAR solves/s and sweep HBM GB/s at 1e-10 rel-residual: mixed/batched vs FP64"
+HBM_PEAK_GBS = 8000.0
+# Oracle (FP64, CPU) iterations to 1e-10 on the default workload, written by
+# tests/golden/make_golden.py (oracle only).
+GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_full_size.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=192)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-iters", type=int, default=24)
+    ap.add_argument("--kernel-timing-solves", type=int, default=1)
+    return ap.parse_args()
+
+
+def timed_solves(solver, bt, steps, warmup):
+    import torch
+    res = None
+    for _ in range(warmup):
+        xt = torch.zeros_like(bt)
+        res = solver.solve(bt, xt)
+    xs = [torch.zeros_like(bt) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        res = solver.solve(bt, xs[i])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, res, xs[-1]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1606_08740_amd import aar, inputs
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    w = inputs.workload(2, n=args.n)
+    prob, b = w.problems[0], w.b[0]
+    N = prob.size
+    bt = torch.as_tensor(b, device="cuda:0")
+
+    # ---- FP64 (headline) ----
+    prm = w.params
+    prm.precision = aar.AAR_FP64
+    s64 = aar.Solver([prob], prm)
+    dt64, r64, x64 = timed_solves(s64, bt, args.steps, args.warmup)
+    # kernel timing pass: HIP events around every sweep launch on the solver's stream
+    s64.set_timing(True)
+    for _ in range(args.kernel_timing_solves):
+        xt = torch.zeros_like(bt)
+        s64.solve(bt, xt)
+    ms_tot, launches = s64.sweep_time()
+    s64.set_timing(False)
+    s64.close()
+    sweep_us = ms_tot / max(launches, 1) * 1e3
+    sweep_bytes = 4 * 8 * N
+    achieved = sweep_bytes / (sweep_us * 1e-6) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": args.steps / dt64,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt64 / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"periodic Poisson {args.n}^3, 12th-order central FD (37-point), "
+                               "64 Gaussian charges minus mean, Jacobi, omega=beta=0.6, m=7, p=6, "
+                               "tol 1e-10, FP64",
+                   "grid": [args.n] * 3, "radius": 6, "m": 7, "p": 6, "tol": 1e-10, "precision": "fp64"},
+        "iterations": r64["iterations"],
+        "rel_residual": r64["rel_residual"],
+        "status": r64["status"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_stencil<double,double,6,false,kSweep> (fused Richardson sweep)",
+                     "bytes_per_launch": sweep_bytes, "mean_launch_us": sweep_us, "launches": launches},
+    }
+
+    # ---- mixed precision on the same system ----
+    if not args.no_mixed:
+        pm = inputs.Params(**{**prm.__dict__})
+        pm.precision = aar.AAR_MIXED_FP32
+        sm = aar.Solver([prob], pm)
+        dtm, rm, xm = timed_solves(sm, bt, args.steps, args.warmup)
+        sm.close()
+        xa = x64.cpu().numpy()
+        xb = xm.cpu().numpy()
+        xa -= xa.mean()
+        xb -= xb.mean()
+        out["mixed_fp32"] = {"value": args.steps / dtm, "unit": "solves/s", "ms_per_step": dtm / args.steps * 1e3,
+                             "iterations": rm["iterations"], "outer_steps": rm["outer_steps"],
+                             "rel_residual": rm["rel_residual"], "status": rm["status"],
+                             "speedup_vs_fp64": dt64 / dtm,
+                             "rel_diff_vs_fp64_gpu": float(np.linalg.norm(xa - xb) / np.linalg.norm(xa))}
+
+    # ---- CPU oracle baseline (bounded sample) ----
+    if not args.no_cpu_baseline:
+        import oracle
+        k = args.cpu_sample_iters
+        t0 = time.perf_counter()
+        oracle.aar_solve(prob, b, m=prm.m, p=prm.p, tol=1e-30, max_iter=k)
+        dtc = time.perf_counter() - t0
+        iters_full = None
+        if os.path.exists(GOLDEN):
+            g = json.load(open(GOLDEN))
+            key = f"periodic_poisson_r6_{args.n}"
+            if key in g:
+                iters_full = g[key]["iterations"]
+        basis = "oracle iterations to 1e-10 (tests/golden)" if iters_full else "GPU iteration count"
+        iters_full = iters_full or r64["iterations"]
+        out["cpu_baseline"] = {"value": 1.0 / (dtc / k * iters_full), "unit": "solves/s",
+                               "cores": oracle.threads(), "kind": "oracle",
+                               "sample": f"{k} AAR iterations of the same {args.n}^3 system ({dtc:.1f} s), "
+                                         f"scaled by {iters_full} iterations per solve ({basis})"}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

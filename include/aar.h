@@ -70,9 +70,20 @@ enum { AAR_FP64 = 0, AAR_MIXED_FP32 = 1, AAR_MIXED_FP32_BF16HIST = 2 };
 
 enum {
     AAR_FLAG_RECORD_RESIDUALS = 1, /* keep r_k of every Anderson step (aar_residual_log)        */
+    AAR_FLAG_DEFLATE_CONSTANT = 2, /* exact FP64 removal of the constant mode, see below        */
     AAR_FLAG_NO_GRAPH = 4,         /* launch kernels one by one instead of replaying HIP graphs */
     AAR_FLAG_NO_AUTOTUNE = 8       /* use the default tile shape instead of timing candidates   */
 };
+/* AAR_FLAG_DEFLATE_CONSTANT: when every axis is periodic and sigma > 0, the
+ * constant vector is an exact eigenvector, A 1 = sigma 1 (upwind convection
+ * included).  With the flag, each FP64 residual r = b - A x is followed by
+ * x += mean(r) / sigma, r -= mean(r) (once before the iteration in FP64
+ * mode, at every refinement step in mixed mode), so the iteration only sees
+ * the mean-free part.  This removes the near-null mode of small shifts,
+ * which FP32 cannot resolve.  It is not part of the paper's method; the
+ * answer is the same solution of A x = b.  aar_create returns
+ * AAR_ERR_UNSUPPORTED for the flag on any system with a Dirichlet axis or
+ * sigma == 0. */
 
 /* One linear system. */
 typedef struct {

@@ -148,7 +148,8 @@ def aar_solve(prob, b, x0=None, omega=0.6, beta=0.6, m=7, p=6, tol=1e-10, max_it
 
     Returns a dict with x, status, iterations, relres (last measured
     ||b - A x_k|| / ||b||) and, when trace_cap > 0, `trace`: one row per
-    Anderson step [k, r_k, ||f_k||, ||f_k - F_k gamma_k||, rank].
+    Anderson step [k, r_k, ||f_k||, ||f_k - F_k gamma_k||, rank,
+    cond(F_k^T F_k) over the kept eigenvalues].
     """
     bd = _Bound(prob)
     b = _f64(b)
@@ -156,7 +157,7 @@ def aar_solve(prob, b, x0=None, omega=0.6, beta=0.6, m=7, p=6, tol=1e-10, max_it
     it = ctypes.c_int64(0)
     rr = ctypes.c_double(0.0)
     tl = ctypes.c_int64(0)
-    tr = np.zeros((max(trace_cap, 1), 5))
+    tr = np.zeros((max(trace_cap, 1), 6))
     st = _load().oracle_aar_solve(bd.ref, _ptr(b), _ptr(x), float(omega), float(beta), int(m), int(p),
                                   float(tol), int(max_iter), ctypes.byref(it), ctypes.byref(rr),
                                   _ptr(tr) if trace_cap > 0 else None, int(trace_cap),

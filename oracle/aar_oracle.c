@@ -266,9 +266,19 @@ void oracle_jacobi_eigen(int l, double *S, double *V)
 }
 
 /* gamma = pinv(G) c for the symmetric positive semidefinite l x l matrix G.
- * Returns the number of eigenvalues kept (the numerical rank). */
+ * Returns the number of eigenvalues kept (the numerical rank); *cond (if not
+ * NULL) receives lambda_max / lambda_min over the kept eigenvalues. */
+static int pinv_solve_cond(int l, const double *G, const double *c, double *gamma, double *cond);
+
 int oracle_pinv_solve(int l, const double *G, const double *c, double *gamma)
 {
+    return pinv_solve_cond(l, G, c, gamma, NULL);
+}
+
+static int pinv_solve_cond(int l, const double *G, const double *c, double *gamma, double *cond)
+{
+    if (cond)
+        *cond = 1.0;
     if (l <= 0)
         return 0;
     double *S = malloc(sizeof(double) * l * l);
@@ -281,6 +291,7 @@ int oracle_pinv_solve(int l, const double *G, const double *c, double *gamma)
             lmax = S[i * l + i];
     double thresh = l * lmax * ldexp(1.0, -52);
     int rank = 0;
+    double lmin_kept = lmax;
     for (int i = 0; i < l; ++i)
         gamma[i] = 0.0;
     for (int e = 0; e < l; ++e) {
@@ -288,12 +299,16 @@ int oracle_pinv_solve(int l, const double *G, const double *c, double *gamma)
         if (!(lam > thresh))
             continue;
         ++rank;
+        if (lam < lmin_kept)
+            lmin_kept = lam;
         double proj = 0.0; /* v_e . c */
         for (int i = 0; i < l; ++i)
             proj += V[i * l + e] * c[i];
         for (int i = 0; i < l; ++i)
             gamma[i] += V[i * l + e] * proj / lam;
     }
+    if (cond && rank > 0)
+        *cond = lmax / lmin_kept;
     free(S);
     free(V);
     return rank;
@@ -340,8 +355,9 @@ static double dot(int64_t N, const double *a, const double *b)
  *   p        extrapolate when (k+1) is a multiple of p
  *   tol      on ||b - A x_k|| / ||b||, tested at Anderson steps only
  *   max_iter cap on the number of iterations (updates)
- *   trace    optional [trace_cap x 5] rows, one per Anderson step:
- *            k, r_k, ||f_k||, ||f_k - F_k gamma_k|| (0 if converged), rank
+ *   trace    optional [trace_cap x 6] rows, one per Anderson step:
+ *            k, r_k, ||f_k||, ||f_k - F_k gamma_k|| (0 if converged), rank,
+ *            condition number of F_k^T F_k over the kept eigenvalues
  * Returns ORACLE_OK, ORACLE_NOT_CONVERGED, ORACLE_BREAKDOWN (NaN/Inf residual)
  * or ORACLE_BAD_ARG.
  */
@@ -418,11 +434,12 @@ int oracle_aar_solve(const oracle_problem *P, const double *b, double *x,
             int64_t row = -1;
             if (trace && trace_len && *trace_len < trace_cap) {
                 row = (*trace_len)++;
-                trace[row * 5 + 0] = (double)k;
-                trace[row * 5 + 1] = r;
-                trace[row * 5 + 2] = sqrt(dot(N, f, f));
-                trace[row * 5 + 3] = 0.0;
-                trace[row * 5 + 4] = 0.0;
+                trace[row * 6 + 0] = (double)k;
+                trace[row * 6 + 1] = r;
+                trace[row * 6 + 2] = sqrt(dot(N, f, f));
+                trace[row * 6 + 3] = 0.0;
+                trace[row * 6 + 4] = 0.0;
+                trace[row * 6 + 5] = 1.0;
             }
             if (!isfinite(r)) {
                 status = ORACLE_BREAKDOWN;
@@ -443,7 +460,8 @@ int oracle_aar_solve(const oracle_problem *P, const double *b, double *x,
                 }
                 c[a] = dot(N, fa, f);
             }
-            int rank = oracle_pinv_solve(cols, G, c, gamma);
+            double cond = 1.0;
+            int rank = pinv_solve_cond(cols, G, c, gamma, &cond);
             /* x_{k+1} = x_k + beta f_k - (X_k + beta F_k) gamma */
 #pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < N; ++i) {
@@ -463,8 +481,9 @@ int oracle_aar_solve(const oracle_problem *P, const double *b, double *x,
                         e -= DF[(int64_t)order[a] * N + i] * gamma[a];
                     res[i] = e;
                 }
-                trace[row * 5 + 3] = sqrt(dot(N, res, res));
-                trace[row * 5 + 4] = rank;
+                trace[row * 6 + 3] = sqrt(dot(N, res, res));
+                trace[row * 6 + 4] = rank;
+                trace[row * 6 + 5] = cond;
             }
         } else {
             /* Richardson step (Eq. 3, first case) */

@@ -205,7 +205,11 @@ hipError_t launch_correct(double *x, const float *d, const double *scale, int64_
 hipError_t launch_copy_f64(const double *in, double *out, int64_t N, hipStream_t s);
 hipError_t launch_cast_f64_f32_plain(const double *in, float *out, int64_t N, hipStream_t s);
 hipError_t launch_zero_f64(double *v, int64_t N, hipStream_t s);
+// constant-mode deflation: mean of r -> scal[2]; x += mean * inv_sigma; r -= mean; partial ||r||^2
+hipError_t launch_deflate(double *x, double *r, int64_t N, double inv_sigma, double *partial, int blocks,
+                          double *scal, hipStream_t s);
 
 int stream_blocks(int64_t N);
+int gram_blocks(int64_t N);
 
 }  // namespace aar

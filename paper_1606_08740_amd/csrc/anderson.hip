@@ -42,6 +42,18 @@ int stream_blocks(int64_t N)
     return (int)b;
 }
 
+// Workgroups of the Gram pass: enough waves to cover HBM latency, few enough
+// that the one-workgroup solve reads its partial table in one pass.
+int gram_blocks(int64_t N)
+{
+    int64_t b = (N + kThreads * 8 - 1) / (kThreads * 8);
+    if (b < 1)
+        b = 1;
+    if (b > 1024)
+        b = 1024;
+    return (int)b;
+}
+
 // ---------------------------------------------------------------------------
 // Gram products
 // ---------------------------------------------------------------------------
@@ -212,7 +224,19 @@ hipError_t launch_gram(Prec prec, const GramArgs &a, int blocks, hipStream_t s)
 // ---------------------------------------------------------------------------
 // Small least-squares solve, convergence test and update plan (one workgroup)
 // ---------------------------------------------------------------------------
-constexpr int kLsqThreads = 64;
+constexpr int kLsqThreads = 256;
+
+// Fixed-order block sum over 256 threads: wave shuffles, then the four wave
+// sums in order.  Every thread receives the result.
+__device__ inline double block_sum256(double v, double *scratch)
+{
+    v = wave_sum_a(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        scratch[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return scratch[0] + scratch[1] + scratch[2] + scratch[3];
+}
 
 __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
 {
@@ -224,8 +248,9 @@ __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
     __shared__ double rot_c[kMaxM / 2], rot_s[kMaxM / 2];
     __shared__ int pair_p[kMaxM / 2], pair_q[kMaxM / 2];
     __shared__ int order[kMaxM];
+    __shared__ double red[kLsqThreads / 64][32];
     __shared__ double sh_rho;
-    __shared__ double sh_off, sh_dg;
+    __shared__ double sh_off;
     __shared__ int sh_stop;
 
     InstState *st = a.state;
@@ -243,34 +268,56 @@ __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
     const int l = (int)(k < a.m ? k : a.m);
     const int np = a.m * (a.m + 1) / 2;
 
-    // residual norm: fixed-order partial sums
+    // residual norm: thread-strided partials, then a fixed-order block sum
     double r = 0.0;
     for (int i = tid; i < a.rho_blocks; i += kLsqThreads)
         r += a.rho_partial[i];
-    r = wave_sum_a(r);
+    r = block_sum256(r, &red[0][0]);
     if (tid == 0)
         sh_rho = r;
-    // G (upper triangle, row-major over the m x m layout) and c
-    for (int e = tid; e < a.ne; e += kLsqThreads) {
-        double v = 0.0;
-        for (int b = 0; b < a.gram_blocks; ++b)
-            v += a.gram_partial[(int64_t)b * a.ne + e];
-        if (e < np) {
-            int row = 0, rem = e;
-            while (rem >= a.m - row) {
-                rem -= a.m - row;
-                ++row;
-            }
-            const int col = row + rem;
-            if (row < l && col < l) {
-                S[row][col] = v;
-                S[col][row] = v;
-            }
-        } else if (e - np < l) {
-            cvec[e - np] = v;
+    // G (upper triangle, row-major over the m x m layout) and c, 32 entries
+    // at a time: each thread sums its rows of the partial table, then the
+    // block sums each entry in a fixed order.
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int e0 = 0; e0 < a.ne; e0 += 32) {
+        double acc[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j)
+            acc[j] = 0.0;
+        for (int b = tid; b < a.gram_blocks; b += kLsqThreads) {
+            const double *row = a.gram_partial + (int64_t)b * a.ne + e0;
+#pragma unroll
+            for (int j = 0; j < 32; ++j)
+                if (e0 + j < a.ne)
+                    acc[j] += row[j];
         }
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            const double v = wave_sum_a(acc[j]);
+            if (lane == 0)
+                red[wave][j] = v;
+        }
+        __syncthreads();
+        if (tid < 32 && e0 + tid < a.ne) {
+            const int e = e0 + tid;
+            const double v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+            if (e < np) {
+                int row = 0, rem = e;
+                while (rem >= a.m - row) {
+                    rem -= a.m - row;
+                    ++row;
+                }
+                const int col = row + rem;
+                if (row < l && col < l) {
+                    S[row][col] = v;
+                    S[col][row] = v;
+                }
+            } else if (e - np < l) {
+                cvec[e - np] = v;
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
     const double rel = sqrt(sh_rho) / st->nb;
     if (tid == 0) {
@@ -704,6 +751,70 @@ __global__ __launch_bounds__(kThreads) void k_cast64_32(const double *in, float 
 hipError_t launch_cast_f64_f32_plain(const double *in, float *out, int64_t N, hipStream_t s)
 {
     hipLaunchKernelGGL(k_cast64_32, dim3(stream_blocks(N)), dim3(kThreads), 0, s, in, out, N);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Constant-mode deflation (periodic systems with A 1 = sigma 1)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_sum_partial(const double *v, int64_t N, double *partial)
+{
+    __shared__ double red[kThreads / 64];
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride)
+        acc += v[i];
+    acc = wave_sum_a(acc);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w)
+            s += red[w];
+        partial[blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_mean_finish(double *out, const double *partial, int blocks, int64_t N)
+{
+    const double s = block_fixed_sum(partial, blocks);
+    if (threadIdx.x == 0)
+        *out = s / (double)N;
+}
+
+__global__ __launch_bounds__(kThreads) void k_deflate_apply(double *x, double *r, int64_t N, double inv_sigma,
+                                                            const double *mean, double *partial)
+{
+    __shared__ double red[kThreads / 64];
+    const double mu = *mean;
+    const double dx = mu * inv_sigma;
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+        x[i] += dx;
+        const double v = r[i] - mu;
+        r[i] = v;
+        acc += v * v;
+    }
+    acc = wave_sum_a(acc);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w)
+            s += red[w];
+        partial[blockIdx.x] = s;
+    }
+}
+
+hipError_t launch_deflate(double *x, double *r, int64_t N, double inv_sigma, double *partial, int blocks,
+                          double *scal, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_partial, dim3(blocks), dim3(kThreads), 0, s, r, N, partial);
+    hipLaunchKernelGGL(k_mean_finish, dim3(1), dim3(64), 0, s, scal + 2, partial, blocks, N);
+    hipLaunchKernelGGL(k_deflate_apply, dim3(blocks), dim3(kThreads), 0, s, x, r, N, inv_sigma, scal + 2, partial);
     return hipGetLastError();
 }
 

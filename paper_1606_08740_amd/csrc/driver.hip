@@ -18,8 +18,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/aar.h"
@@ -70,6 +73,7 @@ struct Operator {
     double diag = 0.0;    // without convection
     double *vel64 = nullptr;
     float *vel32 = nullptr;
+    TileShape ts[2];      // stencil tile for FP64 [0] and FP32 [1] passes
 };
 
 template <typename T> StencilDev<T> make_stencil(const Operator &op, const T *vel)
@@ -256,7 +260,7 @@ aar_status validate_problem(const aar_problem &pr, int idx)
         if (pr.bc[a] == AAR_BC_PERIODIC && pr.n[a] < 2 * pr.radius + 1)
             return fail(AAR_ERR_UNSUPPORTED, "periodic axis shorter than the stencil (n < 2r+1)" + at);
     const int64_t N = (int64_t)pr.n[0] * pr.n[1] * pr.n[2];
-    if (N > ((int64_t)1 << 40))
+    if (N > ((int64_t)1 << 40) || (int64_t)pr.n[0] * pr.n[1] >= ((int64_t)1 << 31))
         return fail(AAR_ERR_UNSUPPORTED, "grid too large" + at);
     return AAR_OK;
 }
@@ -276,6 +280,8 @@ Operator build_operator(const aar_problem &pr)
         }
     }
     op.diag = pr.shift - 2.0 * sum;
+    op.ts[0] = default_tile(pr.radius, true);
+    op.ts[1] = default_tile(pr.radius, false);
     return op;
 }
 
@@ -308,7 +314,7 @@ Sizes compute_sizes(const aar_problem *probs, int count, const aar_params *pa)
         if (pr.velocity)
             vel_total += 3 * N;
     }
-    z.gram_blocks = stream_blocks(z.maxN);
+    z.gram_blocks = std::max(gram_blocks(z.maxN), stream_blocks(z.maxN));
     z.q = pa->m / pa->p;
     z.ne = pa->m * (pa->m + 1) / 2 + pa->m;
     const int64_t N = z.maxN;
@@ -344,11 +350,21 @@ template <> struct Launch<double> {
     {
         return launch_stencil_f64(mode, P.hist, P.radius, P.conv, P.ts, a, nullptr, s);
     }
+    static hipError_t stencil(int mode, const Path<double> &P, StencilArgs<double> a, hipStream_t s,
+                              const TileShape &ts)
+    {
+        return launch_stencil_f64(mode, P.hist, P.radius, P.conv, ts, a, nullptr, s);
+    }
 };
 template <> struct Launch<float> {
     static hipError_t stencil(int mode, const Path<float> &P, StencilArgs<float> a, hipStream_t s)
     {
         return launch_stencil_f32(mode, P.hist, P.radius, P.conv, P.ts, a, nullptr, s);
+    }
+    static hipError_t stencil(int mode, const Path<float> &P, StencilArgs<float> a, hipStream_t s,
+                              const TileShape &ts)
+    {
+        return launch_stencil_f32(mode, P.hist, P.radius, P.conv, ts, a, nullptr, s);
     }
 };
 
@@ -545,17 +561,121 @@ template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool 
     P.N = op.N;
     P.radius = op.prob.radius;
     P.conv = op.prob.velocity != nullptr;
-    P.ts = default_tile(op.prob.radius, f64);
+    P.ts = op.ts[f64 ? 0 : 1];
     int tx, ty, tz, blocks;
     stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], P.ts, &tx, &ty, &tz, &blocks);
     P.rho_blocks = blocks;
-    P.gram_blocks = stream_blocks(op.N);
+    P.gram_blocks = gram_blocks(op.N);
     P.upd_blocks = stream_blocks(op.N);
     P.slot_stride = op.N;
     if constexpr (std::is_same<T, double>::value)
         P.st = make_stencil<double>(op, op.vel64);
     else
         P.st = make_stencil<float>(op, op.vel32);
+}
+
+// Tile autotuner: time the Richardson sweep for each candidate tile height
+// (rows per thread) and z depth on this grid, keep the fastest.  Results are
+// cached per (precision, radius, convection, grid) for the process.
+std::mutex g_tune_mutex;
+std::map<std::tuple<int, int, int, int, int, int>, TileShape> g_tune_cache;
+
+template <typename T> aar_status autotune(aar_solver_t *S, int idx)
+{
+    const bool f64 = std::is_same<T, double>::value;
+    Operator &op = S->ops[idx];
+    const auto key = std::make_tuple(f64 ? 0 : 1, op.prob.radius, op.prob.velocity != nullptr ? 1 : 0,
+                                     op.prob.n[0], op.prob.n[1], op.prob.n[2]);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            op.ts[f64 ? 0 : 1] = it->second;
+            return AAR_OK;
+        }
+    }
+    Path<T> P;
+    if constexpr (std::is_same<T, double>::value)
+        P = S->p64;
+    else
+        P = S->p32;
+    bind_path(S, P, idx, f64);
+    hipStream_t s = S->stream;
+    const int64_t N = op.N;
+    if constexpr (std::is_same<T, double>::value) {
+        AAR_HIP(launch_zero_f64(P.xa, N, s));
+        AAR_HIP(launch_zero_f64(P.b, N, s));
+    } else {
+        AAR_HIP(launch_zero_f32(P.xa, N, s));
+        AAR_HIP(launch_zero_f32(P.b, N, s));
+    }
+    const int nb_blocks = stream_blocks(N);
+    AAR_HIP(launch_norm_partial(f64, P.b, N, S->part_norm, nb_blocks, s));
+    AAR_HIP(launch_init_state(S->state, S->part_norm, nb_blocks, (int64_t)1 << 40, 1.0, s));
+    hipEvent_t e0, e1;
+    AAR_HIP(hipEventCreate(&e0));
+    AAR_HIP(hipEventCreate(&e1));
+    StencilArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.st = P.st;
+    a.b = P.b;
+    a.fring = P.fring;
+    a.state = S->state;
+    a.slot_stride = P.slot_stride;
+    a.p = S->params.p;
+    a.nslots = S->params.m + 1;
+    a.omega = (T)S->params.omega;
+    a.j = 0;
+    a.x = P.xa;
+    a.out = P.xb;
+    float best_ms = 1e30f;
+    TileShape best = P.ts;
+    const int rys[] = {1, 2, 4};
+    const int czs[] = {2, 4, 8, 16, 32, 64};
+    aar_status result = AAR_OK;
+    for (int ry : rys) {
+        int prev_tz = -1;
+        for (int cz : czs) {
+            TileShape ts{ry, cz};
+            int tx, ty, tz, blocks;
+            stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], ts, &tx, &ty, &tz, &blocks);
+            if (tz == prev_tz)
+                continue;      // same grid as a smaller depth
+            prev_tz = tz;
+            hipError_t e = hipSuccess;
+            for (int w = 0; w < 2 && e == hipSuccess; ++w)
+                e = Launch<T>::stencil(kSweep, P, a, s, ts);
+            if (e == hipSuccess)
+                e = hipEventRecord(e0, s);
+            for (int w = 0; w < 5 && e == hipSuccess; ++w)
+                e = Launch<T>::stencil(kSweep, P, a, s, ts);
+            if (e == hipSuccess)
+                e = hipEventRecord(e1, s);
+            if (e == hipSuccess)
+                e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                result = fail(AAR_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+                break;
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = ts;
+            }
+        }
+        if (result != AAR_OK)
+            break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result != AAR_OK)
+        return result;
+    op.ts[f64 ? 0 : 1] = best;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_cache[key] = best;
+    return AAR_OK;
 }
 
 // x (length N, FP64 device) on entry x0, on exit the answer of system idx.
@@ -581,6 +701,19 @@ aar_status solve_one(aar_solver_t *S, int idx, const double *b, double *x, aar_r
         AAR_HIP(hipMemcpyAsync(P.b, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
         AAR_HIP(hipMemcpyAsync(P.xa, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
         const int nb_blocks = stream_blocks(N);
+        if (pa.flags & AAR_FLAG_DEFLATE_CONSTANT) {
+            // x_0 += mean(b - A x_0) / sigma; the first history slot is scratch here
+            double *r = static_cast<double *>(P.fring);
+            StencilArgs<double> ra;
+            std::memset(&ra, 0, sizeof(ra));
+            ra.st = P.st;
+            ra.x = P.xa;
+            ra.b = P.b;
+            ra.out = r;
+            ra.partial = S->part_rho;
+            AAR_HIP(launch_stencil_f64(kResid, Prec::F64, P.radius, P.conv, P.ts, ra, nullptr, s));
+            AAR_HIP(launch_deflate(P.xa, r, N, 1.0 / op.prob.shift, S->part_norm, nb_blocks, S->scal, s));
+        }
         AAR_HIP(launch_norm_partial(true, P.b, N, S->part_norm, nb_blocks, s));
         AAR_HIP(launch_init_state(S->state, S->part_norm, nb_blocks, pa.max_iter, pa.tol, s));
         AAR_HIP(hipMemcpyAsync(&st, S->state, sizeof(InstState), hipMemcpyDeviceToHost, s));
@@ -659,7 +792,12 @@ aar_status solve_one(aar_solver_t *S, int idx, const double *b, double *x, aar_r
         ra.out = S->r64;
         ra.partial = S->part_rho;
         AAR_HIP(launch_stencil_f64(kResid, Prec::F64, R64.radius, R64.conv, R64.ts, ra, nullptr, s));
-        AAR_HIP(launch_finish_norm(S->scal, S->part_rho, R64.rho_blocks, s));
+        if (pa.flags & AAR_FLAG_DEFLATE_CONSTANT) {
+            AAR_HIP(launch_deflate(S->x64, S->r64, N, 1.0 / op.prob.shift, S->part_norm, nb_blocks, S->scal, s));
+            AAR_HIP(launch_finish_norm(S->scal, S->part_norm, nb_blocks, s));
+        } else {
+            AAR_HIP(launch_finish_norm(S->scal, S->part_rho, R64.rho_blocks, s));
+        }
         AAR_HIP(hipMemcpyAsync(host_scal, S->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         AAR_HIP(hipStreamSynchronize(s));
         rel = host_scal[0] / nb;
@@ -757,6 +895,16 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
     for (int i = 0; i < count; ++i)
         if ((st = validate_problem(problems[i], i)) != AAR_OK)
             return st;
+    if (params->flags & AAR_FLAG_DEFLATE_CONSTANT) {
+        for (int i = 0; i < count; ++i) {
+            const aar_problem &pr = problems[i];
+            const bool ok = pr.bc[0] == AAR_BC_PERIODIC && pr.bc[1] == AAR_BC_PERIODIC &&
+                            pr.bc[2] == AAR_BC_PERIODIC && pr.shift > 0.0;
+            if (!ok)
+                return fail(AAR_ERR_UNSUPPORTED, "AAR_FLAG_DEFLATE_CONSTANT needs periodic axes and shift > 0 "
+                                                 "(system " + std::to_string(i) + ")");
+        }
+    }
 
     std::unique_ptr<aar_solver_t> S(new aar_solver_t());
     S->params = *params;
@@ -836,6 +984,12 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
         S->ops.push_back(op);
     }
     AAR_HIP(hipStreamSynchronize(S->stream));
+    if (!(params->flags & AAR_FLAG_NO_AUTOTUNE) && count == 1) {
+        st = S->mixed ? autotune<float>(S.get(), 0) : autotune<double>(S.get(), 0);
+        if (st != AAR_OK)
+            return st;
+        AAR_HIP(hipStreamSynchronize(S->stream));
+    }
     *out = S.release();
     return AAR_OK;
 }

@@ -22,8 +22,11 @@
 // column's 2r+1 z-values in registers (a queue advanced once per plane), and
 // the current plane plus an r-wide halo sits in LDS for the x and y taps.  So
 // every interior value is fetched from global memory once per pass; halos
-// are re-fetched from L2.  Tiles are assigned so that each XCD works on a
-// contiguous block of tiles (shared halos stay in its L2).
+// are re-fetched from L2.  The loads of plane z+1 (queue front, halo, b) are
+// issued before plane z is computed, so memory latency overlaps the taps.
+// Tiles are assigned so that each XCD works on a contiguous block of tiles
+// (shared halos stay in its L2).  FP64 hot passes use the weighted-sum form
+// of the taps (half the flops of the difference form).
 #include "aar_device.h"
 
 namespace aar {
@@ -32,28 +35,6 @@ __device__ inline int wrap_index(int g, int n)
 {
     g %= n;
     return g < 0 ? g + n : g;
-}
-
-// Value at (gx, gy, gz) under the boundary rule of each axis.
-template <typename T>
-__device__ inline T load_bc(const T *__restrict__ x, int gx, int gy, int gz, const StencilDev<T> &st)
-{
-    if (gx < 0 || gx >= st.n0) {
-        if (!st.per0)
-            return T(0);
-        gx = wrap_index(gx, st.n0);
-    }
-    if (gy < 0 || gy >= st.n1) {
-        if (!st.per1)
-            return T(0);
-        gy = wrap_index(gy, st.n1);
-    }
-    if (gz < 0 || gz >= st.n2) {
-        if (!st.per2)
-            return T(0);
-        gz = wrap_index(gz, st.n2);
-    }
-    return x[gx + (int64_t)st.n0 * (gy + (int64_t)st.n1 * gz)];
 }
 
 template <typename T> __device__ inline T wave_sum(T v)
@@ -67,9 +48,15 @@ template <typename T> __device__ inline T wave_sum(T v)
 template <typename T, typename H, int R, bool CONV, int MODE, int RY>
 __global__ __launch_bounds__(kThreads) void k_stencil(const StencilArgs<T> a)
 {
+    // FP64 hot passes use the weighted-sum form (half the flops); FP32 passes
+    // and the FP64 refinement residual keep the difference form.
+    constexpr bool kStd = sizeof(T) == 8 && MODE != kResid;
     constexpr int TY = kWY * RY;
     constexpr int LX = kTX + 2 * R;
     constexpr int LY = TY + 2 * R;
+    constexpr int kHaloRows = 2 * R * LX;
+    constexpr int kHalo = kHaloRows + TY * 2 * R;
+    constexpr int NH = (kHalo + kThreads - 1) / kThreads;
     __shared__ T sh[LY][LX];
     __shared__ double red[kWY];
 
@@ -101,30 +88,36 @@ __global__ __launch_bounds__(kThreads) void k_stencil(const StencilArgs<T> a)
     if constexpr (MODE == kSweep || MODE == kFk)
         fout = reinterpret_cast<H *>(a.fring) + (int64_t)(k % a.nslots) * a.slot_stride;
 
-    // z-queue: q[ry][d] = x at plane z - R + d of this thread's column
-    T q[RY][2 * R + 1];
+    // In-plane offsets (boundary rule applied; -1: outside a Dirichlet
+    // boundary, value 0) of this thread's columns and of its halo cells.
+    int coff[RY];
+    bool own[RY];
 #pragma unroll
     for (int ry = 0; ry < RY; ++ry) {
-        const int gy = y0 + ty + ry * kWY;
-#pragma unroll
-        for (int d = 0; d < 2 * R; ++d)
-            q[ry][d] = load_bc(a.x, gx, gy, z0 - R + d, st);
+        int cx = gx, cy = y0 + ty + ry * kWY;
+        own[ry] = cx < st.n0 && cy < st.n1;
+        bool in = true;
+        if (cx >= st.n0) {
+            if (st.per0)
+                cx = wrap_index(cx, st.n0);
+            else
+                in = false;
+        }
+        if (cy >= st.n1) {
+            if (st.per1)
+                cy = wrap_index(cy, st.n1);
+            else
+                in = false;
+        }
+        coff[ry] = in ? cx + st.n0 * cy : -1;
     }
-
-    double acc = 0.0;
-    constexpr int kHaloRows = 2 * R * LX;
-    constexpr int kHalo = kHaloRows + TY * 2 * R;
-
-    for (int z = z0; z < z1; ++z) {
+    int hoff[NH], hlds[NH];
 #pragma unroll
-        for (int ry = 0; ry < RY; ++ry)
-            q[ry][2 * R] = load_bc(a.x, gx, y0 + ty + ry * kWY, z + R, st);
-
-        __syncthreads();   // previous plane's taps have been read
-#pragma unroll
-        for (int ry = 0; ry < RY; ++ry)
-            sh[R + ty + ry * kWY][R + tx] = q[ry][R];
-        for (int h = tid; h < kHalo; h += kThreads) {
+    for (int j = 0; j < NH; ++j) {
+        const int h = tid + j * kThreads;
+        hoff[j] = -1;
+        hlds[j] = -1;
+        if (h < kHalo) {
             int ly, lx;
             if (h < kHaloRows) {
                 const int r = h / LX;
@@ -136,29 +129,120 @@ __global__ __launch_bounds__(kThreads) void k_stencil(const StencilArgs<T> a)
                 ly = R + t / (2 * R);
                 lx = c < R ? c : c + kTX;
             }
-            sh[ly][lx] = load_bc(a.x, x0 + lx - R, y0 + ly - R, z, st);
+            hlds[j] = ly * LX + lx;
+            int cx = x0 + lx - R, cy = y0 + ly - R;
+            bool in = true;
+            if (cx < 0 || cx >= st.n0) {
+                if (st.per0)
+                    cx = wrap_index(cx, st.n0);
+                else
+                    in = false;
+            }
+            if (cy < 0 || cy >= st.n1) {
+                if (st.per1)
+                    cy = wrap_index(cy, st.n1);
+                else
+                    in = false;
+            }
+            hoff[j] = in ? cx + st.n0 * cy : -1;
         }
+    }
+    // plane index under the z boundary rule (-1: zero plane)
+    auto zplane = [&](int z) -> int {
+        if (z < 0 || z >= st.n2)
+            return st.per2 ? wrap_index(z, st.n2) : -1;
+        return z;
+    };
+    auto ld = [&](int off, int zp) -> T { return (off >= 0 && zp >= 0) ? a.x[off + plane * zp] : T(0); };
+
+    // z-queue: q[ry][d] = x at plane z - R + d of this thread's column
+    T q[RY][2 * R + 1];
+#pragma unroll
+    for (int ry = 0; ry < RY; ++ry)
+#pragma unroll
+        for (int d = 0; d < 2 * R; ++d)
+            q[ry][d] = ld(coff[ry], zplane(z0 - R + d));
+
+    // values of the next plane, fetched one plane ahead
+    T front[RY], hv[NH], bv[RY], vv[CONV ? 3 * RY : 1];
+    auto fetch = [&](int z) {
+        const int zf = zplane(z + R);
+#pragma unroll
+        for (int ry = 0; ry < RY; ++ry)
+            front[ry] = ld(coff[ry], zf);
+#pragma unroll
+        for (int j = 0; j < NH; ++j)
+            hv[j] = ld(hoff[j], z);
+        if constexpr (MODE != kApply) {
+#pragma unroll
+            for (int ry = 0; ry < RY; ++ry)
+                bv[ry] = own[ry] ? a.b[coff[ry] + plane * z] : T(0);
+        }
+        if constexpr (CONV) {
+#pragma unroll
+            for (int ry = 0; ry < RY; ++ry)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    vv[3 * ry + c] = own[ry] ? st.vel[c * st.N + coff[ry] + plane * z] : T(0);
+        }
+    };
+    if (z0 < z1)
+        fetch(z0);
+
+    double acc = 0.0;
+    for (int z = z0; z < z1; ++z) {
+#pragma unroll
+        for (int ry = 0; ry < RY; ++ry)
+            q[ry][2 * R] = front[ry];
+        __syncthreads();   // the previous plane's taps have been read
+#pragma unroll
+        for (int ry = 0; ry < RY; ++ry)
+            sh[R + ty + ry * kWY][R + tx] = q[ry][R];
+#pragma unroll
+        for (int j = 0; j < NH; ++j)
+            if (hlds[j] >= 0)
+                (&sh[0][0])[hlds[j]] = hv[j];
         __syncthreads();
+        T bcur[RY], vcur[CONV ? 3 * RY : 1];
+#pragma unroll
+        for (int ry = 0; ry < RY; ++ry)
+            bcur[ry] = bv[ry];
+        if constexpr (CONV) {
+#pragma unroll
+            for (int c = 0; c < 3 * RY; ++c)
+                vcur[c] = vv[c];
+        }
+        if (z + 1 < z1)
+            fetch(z + 1);
 
 #pragma unroll
         for (int ry = 0; ry < RY; ++ry) {
-            const int gy = y0 + ty + ry * kWY;
             const int lx = R + tx, ly = R + ty + ry * kWY;
             const T c = q[ry][R];
-            T ax = st.sigma * c;
+            T ax;
+            if constexpr (kStd) {
+                ax = st.diag * c;
 #pragma unroll
-            for (int s = 1; s <= R; ++s) {
-                ax += st.c0[s] * ((sh[ly][lx + s] - c) + (sh[ly][lx - s] - c));
-                ax += st.c1[s] * ((sh[ly + s][lx] - c) + (sh[ly - s][lx] - c));
-                ax += st.c2[s] * ((q[ry][R + s] - c) + (q[ry][R - s] - c));
+                for (int s = 1; s <= R; ++s) {
+                    ax += st.c0[s] * (sh[ly][lx + s] + sh[ly][lx - s]);
+                    ax += st.c1[s] * (sh[ly + s][lx] + sh[ly - s][lx]);
+                    ax += st.c2[s] * (q[ry][R + s] + q[ry][R - s]);
+                }
+            } else {
+                ax = st.sigma * c;
+#pragma unroll
+                for (int s = 1; s <= R; ++s) {
+                    ax += st.c0[s] * ((sh[ly][lx + s] - c) + (sh[ly][lx - s] - c));
+                    ax += st.c1[s] * ((sh[ly + s][lx] - c) + (sh[ly - s][lx] - c));
+                    ax += st.c2[s] * ((q[ry][R + s] - c) + (q[ry][R - s] - c));
+                }
             }
-            const bool valid = gx < st.n0 && gy < st.n1;
-            if (!valid)
+            if (!own[ry])
                 continue;
-            const int64_t id = gx + (int64_t)st.n0 * gy + plane * z;
+            const int64_t id = coff[ry] + plane * z;
             T dg = st.diag;
             if constexpr (CONV) {
-                const T v0 = st.vel[id], v1 = st.vel[st.N + id], v2 = st.vel[2 * st.N + id];
+                const T v0 = vcur[3 * ry], v1 = vcur[3 * ry + 1], v2 = vcur[3 * ry + 2];
                 ax += v0 > T(0) ? -v0 * st.ih0 * (sh[ly][lx - 1] - c) : v0 * st.ih0 * (sh[ly][lx + 1] - c);
                 ax += v1 > T(0) ? -v1 * st.ih1 * (sh[ly - 1][lx] - c) : v1 * st.ih1 * (sh[ly + 1][lx] - c);
                 ax += v2 > T(0) ? -v2 * st.ih2 * (q[ry][R - 1] - c) : v2 * st.ih2 * (q[ry][R + 1] - c);
@@ -167,7 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_stencil(const StencilArgs<T> a)
             if constexpr (MODE == kApply) {
                 a.out[id] = ax;
             } else {
-                const T res = a.b[id] - ax;
+                const T res = bcur[ry] - ax;
                 if constexpr (MODE == kResid) {
                     a.out[id] = res;
                     acc += (double)res * (double)res;

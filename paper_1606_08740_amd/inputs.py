@@ -231,13 +231,15 @@ def convection_diffusion_upwind(n: int = 128, seed: int = 4, tol: float = 1e-10,
 
 def batched_helmholtz(count: int = 512, seed: int = 5, nmin: int = 16, nmax: int = 96,
                       radius: int = 4, shift_max: float = 10.0, tol: float = 1e-10,
-                      precision: int = 1) -> Workload:
+                      precision: int = 1, flags: int = 2) -> Workload:
     """`count` periodic shifted Helmholtz systems -Lap u + sigma u = b, order 2r.
 
     Edge n_i ~ U{nmin..nmax}, h_i = 1/n_i, sigma_i ~ U(0, shift_max),
     b_i ~ N(0,1) i.i.d.  A real, positive-shift stand-in for the paper's
     periodic Helmholtz problem (Eq. 7), which is solved many times over in
-    the applications that motivate the method.
+    the applications that motivate the method.  `flags` defaults to the
+    solver's exact constant-mode deflation (value 2): small shifts make the
+    constant vector a near-null mode that FP32 cannot resolve.
     """
     u = uniform(seed, 1, 2 * count).reshape(count, 2)
     probs, bs, xs = [], [], []
@@ -251,7 +253,7 @@ def batched_helmholtz(count: int = 512, seed: int = 5, nmin: int = 16, nmax: int
         bs.append(normal(seed, 100 + i, prob.size))
         xs.append(np.zeros(prob.size))
     return Workload(f"batched_helmholtz_r{radius}_{count}x[{nmin}..{nmax}]^3", probs, bs, xs,
-                    Params(omega=0.6, beta=0.6, m=7, p=6, tol=tol, precision=precision))
+                    Params(omega=0.6, beta=0.6, m=7, p=6, tol=tol, precision=precision, flags=flags))
 
 
 def workload(index: int, **kw) -> Workload:

@@ -19,9 +19,12 @@ MIXED_CASES = [
     ("c1_32_dirichlet", lambda: inputs.workload(1, tol=1e-10), None),
     ("periodic_r6_40", lambda: inputs.workload(3, n=40), "mean_free"),
     ("upwind_24", lambda: inputs.workload(4, n=24), None),
-    ("helmholtz_r4_28_small_shift", lambda: inputs.Workload(
+    ("helmholtz_r4_28_small_shift_deflated", lambda: inputs.Workload(
         "h", [inputs.periodic_problem(28, 4, shift=0.05)], [inputs.normal(9, 0, 28 ** 3)], [None],
-        inputs.Params(tol=1e-10, precision=1)), None),
+        inputs.Params(tol=1e-10, precision=1, flags=aar.AAR_FLAG_DEFLATE_CONSTANT)), None),
+    ("helmholtz_r4_48_shift_0.02_deflated", lambda: inputs.Workload(
+        "h", [inputs.periodic_problem(48, 4, shift=0.02)], [inputs.normal(9, 1, 48 ** 3)], [None],
+        inputs.Params(tol=1e-10, precision=1, flags=aar.AAR_FLAG_DEFLATE_CONSTANT)), None),
 ]
 
 
@@ -39,6 +42,26 @@ def test_mixed_reaches_fp64_tolerance(name, make, cmp):
     ref = oracle.aar_solve(prob, b, m=prm.m, p=prm.p, tol=prm.tol)
     a, r = (mean_free(x), mean_free(ref["x"])) if cmp == "mean_free" else (x, ref["x"])
     assert rel_err(a, r) < 1e-6
+
+
+def test_fp64_deflation_same_answer():
+    """The exact constant-mode step changes the path, not the answer."""
+    prob = inputs.periodic_problem(24, 4, shift=0.3)
+    b = inputs.normal(12, 0, prob.size) + 0.5
+    prm = inputs.Params(tol=1e-10, precision=0, flags=aar.AAR_FLAG_DEFLATE_CONSTANT)
+    say("fp64 deflation")
+    x, res, _ = gpu_solve(prob, prm, b)
+    assert res["status"] == aar.AAR_OK
+    assert oracle.relative_residual(prob, b, x) < prm.tol
+    ref = oracle.aar_solve(prob, b, m=prm.m, p=prm.p, tol=prm.tol)
+    assert rel_err(x, ref["x"]) < 1e-7
+
+
+def test_deflation_rejected_for_dirichlet():
+    prob = inputs.dirichlet_poisson_problem(8)
+    with pytest.raises(aar.AarError) as ei:
+        aar.Solver([prob], inputs.Params(flags=aar.AAR_FLAG_DEFLATE_CONSTANT))
+    assert ei.value.status == aar.AAR_ERR_UNSUPPORTED
 
 
 def test_batched_matches_solo_oracle():
