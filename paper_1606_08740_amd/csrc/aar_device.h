@@ -5,6 +5,8 @@
 //   b        right-hand side
 //   fring    m+1 slots of f_j = D^{-1}(b - A x_j); slot j mod (m+1) holds f_j
 //   dxring   q = floor(m/p) slots of the Anderson increments x_{k+1} - x_k
+//            (ring slots are N rounded up to 8 elements apart, so vector
+//            accesses stay aligned)
 //   fcur     f_k of the Anderson step in the bulk precision (bf16 history only)
 // All vectors are x-fastest, one value per grid point: i + n0*(j + n1*k).
 #pragma once
@@ -128,7 +130,7 @@ template <typename T> struct StencilArgs {
 
 struct GramArgs {
     const void *fring;
-    double *partial;        // [gridDim.x][ne]
+    double *partial;        // [ne][gridDim.x] (entry-major)
     const InstState *state;
     int64_t N;
     int64_t slot_stride;
@@ -140,8 +142,7 @@ struct LsqArgs {
     InstState *state;
     const double *rho_partial;   // from the kFk stencil pass
     int32_t rho_blocks;
-    const double *gram_partial;  // from the Gram pass
-    int32_t gram_blocks;
+    const double *gram_final;    // G (upper triangle) and c, summed by k_gram_finish
     int32_t ne;
     int32_t m, p, nslots, q;     // q: dx ring slots (0: none kept)
     double omega, beta;
@@ -157,10 +158,10 @@ template <typename T> struct UpdateArgs {
     T *xout;
     const void *fring;
     const T *fcur;          // non-null: use instead of the ring slot for f_k
-    T *dxring;
+    T *dxring;              // slots slot_stride elements apart
     const InstState *state;
     int64_t N;
-    int64_t slot_stride;
+    int64_t slot_stride;    // elements between slots, a multiple of 8
 };
 
 // Workgroup index -> logical tile index so that each XCD (and its L2) gets a
@@ -192,6 +193,8 @@ void stencil_grid(int n0, int n1, int n2, const TileShape &ts, int *tx, int *ty,
 
 hipError_t launch_gram(Prec prec, const GramArgs &a, int blocks, hipStream_t s);
 hipError_t launch_lsq(const LsqArgs &a, hipStream_t s);
+hipError_t launch_gram_finish(const double *partial, int blocks, double *out, int ne, const InstState *state,
+                              int p, hipStream_t s);
 hipError_t launch_update(Prec prec, const UpdateArgs<double> *a64, const UpdateArgs<float> *a32, int blocks,
                          hipStream_t s);
 hipError_t launch_norm_partial(bool f64, const void *v, int64_t N, double *partial, int blocks, hipStream_t s);

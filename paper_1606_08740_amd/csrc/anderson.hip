@@ -57,11 +57,33 @@ int gram_blocks(int64_t N)
 // ---------------------------------------------------------------------------
 // Gram products
 // ---------------------------------------------------------------------------
+// V consecutive elements moved by one 16-byte (8-byte for bf16) access.
+template <typename E, int V> struct alignas(sizeof(E) * V) Pack {
+    E v[V];
+};
+
+template <typename H> struct VecWidth {
+    static constexpr int value = 16 / (int)sizeof(H) > 8 ? 8 : 16 / (int)sizeof(H);
+};
+template <> struct VecWidth<bf16_t> {
+    static constexpr int value = 4;
+};
+
+template <typename H, int V>
+__device__ inline void load_vec(const H *p, int64_t i, double *out)
+{
+    const Pack<H, V> pk = *reinterpret_cast<const Pack<H, V> *>(p + i);
+#pragma unroll
+    for (int u = 0; u < V; ++u)
+        out[u] = (double)Hist<H>::load(pk.v, u);
+}
+
 template <typename H, int MC>
 __global__ __launch_bounds__(kThreads) void k_gram(const GramArgs a)
 {
     constexpr int NP = MC * (MC + 1) / 2;
     constexpr int NE = NP + MC;
+    constexpr int V = VecWidth<H>::value;
     __shared__ double red[kThreads / 64][NE];
     const InstState *s = a.state;
     if (s->status != kRunning)
@@ -83,12 +105,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(const GramArgs a)
     for (int e = 0; e < NE; ++e)
         acc[e] = 0.0;
 
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.N; i += stride) {
-        double fv[MC + 1];
-#pragma unroll
-        for (int t = 0; t <= MC; ++t)
-            fv[t] = t <= l ? (double)Hist<H>::load(slot[t], i) : 0.0;
+    auto accumulate = [&](const double *fv) {
         double fk = 0.0;   // f_k sits at position l
 #pragma unroll
         for (int t = 0; t <= MC; ++t)
@@ -107,6 +124,37 @@ __global__ __launch_bounds__(kThreads) void k_gram(const GramArgs a)
 #pragma unroll
         for (int c = 0; c < MC; ++c)
             acc[NP + c] += d[c] * fk;
+    };
+
+    // slot bases are padded to 8 elements, so every V-aligned index is aligned
+    const int64_t nvec = a.N / V;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvec; v += stride) {
+        double fv[MC + 1][V];
+#pragma unroll
+        for (int t = 0; t <= MC; ++t) {
+            if (t <= l)
+                load_vec<H, V>(slot[t], v * V, fv[t]);
+            else
+#pragma unroll
+                for (int u = 0; u < V; ++u)
+                    fv[t][u] = 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            double col[MC + 1];
+#pragma unroll
+            for (int t = 0; t <= MC; ++t)
+                col[t] = fv[t][u];
+            accumulate(col);
+        }
+    }
+    for (int64_t i = nvec * V + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.N; i += stride) {
+        double col[MC + 1];
+#pragma unroll
+        for (int t = 0; t <= MC; ++t)
+            col[t] = t <= l ? (double)Hist<H>::load(slot[t], i) : 0.0;
+        accumulate(col);
     }
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -117,11 +165,12 @@ __global__ __launch_bounds__(kThreads) void k_gram(const GramArgs a)
             red[wave][e] = v;
     }
     __syncthreads();
+    // transposed partial table: entry-major, one column per workgroup
     for (int e = threadIdx.x; e < NE; e += blockDim.x) {
         double v = 0.0;
         for (int w = 0; w < kThreads / 64; ++w)
             v += red[w][e];
-        a.partial[(int64_t)blockIdx.x * a.ne + e] = v;
+        a.partial[(int64_t)e * gridDim.x + blockIdx.x] = v;
     }
 }
 
@@ -177,7 +226,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_entry(const GramArgs a)
         double v = 0.0;
         for (int w = 0; w < kThreads / 64; ++w)
             v += red[w];
-        a.partial[(int64_t)blockIdx.x * a.ne + e] = v;
+        a.partial[(int64_t)e * gridDim.x + blockIdx.x] = v;
     }
 }
 
@@ -224,19 +273,34 @@ hipError_t launch_gram(Prec prec, const GramArgs &a, int blocks, hipStream_t s)
 // ---------------------------------------------------------------------------
 // Small least-squares solve, convergence test and update plan (one workgroup)
 // ---------------------------------------------------------------------------
-constexpr int kLsqThreads = 256;
-
-// Fixed-order block sum over 256 threads: wave shuffles, then the four wave
-// sums in order.  Every thread receives the result.
-__device__ inline double block_sum256(double v, double *scratch)
+// Fixed-order sum of one entry's per-workgroup partials (one workgroup per
+// entry of G and c): thread-strided sums, then the four wave sums in order.
+__global__ __launch_bounds__(kThreads) void k_gram_finish(const double *partial, int blocks, double *out,
+                                                          const InstState *state, int p)
 {
+    __shared__ double red[kThreads / 64];
+    if (state->status != kRunning || state->cycle * p + p - 1 >= state->max_iter)
+        return;
+    const double *col = partial + (int64_t)blockIdx.x * blocks;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < blocks; b += kThreads)
+        v += col[b];
     v = wave_sum_a(v);
-    __syncthreads();
     if ((threadIdx.x & 63) == 0)
-        scratch[threadIdx.x >> 6] = v;
+        red[threadIdx.x >> 6] = v;
     __syncthreads();
-    return scratch[0] + scratch[1] + scratch[2] + scratch[3];
+    if (threadIdx.x == 0)
+        out[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
+
+hipError_t launch_gram_finish(const double *partial, int blocks, double *out, int ne, const InstState *state,
+                              int p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gram_finish, dim3(ne), dim3(kThreads), 0, s, partial, blocks, out, state, p);
+    return hipGetLastError();
+}
+
+constexpr int kLsqThreads = 64;   // one wave: barriers are cheap
 
 __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
 {
@@ -247,9 +311,6 @@ __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
     __shared__ double gam[kMaxM];
     __shared__ double rot_c[kMaxM / 2], rot_s[kMaxM / 2];
     __shared__ int pair_p[kMaxM / 2], pair_q[kMaxM / 2];
-    __shared__ int order[kMaxM];
-    __shared__ double red[kLsqThreads / 64][32];
-    __shared__ double sh_rho;
     __shared__ double sh_off;
     __shared__ int sh_stop;
 
@@ -268,58 +329,33 @@ __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
     const int l = (int)(k < a.m ? k : a.m);
     const int np = a.m * (a.m + 1) / 2;
 
-    // residual norm: thread-strided partials, then a fixed-order block sum
+    // residual norm: thread-strided partials, fixed-order wave sum, broadcast
     double r = 0.0;
     for (int i = tid; i < a.rho_blocks; i += kLsqThreads)
         r += a.rho_partial[i];
-    r = block_sum256(r, &red[0][0]);
-    if (tid == 0)
-        sh_rho = r;
-    // G (upper triangle, row-major over the m x m layout) and c, 32 entries
-    // at a time: each thread sums its rows of the partial table, then the
-    // block sums each entry in a fixed order.
-    const int lane = tid & 63, wave = tid >> 6;
-    for (int e0 = 0; e0 < a.ne; e0 += 32) {
-        double acc[32];
-#pragma unroll
-        for (int j = 0; j < 32; ++j)
-            acc[j] = 0.0;
-        for (int b = tid; b < a.gram_blocks; b += kLsqThreads) {
-            const double *row = a.gram_partial + (int64_t)b * a.ne + e0;
-#pragma unroll
-            for (int j = 0; j < 32; ++j)
-                if (e0 + j < a.ne)
-                    acc[j] += row[j];
-        }
-#pragma unroll
-        for (int j = 0; j < 32; ++j) {
-            const double v = wave_sum_a(acc[j]);
-            if (lane == 0)
-                red[wave][j] = v;
-        }
-        __syncthreads();
-        if (tid < 32 && e0 + tid < a.ne) {
-            const int e = e0 + tid;
-            const double v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-            if (e < np) {
-                int row = 0, rem = e;
-                while (rem >= a.m - row) {
-                    rem -= a.m - row;
-                    ++row;
-                }
-                const int col = row + rem;
-                if (row < l && col < l) {
-                    S[row][col] = v;
-                    S[col][row] = v;
-                }
-            } else if (e - np < l) {
-                cvec[e - np] = v;
+    r = wave_sum_a(r);
+    const double rho2 = __shfl(r, 0, 64);
+    // G (upper triangle, row-major over the m x m layout) and c
+    for (int e = tid; e < a.ne; e += kLsqThreads) {
+        const double v = a.gram_final[e];
+        if (e < np) {
+            int row = 0, rem = e;
+            while (rem >= a.m - row) {
+                rem -= a.m - row;
+                ++row;
             }
+            const int col = row + rem;
+            if (row < l && col < l) {
+                S[row][col] = v;
+                S[col][row] = v;
+            }
+        } else if (e - np < l) {
+            cvec[e - np] = v;
         }
-        __syncthreads();
     }
+    __syncthreads();
 
-    const double rel = sqrt(sh_rho) / st->nb;
+    const double rel = sqrt(rho2) / st->nb;
     if (tid == 0) {
         st->last_r = rel;
         if (a.log && st->log_count < a.log_cap)
@@ -371,28 +407,35 @@ __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
                 S[row][col] = 0.0;
         }
     }
-    for (int i = tid; i < L; i += kLsqThreads)
-        order[i] = i;
     __syncthreads();
     const int half = L / 2;
+    const int M1 = L - 1;
     for (int sweep = 0; sweep < 60 && L >= 2; ++sweep) {
-        if (tid == 0) {
-            double off = 0.0, dg = 0.0;
-            for (int i = 0; i < l; ++i) {
-                dg += S[i][i] * S[i][i];
-                for (int j = 0; j < l; ++j)
-                    if (i != j)
-                        off += S[i][j] * S[i][j];
-            }
-            sh_stop = (off <= 1e-34 * dg) || !(off == off);
+        double off = 0.0, dg = 0.0;
+        for (int i = tid; i < l * l; i += kLsqThreads) {
+            const int row = i / l, col = i % l;
+            const double v = S[row][col];
+            if (row == col)
+                dg += v * v;
+            else
+                off += v * v;
         }
-        __syncthreads();
-        if (sh_stop)
+        off = __shfl(wave_sum_a(off), 0, 64);
+        dg = __shfl(wave_sum_a(dg), 0, 64);
+        if (off <= 1e-34 * dg || !(off == off))
             break;
-        for (int round = 0; round < L - 1; ++round) {
+        for (int round = 0; round < M1; ++round) {
             if (tid < half) {
-                // circle method: order[0] fixed, pairs (order[i], order[L-1-i])
-                int p = order[tid], qq = order[L - 1 - tid];
+                // circle method: index L-1 meets `round`; the others pair
+                // (round + i) mod (L-1) with (round - i) mod (L-1)
+                int p, qq;
+                if (tid == 0) {
+                    p = round;
+                    qq = L - 1;
+                } else {
+                    p = (round + tid) % M1;
+                    qq = (round - tid + M1) % M1;
+                }
                 if (p > qq) {
                     const int t = p;
                     p = qq;
@@ -438,21 +481,13 @@ __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
                 V[row][qq] = sn * vp + c * vq;
             }
             __syncthreads();
-            // zero the annihilated pairs exactly, then rotate the tournament
+            // the annihilated pairs are zero in exact arithmetic
             if (tid < half) {
                 const int p = pair_p[tid], qq = pair_q[tid];
                 if (qq < l && rot_s[tid] != 0.0) {
                     S[p][qq] = 0.0;
                     S[qq][p] = 0.0;
                 }
-            }
-            __syncthreads();
-            if (tid == 0) {
-                // round-robin: keep order[0], rotate the rest by one position
-                const int last = order[L - 1];
-                for (int i = L - 1; i > 1; --i)
-                    order[i] = order[i - 1];
-                order[1] = last;
             }
             __syncthreads();
         }
@@ -530,6 +565,7 @@ hipError_t launch_lsq(const LsqArgs &a, hipStream_t s)
 template <typename T, typename H>
 __global__ __launch_bounds__(kThreads) void k_update(const UpdateArgs<T> a)
 {
+    constexpr int V = 16 / (int)sizeof(T);
     __shared__ const H *fs[kMaxSlots];
     __shared__ T al[kMaxSlots];
     __shared__ const T *ds[kMaxM];
@@ -552,18 +588,64 @@ __global__ __launch_bounds__(kThreads) void k_update(const UpdateArgs<T> a)
         }
     }
     if (threadIdx.x < kMaxM && (int)threadIdx.x < st->nd) {
-        ds[threadIdx.x] = a.dxring + (int64_t)st->dslot[threadIdx.x] * a.N;
+        ds[threadIdx.x] = a.dxring + (int64_t)st->dslot[threadIdx.x] * a.slot_stride;
         de[threadIdx.x] = (T)st->delta[threadIdx.x];
     }
     __syncthreads();
     const int nf = nf_s, nd = nd_s;
-    T *dxw = ws_s >= 0 ? a.dxring + (int64_t)ws_s * a.N : nullptr;
+    T *dxw = ws_s >= 0 ? a.dxring + (int64_t)ws_s * a.slot_stride : nullptr;
+    const T *fk_ptr = a.fcur;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.N; i += stride) {
+    const int64_t nvec = a.N / V;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvec; v += stride) {
+        const int64_t i = v * V;
+        T d[V];
+#pragma unroll
+        for (int u = 0; u < V; ++u)
+            d[u] = T(0);
+        for (int t = 0; t < nf - 1; ++t) {
+            const Pack<H, V> h = *reinterpret_cast<const Pack<H, V> *>(fs[t] + i);
+#pragma unroll
+            for (int u = 0; u < V; ++u)
+                d[u] += al[t] * (T)Hist<H>::load(h.v, u);
+        }
+        T fk[V];
+        if (fk_ptr) {
+            const Pack<T, V> h = *reinterpret_cast<const Pack<T, V> *>(fk_ptr + i);
+#pragma unroll
+            for (int u = 0; u < V; ++u)
+                fk[u] = h.v[u];
+        } else {
+            const Pack<H, V> h = *reinterpret_cast<const Pack<H, V> *>(fs[nf - 1] + i);
+#pragma unroll
+            for (int u = 0; u < V; ++u)
+                fk[u] = (T)Hist<H>::load(h.v, u);
+        }
+#pragma unroll
+        for (int u = 0; u < V; ++u)
+            d[u] += al[nf - 1] * fk[u];
+        for (int t = 0; t < nd; ++t) {
+            const Pack<T, V> h = *reinterpret_cast<const Pack<T, V> *>(ds[t] + i);
+#pragma unroll
+            for (int u = 0; u < V; ++u)
+                d[u] += de[t] * h.v[u];
+        }
+        const Pack<T, V> xk = *reinterpret_cast<const Pack<T, V> *>(a.xin + i);
+        Pack<T, V> xn, dx;
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            xn.v[u] = xk.v[u] + d[u];
+            dx.v[u] = xn.v[u] - xk.v[u];     // the increment actually taken
+        }
+        *reinterpret_cast<Pack<T, V> *>(a.xout + i) = xn;
+        if (dxw)
+            *reinterpret_cast<Pack<T, V> *>(dxw + i) = dx;
+    }
+    for (int64_t i = nvec * V + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.N; i += stride) {
         T d = 0;
         for (int t = 0; t < nf - 1; ++t)
             d += al[t] * (T)Hist<H>::load(fs[t], i);
-        const T fk = a.fcur ? a.fcur[i] : (T)Hist<H>::load(fs[nf - 1], i);
+        const T fk = fk_ptr ? fk_ptr[i] : (T)Hist<H>::load(fs[nf - 1], i);
         d += al[nf - 1] * fk;
         for (int t = 0; t < nd; ++t)
             d += de[t] * ds[t][i];

@@ -154,6 +154,7 @@ struct aar_solver_t {
     // device workspace (sized for the largest system)
     InstState *state = nullptr;
     double *part_rho = nullptr, *part_gram = nullptr, *part_norm = nullptr;
+    double *gram_final = nullptr;
     double *scal = nullptr;       // [0] ||r|| of the refinement, [1] ||b|| (FP64)
     double *log = nullptr;
     int64_t log_cap = 0;
@@ -317,11 +318,11 @@ Sizes compute_sizes(const aar_problem *probs, int count, const aar_params *pa)
     z.gram_blocks = std::max(gram_blocks(z.maxN), stream_blocks(z.maxN));
     z.q = pa->m / pa->p;
     z.ne = pa->m * (pa->m + 1) / 2 + pa->m;
-    const int64_t N = z.maxN;
+    const int64_t N = (z.maxN + 7) / 8 * 8;
     const int slots = pa->m + 1;
     size_t b = 0;
     b += sizeof(InstState) * (size_t)count;
-    b += sizeof(double) * ((size_t)z.max_stencil_blocks + (size_t)z.gram_blocks * z.ne + z.gram_blocks + 8);
+    b += sizeof(double) * ((size_t)z.max_stencil_blocks + (size_t)z.gram_blocks * z.ne + z.gram_blocks + z.ne + 8);
     if (!mixed) {
         b += sizeof(double) * (size_t)N * (3 + slots + z.q);
         b += sizeof(double) * (size_t)vel_total;
@@ -430,13 +431,15 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
     g.ne = S->ne;
     if ((e = launch_gram(P.hist, g, P.gram_blocks, s)) != hipSuccess)
         return e;
+    if ((e = launch_gram_finish(S->part_gram, P.gram_blocks, S->gram_final, S->ne, S->state, pa.p, s)) !=
+        hipSuccess)
+        return e;
 
     LsqArgs l;
     l.state = S->state;
     l.rho_partial = S->part_rho;
     l.rho_blocks = P.rho_blocks;
-    l.gram_partial = S->part_gram;
-    l.gram_blocks = P.gram_blocks;
+    l.gram_final = S->gram_final;
     l.ne = S->ne;
     l.m = pa.m;
     l.p = pa.p;
@@ -567,7 +570,7 @@ template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool 
     P.rho_blocks = blocks;
     P.gram_blocks = gram_blocks(op.N);
     P.upd_blocks = stream_blocks(op.N);
-    P.slot_stride = op.N;
+    P.slot_stride = (op.N + 7) / 8 * 8;
     if constexpr (std::is_same<T, double>::value)
         P.st = make_stencil<double>(op, op.vel64);
     else
@@ -923,7 +926,7 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
     S->q = z.q;
     S->ne = z.ne;
     S->last_log_count.assign(count, 0);
-    const int64_t N = z.maxN;
+    const int64_t N = (z.maxN + 7) / 8 * 8;    // vectors padded: ring slots stay 8-element aligned
     const int slots = params->m + 1;
 
     st = AAR_OK;
@@ -931,6 +934,7 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
     S->part_rho = S->alloc<double>(z.max_stencil_blocks, &st);
     S->part_gram = S->alloc<double>((size_t)z.gram_blocks * z.ne, &st);
     S->part_norm = S->alloc<double>(z.gram_blocks, &st);
+    S->gram_final = S->alloc<double>(z.ne, &st);
     S->scal = S->alloc<double>(8, &st);
     if (st != AAR_OK)
         return st;
