@@ -161,7 +161,8 @@ template <typename T> struct UpdateArgs {
     T *dxring;              // slots slot_stride elements apart
     const InstState *state;
     int64_t N;
-    int64_t slot_stride;    // elements between slots, a multiple of 8
+    int64_t slot_stride;    // elements between f slots, a multiple of 8
+    int64_t dx_stride;      // elements between dx slots, a multiple of 8
 };
 
 // Workgroup index -> logical tile index so that each XCD (and its L2) gets a

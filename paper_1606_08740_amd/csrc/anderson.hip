@@ -8,12 +8,15 @@
 //             deterministic.  Together with the residual norm of the kFk
 //             stencil pass this is the single global reduction per Anderson
 //             step of Secs. 3.2-3.3.
-//   k_lsq     one workgroup: finishes the reductions in a fixed order, tests
-//             convergence on ||b - A x_k|| / ||b|| (Sec. 2), solves
-//             gamma = (F^T F)^+ F^T f_k by a parallel (round-robin ordered)
-//             Jacobi eigendecomposition with small eigenvalues dropped
-//             (Moore-Penrose pseudoinverse, Sec. 3.2), and writes the update
-//             as a linear combination of history slots.
+//   k_gram_finish  sums each entry's per-workgroup partials (fixed order).
+//   k_lsq     one wave: finishes the residual norm, tests convergence on
+//             ||b - A x_k|| / ||b|| (Sec. 2), solves gamma = (F^T F)^+ F^T f_k
+//             (Moore-Penrose pseudoinverse, Sec. 3.2) and writes the update
+//             as a linear combination of history slots.  The pseudoinverse
+//             drops eigenvalues <= rcond * l * lambda_max; when a Cholesky
+//             factor proves all eigenvalues exceed that threshold it is the
+//             inverse and the Cholesky solve is used, otherwise a parallel
+//             (round-robin ordered) Jacobi eigendecomposition.
 //   k_update  x_{k+1} = x_k + beta f_k - (X_k + beta F_k) gamma, streamed.
 //             X_k columns of Richardson steps are omega f_j (their exact
 //             increment); those of Anderson steps come from a small ring of
@@ -311,8 +314,10 @@ __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
     __shared__ double gam[kMaxM];
     __shared__ double rot_c[kMaxM / 2], rot_s[kMaxM / 2];
     __shared__ int pair_p[kMaxM / 2], pair_q[kMaxM / 2];
+    __shared__ double Li[kMaxM][kMaxM + 1];
     __shared__ double sh_off;
     __shared__ int sh_stop;
+    __shared__ int sh_fail;
 
     InstState *st = a.state;
     if (st->status != kRunning)
@@ -397,6 +402,81 @@ __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
         }
     }
 
+    // ---- fast path: Cholesky S = L L^T ----
+    // When every eigenvalue of S provably exceeds the pseudoinverse threshold
+    // rcond * l * lambda_max, the pseudoinverse is the inverse and
+    // gamma = L^-T L^-1 c.  The proof: lambda_min >= 1 / ||L^-1||_F^2 and
+    // lambda_max <= trace(S).  Otherwise the eigendecomposition below runs.
+    int fast = 0;
+    if (l > 0) {
+        for (int i = tid; i < l * l; i += kLsqThreads)
+            V[i / l][i % l] = S[i / l][i % l];
+        if (tid == 0)
+            sh_fail = 0;
+        __syncthreads();
+        for (int j = 0; j < l; ++j) {
+            if (tid == 0) {
+                const double piv = V[j][j];
+                if (!(piv > 0.0))
+                    sh_fail = 1;
+                else
+                    V[j][j] = sqrt(piv);
+            }
+            __syncthreads();
+            if (sh_fail)
+                break;
+            for (int i = j + 1 + tid; i < l; i += kLsqThreads)
+                V[i][j] /= V[j][j];
+            __syncthreads();
+            const int w = l - j - 1;   // trailing block (j+1 .. l-1)^2, lower part
+            for (int idx = tid; idx < w * w; idx += kLsqThreads) {
+                const int i = j + 1 + idx / w, kk = j + 1 + idx % w;
+                if (kk <= i)
+                    V[i][kk] -= V[i][j] * V[kk][j];
+            }
+            __syncthreads();
+        }
+        if (!sh_fail) {
+            // columns of L^-1, one lane per column
+            for (int c = tid; c < l; c += kLsqThreads) {
+                for (int i = 0; i < c; ++i)
+                    Li[i][c] = 0.0;
+                for (int i = c; i < l; ++i) {
+                    double acc = i == c ? 1.0 : 0.0;
+                    for (int kk = c; kk < i; ++kk)
+                        acc -= V[i][kk] * Li[kk][c];
+                    Li[i][c] = acc / V[i][i];
+                }
+            }
+            __syncthreads();
+            double fro = 0.0, tr = 0.0;
+            for (int i = tid; i < l * l; i += kLsqThreads)
+                fro += Li[i / l][i % l] * Li[i / l][i % l];
+            for (int i = tid; i < l; i += kLsqThreads)
+                tr += S[i][i];
+            fro = __shfl(wave_sum_a(fro), 0, 64);
+            tr = __shfl(wave_sum_a(tr), 0, 64);
+            fast = (1.0 / fro > a.rcond * (double)l * tr) && fro == fro;
+            if (fast) {
+                for (int i = tid; i < l; i += kLsqThreads) {   // y = L^-1 c
+                    double y = 0.0;
+                    for (int kk = 0; kk <= i; ++kk)
+                        y += Li[i][kk] * cvec[kk];
+                    wvec[i] = y;
+                }
+                __syncthreads();
+                for (int i = tid; i < l; i += kLsqThreads) {   // gamma = L^-T y
+                    double g = 0.0;
+                    for (int kk = i; kk < l; ++kk)
+                        g += Li[kk][i] * wvec[kk];
+                    gam[i] = g;
+                }
+                __syncthreads();
+            }
+        }
+    }
+
+    if (!fast) {
     // ---- gamma = pinv(S) c by parallel cyclic Jacobi (round-robin pairs) ----
     const int L = l + (l & 1);   // even order; index l is a dummy when l is odd
     for (int i = tid; i < kMaxM * kMaxM; i += kLsqThreads) {
@@ -410,20 +490,12 @@ __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
     __syncthreads();
     const int half = L / 2;
     const int M1 = L - 1;
-    for (int sweep = 0; sweep < 60 && L >= 2; ++sweep) {
-        double off = 0.0, dg = 0.0;
-        for (int i = tid; i < l * l; i += kLsqThreads) {
-            const int row = i / l, col = i % l;
-            const double v = S[row][col];
-            if (row == col)
-                dg += v * v;
-            else
-                off += v * v;
-        }
-        off = __shfl(wave_sum_a(off), 0, 64);
-        dg = __shfl(wave_sum_a(dg), 0, 64);
-        if (off <= 1e-34 * dg || !(off == off))
-            break;
+    // Sweeps stop when one applies no rotation: a pair is rotated only while
+    // |s_pq| > 1e-15 sqrt(|s_pp s_qq|) (negligible against both diagonals).
+    for (int sweep = 0; sweep < 40 && L >= 2; ++sweep) {
+        if (tid == 0)
+            sh_stop = 1;
+        __syncthreads();
         for (int round = 0; round < M1; ++round) {
             if (tid < half) {
                 // circle method: index L-1 meets `round`; the others pair
@@ -445,11 +517,12 @@ __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
                 if (qq < l) {
                     const double apq = S[p][qq];
                     const double app = S[p][p], aqq = S[qq][qq];
-                    if (apq != 0.0 && fabs(apq) > 1e-300) {
+                    if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
                         const double theta = (aqq - app) / (2.0 * apq);
                         const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
                         c = 1.0 / sqrt(t * t + 1.0);
                         sn = t * c;
+                        sh_stop = 0;
                     }
                 }
                 pair_p[tid] = p;
@@ -491,6 +564,8 @@ __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
             }
             __syncthreads();
         }
+        if (sh_stop)
+            break;
     }
     // eigenvalues on the diagonal; drop those <= rcond * l * lambda_max
     if (tid == 0) {
@@ -516,15 +591,19 @@ __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
         gam[i] = g;
     }
     __syncthreads();
+    }   // !fast
 
     // ---- update plan ----
     // x_{k+1} = x_k + beta f_k - sum_i gamma_i (dX_i + beta dF_i), column i
     // covering iteration j_i = k - l + i:  dF_i = f_{j_i+1} - f_{j_i},
     // dX_i = omega f_{j_i} (Richardson j_i) or the stored increment (Anderson j_i).
     if (tid == 0) {
-        int rank = 0;
-        for (int e = 0; e < l; ++e)
-            rank += S[e][e] > thresh;
+        int rank = l;
+        if (!fast) {
+            rank = 0;
+            for (int e = 0; e < l; ++e)
+                rank += S[e][e] > sh_off;
+        }
         st->rank = rank;
         int nd = 0;
         for (int t = 0; t <= l; ++t) {
@@ -588,12 +667,12 @@ __global__ __launch_bounds__(kThreads) void k_update(const UpdateArgs<T> a)
         }
     }
     if (threadIdx.x < kMaxM && (int)threadIdx.x < st->nd) {
-        ds[threadIdx.x] = a.dxring + (int64_t)st->dslot[threadIdx.x] * a.slot_stride;
+        ds[threadIdx.x] = a.dxring + (int64_t)st->dslot[threadIdx.x] * a.dx_stride;
         de[threadIdx.x] = (T)st->delta[threadIdx.x];
     }
     __syncthreads();
     const int nf = nf_s, nd = nd_s;
-    T *dxw = ws_s >= 0 ? a.dxring + (int64_t)ws_s * a.slot_stride : nullptr;
+    T *dxw = ws_s >= 0 ? a.dxring + (int64_t)ws_s * a.dx_stride : nullptr;
     const T *fk_ptr = a.fcur;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t nvec = a.N / V;

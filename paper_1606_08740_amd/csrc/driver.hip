@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -129,11 +130,22 @@ template <typename T> struct Path {
     int radius = 1;
     bool conv = false;
     int rho_blocks = 0, gram_blocks = 0, upd_blocks = 0;
+    int64_t dx_stride = 0;     // elements between dx slots
 };
 
 size_t hist_bytes(Prec p)
 {
     return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2);
+}
+
+// Byte offset added between consecutive bulk vectors (multiple of 64).
+size_t stagger_bytes()
+{
+    const char *env = getenv("AAR_STAGGER_BYTES");
+    long v = env ? atol(env) : 0;
+    if (v < 0)
+        v = 0;
+    return (size_t)((v + 63) / 64 * 64);
 }
 
 }  // namespace
@@ -161,6 +173,9 @@ struct aar_solver_t {
     Path<double> p64;
     Path<float> p32;
     double *x64 = nullptr, *b64 = nullptr, *r64 = nullptr;   // refinement vectors (mixed)
+
+    int64_t slot_stride[2] = {0, 0};   // ring slot spacing (elements) for the FP64 and FP32 paths
+    int64_t dx_stride = 0;              // FP32 path: dx slot spacing (elements)
 
     // graphs (single system)
     hipGraphExec_t graph = nullptr;
@@ -318,20 +333,19 @@ Sizes compute_sizes(const aar_problem *probs, int count, const aar_params *pa)
     z.gram_blocks = std::max(gram_blocks(z.maxN), stream_blocks(z.maxN));
     z.q = pa->m / pa->p;
     z.ne = pa->m * (pa->m + 1) / 2 + pa->m;
-    const int64_t N = (z.maxN + 7) / 8 * 8;
     const int slots = pa->m + 1;
+    const size_t stagger = stagger_bytes();
+    auto vec_span = [&](size_t esize) { return (((size_t)z.maxN * esize + 4095) / 4096) * 4096 + stagger; };
     size_t b = 0;
     b += sizeof(InstState) * (size_t)count;
     b += sizeof(double) * ((size_t)z.max_stencil_blocks + (size_t)z.gram_blocks * z.ne + z.gram_blocks + z.ne + 8);
     if (!mixed) {
-        b += sizeof(double) * (size_t)N * (3 + slots + z.q);
+        b += vec_span(8) * (3 + slots + z.q);
         b += sizeof(double) * (size_t)vel_total;
     } else {
-        b += sizeof(float) * (size_t)N * (3 + z.q);
-        b += hist_bytes(hist) * (size_t)N * slots;
+        b += vec_span(4) * (3 + z.q) + vec_span(hist_bytes(hist)) * slots + vec_span(8) * 3;
         if (hist == Prec::F32_BF16)
-            b += sizeof(float) * (size_t)N;
-        b += sizeof(double) * (size_t)N * 3;
+            b += vec_span(4);
         b += (sizeof(double) + sizeof(float)) * (size_t)vel_total;
     }
     if (pa->flags & AAR_FLAG_RECORD_RESIDUALS) {
@@ -464,6 +478,7 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
     u.state = S->state;
     u.N = P.N;
     u.slot_stride = P.slot_stride;
+    u.dx_stride = P.dx_stride;
     if constexpr (std::is_same<T, double>::value)
         return launch_update(P.hist, &u, nullptr, P.upd_blocks, s);
     else
@@ -570,7 +585,8 @@ template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool 
     P.rho_blocks = blocks;
     P.gram_blocks = gram_blocks(op.N);
     P.upd_blocks = stream_blocks(op.N);
-    P.slot_stride = (op.N + 7) / 8 * 8;
+    P.slot_stride = S->slot_stride[f64 ? 0 : 1];
+    P.dx_stride = f64 ? S->slot_stride[0] : S->dx_stride;
     if constexpr (std::is_same<T, double>::value)
         P.st = make_stencil<double>(op, op.vel64);
     else
@@ -942,30 +958,51 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
         S->log_cap = z.log_cap;
         S->log = S->alloc<double>(z.log_cap, &st);
     }
+    // Bulk vectors and ring slots come from one arena, each starting on a
+    // 4 KiB boundary plus an optional stagger (AAR_STAGGER_BYTES; measured
+    // to make no difference on MI355X, so 0 by default).
+    const size_t stagger = stagger_bytes();
+    auto vec_span = [&](size_t esize) { return (((size_t)N * esize + 4095) / 4096) * 4096 + stagger; };
+    size_t arena = 0;
+    if (!S->mixed) {
+        arena = vec_span(8) * (3 + slots + S->q);
+    } else {
+        arena = vec_span(4) * (3 + S->q) + vec_span(hist_bytes(S->hist)) * slots + vec_span(8) * 3 +
+                (S->hist == Prec::F32_BF16 ? vec_span(4) : 0);
+    }
+    char *base = S->alloc<char>(arena, &st);
+    if (st != AAR_OK)
+        return st;
+    size_t off = 0;
+    auto carve = [&](size_t esize, int count_vec) -> void * {
+        void *p = base + off;
+        off += vec_span(esize) * count_vec;
+        return p;
+    };
     if (!S->mixed) {
         Path<double> &P = S->p64;
         P.hist = Prec::F64;
-        P.xa = S->alloc<double>(N, &st);
-        P.xb = S->alloc<double>(N, &st);
-        P.b = S->alloc<double>(N, &st);
-        P.fring = S->alloc<double>((size_t)N * slots, &st);
-        P.dx = S->q > 0 ? S->alloc<double>((size_t)N * S->q, &st) : nullptr;
+        P.xa = (double *)carve(8, 1);
+        P.xb = (double *)carve(8, 1);
+        P.b = (double *)carve(8, 1);
+        P.fring = carve(8, slots);
+        P.dx = S->q > 0 ? (double *)carve(8, S->q) : nullptr;
+        S->slot_stride[0] = vec_span(8) / 8;
     } else {
         Path<float> &P = S->p32;
         P.hist = S->hist;
-        P.xa = S->alloc<float>(N, &st);
-        P.xb = S->alloc<float>(N, &st);
-        P.b = S->alloc<float>(N, &st);
-        if (S->hist == Prec::F32_BF16) {
-            P.fring = S->alloc<bf16_t>((size_t)N * slots, &st);
-            P.fcur = S->alloc<float>(N, &st);
-        } else {
-            P.fring = S->alloc<float>((size_t)N * slots, &st);
-        }
-        P.dx = S->q > 0 ? S->alloc<float>((size_t)N * S->q, &st) : nullptr;
-        S->x64 = S->alloc<double>(N, &st);
-        S->b64 = S->alloc<double>(N, &st);
-        S->r64 = S->alloc<double>(N, &st);
+        P.xa = (float *)carve(4, 1);
+        P.xb = (float *)carve(4, 1);
+        P.b = (float *)carve(4, 1);
+        P.fring = carve(hist_bytes(S->hist), slots);
+        if (S->hist == Prec::F32_BF16)
+            P.fcur = (float *)carve(4, 1);
+        P.dx = S->q > 0 ? (float *)carve(4, S->q) : nullptr;
+        S->x64 = (double *)carve(8, 1);
+        S->b64 = (double *)carve(8, 1);
+        S->r64 = (double *)carve(8, 1);
+        S->slot_stride[1] = vec_span(hist_bytes(S->hist)) / hist_bytes(S->hist);
+        S->dx_stride = vec_span(4) / 4;
     }
     if (st != AAR_OK)
         return st;
