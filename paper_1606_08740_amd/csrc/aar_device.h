@@ -25,6 +25,8 @@ constexpr int kMaxSlots = kMaxM + 1;
 constexpr int kFastGramM = 12; // per-thread Gram accumulators up to this m
 constexpr int kXcds = 8;       // MI355X: workgroups are dealt round-robin to 8 XCDs
 
+enum class Prec : int { F64 = 0, F32 = 1, F32_BF16 = 2 };
+
 // Per-system run state, written only by single-workgroup kernels.
 enum : int32_t {
     kRunning = 0,
@@ -128,6 +130,161 @@ template <typename T> struct StencilArgs {
     T omega;
 };
 
+// Batched systems: one descriptor per system; packed vectors hold system i
+// at element offset `off` (64-byte aligned) in every array.
+template <typename T> struct BatchDesc {
+    StencilDev<T> st;
+    int64_t off;
+    int32_t tiles_x, tiles_y, tiles_z, cz;
+    int32_t ntiles;          // stencil tiles
+    int32_t nchunks;         // streaming chunks of kChunk points
+};
+
+constexpr int kChunk = 8192;   // points per streaming work item of the batched passes
+
+template <typename T> struct BatchStencilArgs {
+    const BatchDesc<T> *desc;
+    const int2 *items;       // (system, tile)
+    const int *nitems;
+    const T *x;
+    const T *b;
+    T *out;
+    void *fring;             // H-typed, slot stride slot_stride
+    T *fcur;
+    double *partial;         // one per work item (kFk, kResid)
+    const InstState *state;  // per system
+    const int *mask;         // kResid: systems to process (nonzero)
+    int64_t slot_stride;
+    int32_t j, p, nslots;
+    T omega;
+};
+
+// ---- batched driver ----
+enum : int32_t { kPhaseStart = 0, kPhaseInner = 1, kPhaseDone = 2 };
+
+struct BatchCtl {            // per-system control of a batched solve
+    int32_t phase;
+    int32_t status;          // final aar status of the system
+    int32_t outer;           // refinement steps taken
+    int32_t dsel;            // buffer holding the last run's answer (0: xa, 1: xb)
+    int32_t zero;            // b == 0: the answer is x = 0
+    int32_t pad;
+    int64_t used;            // iterations used so far
+    int64_t iters_last;      // iterations of the last run
+    double rnorm;            // ||r|| of the current refinement step
+    double nb64;             // ||b|| (FP64)
+    double rel;              // last FP64 relative residual
+    double mean;             // deflation: mean of r
+};
+
+struct CompactArgs {
+    int32_t mode;            // 0: running inner systems, 1: refine != 0, 2: all systems
+    int32_t count;
+    const BatchCtl *ctl;
+    const InstState *state;
+    const int *refine;
+    const int *ntiles;
+    const int *nchunks;
+    int2 *sitems;
+    int2 *citems;
+    int *nsitems;
+    int *ncitems;
+    int *sbase;
+    int *cbase;
+};
+
+struct BatchGramArgs {
+    const int2 *items;
+    const int *nitems;
+    const InstState *state;
+    const void *fring;
+    const int64_t *offs;
+    const int64_t *sizes;
+    double *partial;         // [item][ne]
+    int64_t slot_stride;
+    int32_t m, p, nslots;
+};
+
+struct BatchLsqArgs {
+    InstState *state;
+    const int *sbase;
+    const int *cbase;
+    const int *ntiles;
+    const int *nchunks;
+    const double *rho_partial;   // per stencil item
+    const double *gram_partial;  // per chunk item, ne entries each
+};
+
+template <typename T> struct BatchUpdateArgs {
+    const int2 *items;
+    const int *nitems;
+    const InstState *state;
+    const int64_t *offs;
+    const int64_t *sizes;
+    const T *xin;
+    T *xout;
+    const void *fring;
+    const T *fcur;
+    T *dxring;
+    int64_t slot_stride;
+    int64_t dx_stride;
+};
+
+enum : int32_t {
+    kOpGather = 0, kOpScatter = 1, kOpNorm = 2, kOpSum = 3, kOpCorrect = 4, kOpDeflate = 5, kOpPrepare = 6,
+    kOpZero64 = 7, kOpScatterSel = 8,
+};
+
+struct BatchStreamArgs {
+    const int2 *items;
+    const int *nitems;
+    int32_t op;
+    int32_t mask_min;        // process systems with mask >= mask_min (mask may be null)
+    const int *mask;
+    const BatchCtl *ctl;
+    const int64_t *offs;
+    const int64_t *sizes;
+    const int64_t *uoffs;    // caller's offsets (gather / scatter)
+    double *user;
+    double *v64;
+    double *x64;
+    float *xa32;             // kOpCorrect reads, kOpPrepare zeroes xa32
+    const float *xb32;
+    float *rhs32;
+    const double *inv_shift;
+    double *partial;         // per item, or null
+};
+
+enum : int32_t { kCtlSelect = 0, kCtlNormB = 1, kCtlMean = 2, kCtlDecide = 3, kCtlStart = 4 };
+
+struct BatchCtlArgs {
+    int32_t step;
+    int32_t p;
+    int32_t mixed;
+    int32_t deflate;
+    int32_t max_outer;
+    int32_t pad;
+    int64_t max_iter;
+    double tol, inner_tol;
+    BatchCtl *ctl;
+    InstState *state;
+    int *refine;
+    int *remaining;
+    const double *partial;
+    const int *sbase;
+    const int *cbase;
+    const int *ntiles;
+    const int *nchunks;
+    const int64_t *sizes;
+};
+
+hipError_t launch_compact(const CompactArgs &a, hipStream_t s);
+hipError_t launch_gram_batched(Prec prec, const BatchGramArgs &a, int grid, hipStream_t s);
+hipError_t launch_update_batched(Prec prec, const BatchUpdateArgs<double> *a64, const BatchUpdateArgs<float> *a32,
+                                 int grid, hipStream_t s);
+hipError_t launch_stream_batched(const BatchStreamArgs &a, int grid, hipStream_t s);
+hipError_t launch_ctl_batched(const BatchCtlArgs &a, int count, hipStream_t s);
+
 struct GramArgs {
     const void *fring;
     double *partial;        // [ne][gridDim.x] (entry-major)
@@ -177,7 +334,6 @@ __device__ inline int xcd_tile(int b, int nb)
 // ---------------------------------------------------------------------------
 // Host-side launch helpers (implemented in the .hip sources)
 // ---------------------------------------------------------------------------
-enum class Prec : int { F64 = 0, F32 = 1, F32_BF16 = 2 };
 
 struct TileShape {
     int ry;      // y rows per thread (tile height = kWY * ry)
@@ -191,9 +347,15 @@ hipError_t launch_stencil_f64(int mode, Prec hist, int radius, bool conv, const 
 hipError_t launch_stencil_f32(int mode, Prec hist, int radius, bool conv, const TileShape &ts,
                               StencilArgs<float> a, int *blocks_out, hipStream_t s);
 void stencil_grid(int n0, int n1, int n2, const TileShape &ts, int *tx, int *ty, int *tz, int *blocks);
+hipError_t launch_stencil_batched_f64(int mode, int radius, bool conv, int ry, const BatchStencilArgs<double> &a,
+                                      int grid, hipStream_t s);
+hipError_t launch_stencil_batched_f32(int mode, Prec hist, int radius, bool conv, int ry,
+                                      const BatchStencilArgs<float> &a, int grid, hipStream_t s);
 
 hipError_t launch_gram(Prec prec, const GramArgs &a, int blocks, hipStream_t s);
 hipError_t launch_lsq(const LsqArgs &a, hipStream_t s);
+hipError_t launch_lsq_batched(const LsqArgs &base, const BatchLsqArgs &b, int count, hipStream_t s);
+
 hipError_t launch_gram_finish(const double *partial, int blocks, double *out, int ne, const InstState *state,
                               int p, hipStream_t s);
 hipError_t launch_update(Prec prec, const UpdateArgs<double> *a64, const UpdateArgs<float> *a32, int blocks,

@@ -24,16 +24,10 @@
 #include <math.h>
 
 #include "aar_device.h"
+#include "anderson_core.h"
 
 namespace aar {
 
-template <typename T> __device__ inline T wave_sum_a(T v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-        v += __shfl_down(v, off, 64);
-    return v;
-}
 
 int stream_blocks(int64_t N)
 {
@@ -60,27 +54,6 @@ int gram_blocks(int64_t N)
 // ---------------------------------------------------------------------------
 // Gram products
 // ---------------------------------------------------------------------------
-// V consecutive elements moved by one 16-byte (8-byte for bf16) access.
-template <typename E, int V> struct alignas(sizeof(E) * V) Pack {
-    E v[V];
-};
-
-template <typename H> struct VecWidth {
-    static constexpr int value = 16 / (int)sizeof(H) > 8 ? 8 : 16 / (int)sizeof(H);
-};
-template <> struct VecWidth<bf16_t> {
-    static constexpr int value = 4;
-};
-
-template <typename H, int V>
-__device__ inline void load_vec(const H *p, int64_t i, double *out)
-{
-    const Pack<H, V> pk = *reinterpret_cast<const Pack<H, V> *>(p + i);
-#pragma unroll
-    for (int u = 0; u < V; ++u)
-        out[u] = (double)Hist<H>::load(pk.v, u);
-}
-
 template <typename H, int MC>
 __global__ __launch_bounds__(kThreads) void k_gram(const GramArgs a)
 {
@@ -303,333 +276,17 @@ hipError_t launch_gram_finish(const double *partial, int blocks, double *out, in
     return hipGetLastError();
 }
 
-constexpr int kLsqThreads = 64;   // one wave: barriers are cheap
-
 __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
 {
-    __shared__ double S[kMaxM][kMaxM + 1];
-    __shared__ double V[kMaxM][kMaxM + 1];
-    __shared__ double cvec[kMaxM];
-    __shared__ double wvec[kMaxM];
-    __shared__ double gam[kMaxM];
-    __shared__ double rot_c[kMaxM / 2], rot_s[kMaxM / 2];
-    __shared__ int pair_p[kMaxM / 2], pair_q[kMaxM / 2];
-    __shared__ double Li[kMaxM][kMaxM + 1];
-    __shared__ double sh_off;
-    __shared__ int sh_stop;
-    __shared__ int sh_fail;
-
     InstState *st = a.state;
     if (st->status != kRunning)
         return;
-    const int tid = threadIdx.x;
-    const int64_t k = st->cycle * a.p + a.p - 1;
-    if (k >= st->max_iter) {
-        if (tid == 0) {
-            st->iters = st->max_iter;
-            st->status = kMaxIter;
-        }
-        return;
-    }
-    const int l = (int)(k < a.m ? k : a.m);
-    const int np = a.m * (a.m + 1) / 2;
-
     // residual norm: thread-strided partials, fixed-order wave sum, broadcast
     double r = 0.0;
-    for (int i = tid; i < a.rho_blocks; i += kLsqThreads)
+    for (int i = threadIdx.x; i < a.rho_blocks; i += kLsqThreads)
         r += a.rho_partial[i];
     r = wave_sum_a(r);
-    const double rho2 = __shfl(r, 0, 64);
-    // G (upper triangle, row-major over the m x m layout) and c
-    for (int e = tid; e < a.ne; e += kLsqThreads) {
-        const double v = a.gram_final[e];
-        if (e < np) {
-            int row = 0, rem = e;
-            while (rem >= a.m - row) {
-                rem -= a.m - row;
-                ++row;
-            }
-            const int col = row + rem;
-            if (row < l && col < l) {
-                S[row][col] = v;
-                S[col][row] = v;
-            }
-        } else if (e - np < l) {
-            cvec[e - np] = v;
-        }
-    }
-    __syncthreads();
-
-    const double rel = sqrt(rho2) / st->nb;
-    if (tid == 0) {
-        st->last_r = rel;
-        if (a.log && st->log_count < a.log_cap)
-            a.log[st->log_count] = rel;
-        st->log_count += 1;
-    }
-    bool bad = !isfinite(rel);
-    for (int i = 0; i < l && !bad; ++i) {
-        bad = !isfinite(cvec[i]);
-        for (int j = 0; j < l && !bad; ++j)
-            bad = !isfinite(S[i][j]);
-    }
-    if (bad || rel < st->tol) {
-        if (tid == 0) {
-            st->iters = k + 1;
-            st->status = bad ? kBreakdown : kConverged;
-        }
-        return;
-    }
-    if (a.stagnation_window > 0) {
-        // inner solves of the refinement stop when the best residual has not
-        // fallen by the given factor over the last `window` Anderson steps
-        if (tid == 0) {
-            if (rel < a.stagnation_factor * st->best_r) {
-                st->best_r = rel;
-                st->since_best = 0;
-            } else {
-                st->since_best += 1;
-            }
-            sh_stop = st->since_best >= a.stagnation_window;
-        }
-        __syncthreads();
-        if (sh_stop) {
-            if (tid == 0) {
-                st->iters = k + 1;
-                st->status = kStagnated;
-            }
-            return;
-        }
-    }
-
-    // ---- fast path: Cholesky S = L L^T ----
-    // When every eigenvalue of S provably exceeds the pseudoinverse threshold
-    // rcond * l * lambda_max, the pseudoinverse is the inverse and
-    // gamma = L^-T L^-1 c.  The proof: lambda_min >= 1 / ||L^-1||_F^2 and
-    // lambda_max <= trace(S).  Otherwise the eigendecomposition below runs.
-    int fast = 0;
-    if (l > 0) {
-        for (int i = tid; i < l * l; i += kLsqThreads)
-            V[i / l][i % l] = S[i / l][i % l];
-        if (tid == 0)
-            sh_fail = 0;
-        __syncthreads();
-        for (int j = 0; j < l; ++j) {
-            if (tid == 0) {
-                const double piv = V[j][j];
-                if (!(piv > 0.0))
-                    sh_fail = 1;
-                else
-                    V[j][j] = sqrt(piv);
-            }
-            __syncthreads();
-            if (sh_fail)
-                break;
-            for (int i = j + 1 + tid; i < l; i += kLsqThreads)
-                V[i][j] /= V[j][j];
-            __syncthreads();
-            const int w = l - j - 1;   // trailing block (j+1 .. l-1)^2, lower part
-            for (int idx = tid; idx < w * w; idx += kLsqThreads) {
-                const int i = j + 1 + idx / w, kk = j + 1 + idx % w;
-                if (kk <= i)
-                    V[i][kk] -= V[i][j] * V[kk][j];
-            }
-            __syncthreads();
-        }
-        if (!sh_fail) {
-            // columns of L^-1, one lane per column
-            for (int c = tid; c < l; c += kLsqThreads) {
-                for (int i = 0; i < c; ++i)
-                    Li[i][c] = 0.0;
-                for (int i = c; i < l; ++i) {
-                    double acc = i == c ? 1.0 : 0.0;
-                    for (int kk = c; kk < i; ++kk)
-                        acc -= V[i][kk] * Li[kk][c];
-                    Li[i][c] = acc / V[i][i];
-                }
-            }
-            __syncthreads();
-            double fro = 0.0, tr = 0.0;
-            for (int i = tid; i < l * l; i += kLsqThreads)
-                fro += Li[i / l][i % l] * Li[i / l][i % l];
-            for (int i = tid; i < l; i += kLsqThreads)
-                tr += S[i][i];
-            fro = __shfl(wave_sum_a(fro), 0, 64);
-            tr = __shfl(wave_sum_a(tr), 0, 64);
-            fast = (1.0 / fro > a.rcond * (double)l * tr) && fro == fro;
-            if (fast) {
-                for (int i = tid; i < l; i += kLsqThreads) {   // y = L^-1 c
-                    double y = 0.0;
-                    for (int kk = 0; kk <= i; ++kk)
-                        y += Li[i][kk] * cvec[kk];
-                    wvec[i] = y;
-                }
-                __syncthreads();
-                for (int i = tid; i < l; i += kLsqThreads) {   // gamma = L^-T y
-                    double g = 0.0;
-                    for (int kk = i; kk < l; ++kk)
-                        g += Li[kk][i] * wvec[kk];
-                    gam[i] = g;
-                }
-                __syncthreads();
-            }
-        }
-    }
-
-    if (!fast) {
-    // ---- gamma = pinv(S) c by parallel cyclic Jacobi (round-robin pairs) ----
-    const int L = l + (l & 1);   // even order; index l is a dummy when l is odd
-    for (int i = tid; i < kMaxM * kMaxM; i += kLsqThreads) {
-        const int row = i / kMaxM, col = i % kMaxM;
-        if (row < L && col < L) {
-            V[row][col] = row == col ? 1.0 : 0.0;
-            if (row >= l || col >= l)
-                S[row][col] = 0.0;
-        }
-    }
-    __syncthreads();
-    const int half = L / 2;
-    const int M1 = L - 1;
-    // Sweeps stop when one applies no rotation: a pair is rotated only while
-    // |s_pq| > 1e-15 sqrt(|s_pp s_qq|) (negligible against both diagonals).
-    for (int sweep = 0; sweep < 40 && L >= 2; ++sweep) {
-        if (tid == 0)
-            sh_stop = 1;
-        __syncthreads();
-        for (int round = 0; round < M1; ++round) {
-            if (tid < half) {
-                // circle method: index L-1 meets `round`; the others pair
-                // (round + i) mod (L-1) with (round - i) mod (L-1)
-                int p, qq;
-                if (tid == 0) {
-                    p = round;
-                    qq = L - 1;
-                } else {
-                    p = (round + tid) % M1;
-                    qq = (round - tid + M1) % M1;
-                }
-                if (p > qq) {
-                    const int t = p;
-                    p = qq;
-                    qq = t;
-                }
-                double c = 1.0, sn = 0.0;
-                if (qq < l) {
-                    const double apq = S[p][qq];
-                    const double app = S[p][p], aqq = S[qq][qq];
-                    if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
-                        const double theta = (aqq - app) / (2.0 * apq);
-                        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                        c = 1.0 / sqrt(t * t + 1.0);
-                        sn = t * c;
-                        sh_stop = 0;
-                    }
-                }
-                pair_p[tid] = p;
-                pair_q[tid] = qq;
-                rot_c[tid] = c;
-                rot_s[tid] = sn;
-            }
-            __syncthreads();
-            // rows: S <- J^T S
-            for (int it = tid; it < half * L; it += kLsqThreads) {
-                const int pi = it / L, col = it % L;
-                const int p = pair_p[pi], qq = pair_q[pi];
-                const double c = rot_c[pi], sn = rot_s[pi];
-                const double sp = S[p][col], sq = S[qq][col];
-                S[p][col] = c * sp - sn * sq;
-                S[qq][col] = sn * sp + c * sq;
-            }
-            __syncthreads();
-            // columns: S <- S J, V <- V J
-            for (int it = tid; it < half * L; it += kLsqThreads) {
-                const int pi = it / L, row = it % L;
-                const int p = pair_p[pi], qq = pair_q[pi];
-                const double c = rot_c[pi], sn = rot_s[pi];
-                const double sp = S[row][p], sq = S[row][qq];
-                S[row][p] = c * sp - sn * sq;
-                S[row][qq] = sn * sp + c * sq;
-                const double vp = V[row][p], vq = V[row][qq];
-                V[row][p] = c * vp - sn * vq;
-                V[row][qq] = sn * vp + c * vq;
-            }
-            __syncthreads();
-            // the annihilated pairs are zero in exact arithmetic
-            if (tid < half) {
-                const int p = pair_p[tid], qq = pair_q[tid];
-                if (qq < l && rot_s[tid] != 0.0) {
-                    S[p][qq] = 0.0;
-                    S[qq][p] = 0.0;
-                }
-            }
-            __syncthreads();
-        }
-        if (sh_stop)
-            break;
-    }
-    // eigenvalues on the diagonal; drop those <= rcond * l * lambda_max
-    if (tid == 0) {
-        double lmax = 0.0;
-        for (int i = 0; i < l; ++i)
-            lmax = fmax(lmax, S[i][i]);
-        sh_off = a.rcond * (double)l * lmax;
-    }
-    __syncthreads();
-    const double thresh = sh_off;
-    for (int e = tid; e < l; e += kLsqThreads) {
-        const double lam = S[e][e];
-        double proj = 0.0;
-        for (int i = 0; i < l; ++i)
-            proj += V[i][e] * cvec[i];
-        wvec[e] = lam > thresh ? proj / lam : 0.0;
-    }
-    __syncthreads();
-    for (int i = tid; i < l; i += kLsqThreads) {
-        double g = 0.0;
-        for (int e = 0; e < l; ++e)
-            g += V[i][e] * wvec[e];
-        gam[i] = g;
-    }
-    __syncthreads();
-    }   // !fast
-
-    // ---- update plan ----
-    // x_{k+1} = x_k + beta f_k - sum_i gamma_i (dX_i + beta dF_i), column i
-    // covering iteration j_i = k - l + i:  dF_i = f_{j_i+1} - f_{j_i},
-    // dX_i = omega f_{j_i} (Richardson j_i) or the stored increment (Anderson j_i).
-    if (tid == 0) {
-        int rank = l;
-        if (!fast) {
-            rank = 0;
-            for (int e = 0; e < l; ++e)
-                rank += S[e][e] > sh_off;
-        }
-        st->rank = rank;
-        int nd = 0;
-        for (int t = 0; t <= l; ++t) {
-            const double gprev = t >= 1 ? gam[t - 1] : 0.0;
-            const double gcur = t < l ? gam[t] : 0.0;
-            double al = (t == l ? a.beta : 0.0) - a.beta * (gprev - gcur);
-            if (t < l) {
-                const int64_t j = k - l + t;
-                const bool anderson = ((j + 1) % a.p) == 0;
-                if (anderson && a.q > 0) {
-                    const int64_t cyc = (j + 1) / a.p - 1;
-                    st->dslot[nd] = (int)(cyc % a.q);
-                    st->delta[nd] = -gcur;
-                    ++nd;
-                } else {
-                    al -= a.omega * gcur;
-                }
-            }
-            st->alpha[t] = al;
-            st->fslot[t] = (int)((k - l + t) % a.nslots);
-        }
-        st->nf = l + 1;
-        st->nd = nd;
-        st->wslot = a.q > 0 ? (int)(st->cycle % a.q) : -1;
-        st->cycle = st->cycle + 1;
-    }
+    lsq_core(a, st, __shfl(r, 0, 64), a.gram_final);
 }
 
 hipError_t launch_lsq(const LsqArgs &a, hipStream_t s)

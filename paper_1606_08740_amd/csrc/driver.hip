@@ -197,6 +197,35 @@ struct aar_solver_t {
     std::vector<int64_t> last_log_count;
     int last_instance = 0;
 
+    // batched engine (count > 1 with one stencil radius and convection kind)
+    struct Batch {
+        bool on = false;
+        int count = 0, radius = 1, ry = 2, grid_s = 1, grid_c = 1;
+        bool conv = false;
+        int64_t total = 0, stride = 0;
+        int sum_tiles = 0, sum_chunks = 0;
+        std::vector<int64_t> offs, sizes;
+        std::vector<int> ntiles, nchunks;
+        BatchDesc<double> *desc64 = nullptr;
+        BatchDesc<float> *desc32 = nullptr;
+        int64_t *d_offs = nullptr, *d_sizes = nullptr, *d_uoffs = nullptr;
+        int *d_ntiles = nullptr, *d_nchunks = nullptr;
+        double *d_invshift = nullptr;
+        BatchCtl *ctl = nullptr;
+        InstState *state = nullptr;
+        int *refine = nullptr, *remaining = nullptr;
+        int2 *c_s = nullptr, *c_c = nullptr, *a_s = nullptr, *a_c = nullptr;
+        int *c_n = nullptr, *a_n = nullptr;
+        int *c_sb = nullptr, *c_cb = nullptr, *a_sb = nullptr, *a_cb = nullptr;
+        double *p_rho = nullptr, *p_gram = nullptr, *p_s = nullptr, *p_c = nullptr;
+        double *xa64 = nullptr, *xb64 = nullptr, *b64 = nullptr, *r64 = nullptr, *dx64 = nullptr;
+        float *xa32 = nullptr, *xb32 = nullptr, *rhs32 = nullptr, *fcur32 = nullptr, *dx32 = nullptr;
+        void *fring = nullptr;
+        double *log = nullptr;
+        hipGraphExec_t graph = nullptr;
+        int *h_remaining = nullptr;
+    } B;
+
     template <typename T> T *alloc(size_t count, aar_status *st)
     {
         void *p = nullptr;
@@ -216,6 +245,10 @@ struct aar_solver_t {
     {
         if (graph)
             (void)hipGraphExecDestroy(graph);
+        if (B.graph)
+            (void)hipGraphExecDestroy(B.graph);
+        if (B.h_remaining)
+            (void)hipHostFree(B.h_remaining);
         for (void *p : allocations)
             (void)hipFree(p);
         if (host_status)
@@ -872,6 +905,548 @@ aar_status solve_one(aar_solver_t *S, int idx, const double *b, double *x, aar_r
     return final;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched engine
+// ---------------------------------------------------------------------------
+constexpr int kBatchGraphCycles = 8;
+constexpr int kBatchGrid = 8192;
+
+// The batched engine needs one stencil radius and convection kind for all
+// systems and a history the register Gram kernels hold (m <= 12); other
+// batches are solved one system after another.
+bool batch_eligible(const aar_problem *probs, int count, const aar_params *pa)
+{
+    if (count < 2 || pa->m > kFastGramM)
+        return false;
+    for (int i = 1; i < count; ++i) {
+        if (probs[i].radius != probs[0].radius || (probs[i].velocity != nullptr) != (probs[0].velocity != nullptr))
+            return false;
+    }
+    return true;
+}
+
+template <typename T> BatchDesc<T> batch_desc(const Operator &op, int64_t off, int ry, const T *vel)
+{
+    BatchDesc<T> d;
+    std::memset(&d, 0, sizeof(d));
+    d.st = make_stencil<T>(op, vel);
+    d.off = off;
+    TileShape ts{ry, std::min(8, op.prob.n[2])};
+    int tx, ty, tz, blocks;
+    stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], ts, &tx, &ty, &tz, &blocks);
+    d.tiles_x = tx;
+    d.tiles_y = ty;
+    d.tiles_z = tz;
+    d.cz = ts.cz;
+    d.ntiles = blocks;
+    d.nchunks = (int)((op.N + kChunk - 1) / kChunk);
+    return d;
+}
+
+size_t batch_bytes(const aar_problem *probs, int count, const aar_params *pa)
+{
+    int64_t total = 0;
+    int64_t tiles = 0, chunks = 0;
+    for (int i = 0; i < count; ++i) {
+        const int64_t N = (int64_t)probs[i].n[0] * probs[i].n[1] * probs[i].n[2];
+        total += (N + 15) / 16 * 16;
+        tiles += (int64_t)((probs[i].n[0] + kTX - 1) / kTX) * ((probs[i].n[1] + 7) / 8) * ((probs[i].n[2] + 7) / 8);
+        chunks += (N + kChunk - 1) / kChunk;
+    }
+    const int slots = pa->m + 1, q = pa->m / pa->p, ne = pa->m * (pa->m + 1) / 2 + pa->m;
+    size_t b = 0;
+    if (pa->precision == AAR_FP64)
+        b += 8 * (size_t)total * (3 + slots + q);
+    else
+        b += (size_t)total * (4 * (3 + q) + hist_bytes(pa->precision == AAR_MIXED_FP32 ? Prec::F32 : Prec::F32_BF16) * slots +
+                              8 * 3 + (pa->precision == AAR_MIXED_FP32_BF16HIST ? 4 : 0));
+    b += sizeof(double) * (size_t)(2 * tiles + chunks * (ne + 1));
+    b += (sizeof(int2) * 2 + sizeof(int) * 4) * (size_t)(tiles + chunks + count);
+    b += (sizeof(InstState) + sizeof(BatchCtl) + sizeof(BatchDesc<double>) + sizeof(BatchDesc<float>) + 64) * count;
+    return b;
+}
+
+aar_status batch_setup(aar_solver_t *S)
+{
+    auto &B = S->B;
+    const aar_params &pa = S->params;
+    const int count = (int)S->ops.size();
+    aar_status st = AAR_OK;
+    B.on = true;
+    B.count = count;
+    B.radius = S->ops[0].prob.radius;
+    B.conv = S->ops[0].prob.velocity != nullptr;
+    B.ry = B.radius <= 2 ? 4 : 2;
+    B.offs.resize(count);
+    B.sizes.resize(count);
+    B.ntiles.resize(count);
+    B.nchunks.resize(count);
+    std::vector<BatchDesc<double>> d64(count);
+    std::vector<BatchDesc<float>> d32(count);
+    std::vector<double> invshift(count);
+    int64_t total = 0;
+    for (int i = 0; i < count; ++i) {
+        const Operator &op = S->ops[i];
+        B.offs[i] = total;
+        B.sizes[i] = op.N;
+        total += (op.N + 15) / 16 * 16;
+        d64[i] = batch_desc<double>(op, B.offs[i], B.ry, op.vel64);
+        d32[i] = batch_desc<float>(op, B.offs[i], B.ry, op.vel32);
+        B.ntiles[i] = d64[i].ntiles;
+        B.nchunks[i] = d64[i].nchunks;
+        B.sum_tiles += B.ntiles[i];
+        B.sum_chunks += B.nchunks[i];
+        invshift[i] = op.prob.shift > 0.0 ? 1.0 / op.prob.shift : 0.0;
+    }
+    B.total = total;
+    B.stride = total;
+    B.grid_s = std::min(B.sum_tiles, kBatchGrid);
+    B.grid_c = std::min(B.sum_chunks, kBatchGrid);
+    const int slots = pa.m + 1;
+    const int ne = S->ne;
+    B.desc64 = S->alloc<BatchDesc<double>>(count, &st);
+    B.desc32 = S->alloc<BatchDesc<float>>(count, &st);
+    B.d_offs = S->alloc<int64_t>(count, &st);
+    B.d_sizes = S->alloc<int64_t>(count, &st);
+    B.d_uoffs = S->alloc<int64_t>(count, &st);
+    B.d_ntiles = S->alloc<int>(count, &st);
+    B.d_nchunks = S->alloc<int>(count, &st);
+    B.d_invshift = S->alloc<double>(count, &st);
+    B.ctl = S->alloc<BatchCtl>(count, &st);
+    B.state = S->alloc<InstState>(count, &st);
+    B.refine = S->alloc<int>(count, &st);
+    B.remaining = S->alloc<int>(1, &st);
+    B.c_s = S->alloc<int2>(B.sum_tiles, &st);
+    B.a_s = S->alloc<int2>(B.sum_tiles, &st);
+    B.c_c = S->alloc<int2>(B.sum_chunks, &st);
+    B.a_c = S->alloc<int2>(B.sum_chunks, &st);
+    B.c_n = S->alloc<int>(2, &st);
+    B.a_n = S->alloc<int>(2, &st);
+    B.c_sb = S->alloc<int>(count, &st);
+    B.c_cb = S->alloc<int>(count, &st);
+    B.a_sb = S->alloc<int>(count, &st);
+    B.a_cb = S->alloc<int>(count, &st);
+    B.p_rho = S->alloc<double>(B.sum_tiles, &st);
+    B.p_s = S->alloc<double>(B.sum_tiles, &st);
+    B.p_gram = S->alloc<double>((size_t)B.sum_chunks * ne, &st);
+    B.p_c = S->alloc<double>(B.sum_chunks, &st);
+    if (st != AAR_OK)
+        return st;
+    if (!S->mixed) {
+        B.xa64 = S->alloc<double>(total, &st);
+        B.xb64 = S->alloc<double>(total, &st);
+        B.b64 = S->alloc<double>(total, &st);
+        B.fring = S->alloc<double>((size_t)total * slots, &st);
+        B.dx64 = S->q > 0 ? S->alloc<double>((size_t)total * S->q, &st) : nullptr;
+    } else {
+        B.xa64 = S->alloc<double>(total, &st);      // x in FP64 (refinement)
+        B.b64 = S->alloc<double>(total, &st);
+        B.r64 = S->alloc<double>(total, &st);
+        B.xa32 = S->alloc<float>(total, &st);
+        B.xb32 = S->alloc<float>(total, &st);
+        B.rhs32 = S->alloc<float>(total, &st);
+        if (S->hist == Prec::F32_BF16) {
+            B.fring = S->alloc<bf16_t>((size_t)total * slots, &st);
+            B.fcur32 = S->alloc<float>(total, &st);
+        } else {
+            B.fring = S->alloc<float>((size_t)total * slots, &st);
+        }
+        B.dx32 = S->q > 0 ? S->alloc<float>((size_t)total * S->q, &st) : nullptr;
+    }
+    if (pa.flags & AAR_FLAG_RECORD_RESIDUALS) {
+        S->log_cap = std::min<int64_t>(pa.max_iter / pa.p + 2, (int64_t)1 << 16);
+        B.log = S->alloc<double>((size_t)S->log_cap * count, &st);
+    }
+    if (st != AAR_OK)
+        return st;
+    hipStream_t s = S->stream;
+    AAR_HIP(hipMemcpyAsync(B.desc64, d64.data(), sizeof(BatchDesc<double>) * count, hipMemcpyHostToDevice, s));
+    AAR_HIP(hipMemcpyAsync(B.desc32, d32.data(), sizeof(BatchDesc<float>) * count, hipMemcpyHostToDevice, s));
+    AAR_HIP(hipMemcpyAsync(B.d_offs, B.offs.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice, s));
+    AAR_HIP(hipMemcpyAsync(B.d_sizes, B.sizes.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice, s));
+    AAR_HIP(hipMemcpyAsync(B.d_ntiles, B.ntiles.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
+    AAR_HIP(hipMemcpyAsync(B.d_nchunks, B.nchunks.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
+    AAR_HIP(hipMemcpyAsync(B.d_invshift, invshift.data(), sizeof(double) * count, hipMemcpyHostToDevice, s));
+    AAR_HIP(hipHostMalloc((void **)&B.h_remaining, sizeof(int), hipHostMallocDefault));
+    AAR_HIP(hipStreamSynchronize(s));
+    return AAR_OK;
+}
+
+CompactArgs batch_compact_args(aar_solver_t *S, int mode, bool cycle_lists)
+{
+    auto &B = S->B;
+    CompactArgs c;
+    c.mode = mode;
+    c.count = B.count;
+    c.ctl = B.ctl;
+    c.state = B.state;
+    c.refine = B.refine;
+    c.ntiles = B.d_ntiles;
+    c.nchunks = B.d_nchunks;
+    c.sitems = cycle_lists ? B.c_s : B.a_s;
+    c.citems = cycle_lists ? B.c_c : B.a_c;
+    c.nsitems = cycle_lists ? B.c_n : B.a_n;
+    c.ncitems = cycle_lists ? B.c_n + 1 : B.a_n + 1;
+    c.sbase = cycle_lists ? B.c_sb : B.a_sb;
+    c.cbase = cycle_lists ? B.c_cb : B.a_cb;
+    return c;
+}
+
+BatchStreamArgs batch_stream(aar_solver_t *S, int op, const int *mask, int mask_min)
+{
+    auto &B = S->B;
+    BatchStreamArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.items = B.a_c;
+    a.nitems = B.a_n + 1;
+    a.op = op;
+    a.mask = mask;
+    a.mask_min = mask_min;
+    a.ctl = B.ctl;
+    a.offs = B.d_offs;
+    a.sizes = B.d_sizes;
+    a.uoffs = B.d_uoffs;
+    a.inv_shift = B.d_invshift;
+    return a;
+}
+
+BatchCtlArgs batch_ctl(aar_solver_t *S, int step, const double *partial, bool deflate)
+{
+    auto &B = S->B;
+    const aar_params &pa = S->params;
+    BatchCtlArgs c;
+    std::memset(&c, 0, sizeof(c));
+    c.step = step;
+    c.p = pa.p;
+    c.mixed = S->mixed ? 1 : 0;
+    c.deflate = deflate ? 1 : 0;
+    c.max_outer = pa.max_outer > 0 ? pa.max_outer : 30;
+    c.max_iter = pa.max_iter;
+    c.tol = pa.tol;
+    c.inner_tol = pa.inner_tol > 0.0 ? pa.inner_tol : 1e-5;
+    c.ctl = B.ctl;
+    c.state = B.state;
+    c.refine = B.refine;
+    c.remaining = B.remaining;
+    c.partial = partial;
+    c.sbase = B.a_sb;
+    c.cbase = B.a_cb;
+    c.ntiles = B.d_ntiles;
+    c.nchunks = B.d_nchunks;
+    c.sizes = B.d_sizes;
+    return c;
+}
+
+// One batched AAR cycle over the running systems' work lists.
+template <typename T> hipError_t batch_enqueue_cycle(aar_solver_t *S, hipStream_t s)
+{
+    auto &B = S->B;
+    const aar_params &pa = S->params;
+    const bool f64 = std::is_same<T, double>::value;
+    T *xa, *xb, *b;
+    T *dx;
+    T *fcur = nullptr;
+    if constexpr (std::is_same<T, double>::value) {
+        xa = B.xa64;
+        xb = B.xb64;
+        b = B.b64;
+        dx = B.dx64;
+    } else {
+        xa = B.xa32;
+        xb = B.xb32;
+        b = B.rhs32;
+        dx = B.dx32;
+        fcur = B.fcur32;
+    }
+    BatchStencilArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    if constexpr (std::is_same<T, double>::value)
+        a.desc = B.desc64;
+    else
+        a.desc = B.desc32;
+    a.items = B.c_s;
+    a.nitems = B.c_n;
+    a.b = b;
+    a.fring = B.fring;
+    a.state = B.state;
+    a.slot_stride = B.stride;
+    a.p = pa.p;
+    a.nslots = pa.m + 1;
+    a.omega = (T)pa.omega;
+    hipError_t e;
+    const Prec hist = f64 ? Prec::F64 : S->hist;
+    for (int j = 0; j < pa.p - 1; ++j) {
+        a.j = j;
+        a.x = (j & 1) ? xb : xa;
+        a.out = (j & 1) ? xa : xb;
+        if constexpr (std::is_same<T, double>::value)
+            e = launch_stencil_batched_f64(kSweep, B.radius, B.conv, B.ry, a, B.grid_s, s);
+        else
+            e = launch_stencil_batched_f32(kSweep, hist, B.radius, B.conv, B.ry, a, B.grid_s, s);
+        if (e != hipSuccess)
+            return e;
+    }
+    const int jk = pa.p - 1;
+    T *xk = (jk & 1) ? xb : xa;
+    a.j = jk;
+    a.x = xk;
+    a.out = nullptr;
+    a.fcur = fcur;
+    a.partial = B.p_rho;
+    if constexpr (std::is_same<T, double>::value)
+        e = launch_stencil_batched_f64(kFk, B.radius, B.conv, B.ry, a, B.grid_s, s);
+    else
+        e = launch_stencil_batched_f32(kFk, hist, B.radius, B.conv, B.ry, a, B.grid_s, s);
+    if (e != hipSuccess)
+        return e;
+
+    BatchGramArgs g;
+    g.items = B.c_c;
+    g.nitems = B.c_n + 1;
+    g.state = B.state;
+    g.fring = B.fring;
+    g.offs = B.d_offs;
+    g.sizes = B.d_sizes;
+    g.partial = B.p_gram;
+    g.slot_stride = B.stride;
+    g.m = pa.m;
+    g.p = pa.p;
+    g.nslots = pa.m + 1;
+    if ((e = launch_gram_batched(hist, g, B.grid_c, s)) != hipSuccess)
+        return e;
+
+    LsqArgs l;
+    std::memset(&l, 0, sizeof(l));
+    l.ne = S->ne;
+    l.m = pa.m;
+    l.p = pa.p;
+    l.nslots = pa.m + 1;
+    l.q = S->q;
+    l.omega = pa.omega;
+    l.beta = pa.beta;
+    l.rcond = std::ldexp(1.0, -52);
+    l.stagnation_window = S->mixed ? 8 : 0;
+    l.stagnation_factor = 0.9;
+    l.log = B.log;
+    l.log_cap = S->log_cap;
+    BatchLsqArgs bl;
+    bl.state = B.state;
+    bl.sbase = B.c_sb;
+    bl.cbase = B.c_cb;
+    bl.ntiles = B.d_ntiles;
+    bl.nchunks = B.d_nchunks;
+    bl.rho_partial = B.p_rho;
+    bl.gram_partial = B.p_gram;
+    if ((e = launch_lsq_batched(l, bl, B.count, s)) != hipSuccess)
+        return e;
+
+    BatchUpdateArgs<T> u;
+    u.items = B.c_c;
+    u.nitems = B.c_n + 1;
+    u.state = B.state;
+    u.offs = B.d_offs;
+    u.sizes = B.d_sizes;
+    u.xin = xk;
+    u.xout = xa;
+    u.fring = B.fring;
+    u.fcur = fcur;
+    u.dxring = dx;
+    u.slot_stride = B.stride;
+    u.dx_stride = B.stride;
+    if constexpr (std::is_same<T, double>::value)
+        return launch_update_batched(hist, &u, nullptr, B.grid_c, s);
+    else
+        return launch_update_batched(hist, nullptr, &u, B.grid_c, s);
+}
+
+#define AAR_HIPE(expr)                                                                          \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(AAR_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+// FP64 residual r = b - A x of the systems marked for refinement, with
+// per-stencil-item partial norms in p_s.
+aar_status batch_residual(aar_solver_t *S, double *x, const double *b, double *r)
+{
+    auto &B = S->B;
+    BatchStencilArgs<double> a;
+    std::memset(&a, 0, sizeof(a));
+    a.desc = B.desc64;
+    a.items = B.a_s;
+    a.nitems = B.a_n;
+    a.x = x;
+    a.b = b;
+    a.out = r;
+    a.partial = B.p_s;
+    a.mask = B.refine;
+    a.slot_stride = B.stride;
+    AAR_HIPE(launch_stencil_batched_f64(kResid, B.radius, B.conv, B.ry, a, B.grid_s, S->stream));
+    return AAR_OK;
+}
+
+aar_status batch_solve(aar_solver_t *S, const double *b, double *x, const int64_t *offsets, aar_result *results)
+{
+    auto &B = S->B;
+    const aar_params &pa = S->params;
+    hipStream_t s = S->stream;
+    const bool deflate = (pa.flags & AAR_FLAG_DEFLATE_CONSTANT) != 0;
+    const bool use_graph = !(pa.flags & AAR_FLAG_NO_GRAPH);
+    const int count = B.count;
+    AAR_HIP(hipMemcpyAsync(B.d_uoffs, offsets, sizeof(int64_t) * count, hipMemcpyHostToDevice, s));
+    AAR_HIP(hipMemsetAsync(B.ctl, 0, sizeof(BatchCtl) * count, s));
+    AAR_HIP(hipMemsetAsync(B.refine, 0, sizeof(int) * count, s));
+    double *x64 = B.xa64;          // FP64 iterate (FP64 mode: the cycles' xa)
+    // gather b and x0 into the packed layout
+    AAR_HIPE(launch_compact(batch_compact_args(S, 2, false), s));
+    {
+        BatchStreamArgs g = batch_stream(S, kOpGather, nullptr, 0);
+        g.user = const_cast<double *>(b);
+        g.v64 = B.b64;
+        AAR_HIPE(launch_stream_batched(g, B.grid_c, s));
+        g.user = x;
+        g.v64 = x64;
+        AAR_HIPE(launch_stream_batched(g, B.grid_c, s));
+    }
+    auto select = [&]() -> aar_status {
+        AAR_HIP(hipMemsetAsync(B.remaining, 0, sizeof(int), s));
+        AAR_HIPE(launch_ctl_batched(batch_ctl(S, kCtlSelect, nullptr, deflate), count, s));
+        AAR_HIPE(launch_compact(batch_compact_args(S, 1, false), s));
+        return AAR_OK;
+    };
+    // refinement step of the selected systems (mixed), or the start of FP64 runs
+    auto refine_body = [&](bool first) -> aar_status {
+        aar_status e;
+        if (S->mixed) {
+            if (first) {
+                BatchStreamArgs nb = batch_stream(S, kOpNorm, B.refine, 1);
+                nb.v64 = B.b64;
+                nb.partial = B.p_c;
+                AAR_HIPE(launch_stream_batched(nb, B.grid_c, s));
+                AAR_HIPE(launch_ctl_batched(batch_ctl(S, kCtlNormB, B.p_c, deflate), count, s));
+            } else {
+                BatchStreamArgs c = batch_stream(S, kOpCorrect, B.refine, 1);
+                c.v64 = x64;
+                c.xa32 = B.xa32;
+                c.xb32 = B.xb32;
+                AAR_HIPE(launch_stream_batched(c, B.grid_c, s));
+            }
+            if ((e = batch_residual(S, x64, B.b64, B.r64)) != AAR_OK)
+                return e;
+            if (deflate) {
+                BatchStreamArgs sm = batch_stream(S, kOpSum, B.refine, 1);
+                sm.v64 = B.r64;
+                sm.partial = B.p_c;
+                AAR_HIPE(launch_stream_batched(sm, B.grid_c, s));
+                AAR_HIPE(launch_ctl_batched(batch_ctl(S, kCtlMean, B.p_c, deflate), count, s));
+                BatchStreamArgs df = batch_stream(S, kOpDeflate, B.refine, 1);
+                df.v64 = B.r64;
+                df.x64 = x64;
+                df.partial = B.p_c;
+                AAR_HIPE(launch_stream_batched(df, B.grid_c, s));
+                AAR_HIPE(launch_ctl_batched(batch_ctl(S, kCtlDecide, B.p_c, true), count, s));
+            } else {
+                AAR_HIPE(launch_ctl_batched(batch_ctl(S, kCtlDecide, B.p_s, false), count, s));
+            }
+            BatchStreamArgs pr = batch_stream(S, kOpPrepare, B.refine, 2);
+            pr.v64 = B.r64;
+            pr.rhs32 = B.rhs32;
+            pr.xa32 = B.xa32;
+            pr.partial = B.p_c;
+            AAR_HIPE(launch_stream_batched(pr, B.grid_c, s));
+            AAR_HIPE(launch_ctl_batched(batch_ctl(S, kCtlStart, B.p_c, deflate), count, s));
+        } else {
+            if (deflate) {
+                double *r = static_cast<double *>(B.fring);   // slot 0 is scratch before the run
+                if ((e = batch_residual(S, x64, B.b64, r)) != AAR_OK)
+                    return e;
+                BatchStreamArgs sm = batch_stream(S, kOpSum, B.refine, 1);
+                sm.v64 = r;
+                sm.partial = B.p_c;
+                AAR_HIPE(launch_stream_batched(sm, B.grid_c, s));
+                AAR_HIPE(launch_ctl_batched(batch_ctl(S, kCtlMean, B.p_c, deflate), count, s));
+                BatchStreamArgs df = batch_stream(S, kOpDeflate, B.refine, 1);
+                df.v64 = r;
+                df.x64 = x64;
+                AAR_HIPE(launch_stream_batched(df, B.grid_c, s));
+            }
+            AAR_HIPE(launch_ctl_batched(batch_ctl(S, kCtlDecide, nullptr, deflate), count, s));
+            BatchStreamArgs nb = batch_stream(S, kOpNorm, B.refine, 2);
+            nb.v64 = B.b64;
+            nb.partial = B.p_c;
+            AAR_HIPE(launch_stream_batched(nb, B.grid_c, s));
+            AAR_HIPE(launch_ctl_batched(batch_ctl(S, kCtlStart, B.p_c, deflate), count, s));
+        }
+        return AAR_OK;
+    };
+    aar_status e;
+    if ((e = select()) != AAR_OK)
+        return e;
+    if ((e = refine_body(true)) != AAR_OK)
+        return e;
+    if (use_graph && B.graph == nullptr) {
+        AAR_HIP(hipStreamBeginCapture(S->capture_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t ce = hipSuccess;
+        for (int c = 0; c < kBatchGraphCycles && ce == hipSuccess; ++c)
+            ce = S->mixed ? batch_enqueue_cycle<float>(S, S->capture_stream)
+                          : batch_enqueue_cycle<double>(S, S->capture_stream);
+        hipGraph_t g = nullptr;
+        hipError_t ce2 = hipStreamEndCapture(S->capture_stream, &g);
+        if (ce != hipSuccess || ce2 != hipSuccess) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return fail(AAR_ERR_DEVICE, std::string("batched graph capture: ") +
+                                            hipGetErrorString(ce != hipSuccess ? ce : ce2));
+        }
+        hipError_t ce3 = hipGraphInstantiate(&B.graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        AAR_HIP(ce3);
+    }
+    for (;;) {
+        AAR_HIPE(launch_compact(batch_compact_args(S, 0, true), s));
+        if (use_graph) {
+            AAR_HIP(hipGraphLaunch(B.graph, s));
+        } else {
+            for (int c = 0; c < kBatchGraphCycles; ++c)
+                AAR_HIPE(S->mixed ? batch_enqueue_cycle<float>(S, s) : batch_enqueue_cycle<double>(S, s));
+        }
+        if ((e = select()) != AAR_OK)
+            return e;
+        AAR_HIP(hipMemcpyAsync(B.h_remaining, B.remaining, sizeof(int), hipMemcpyDeviceToHost, s));
+        AAR_HIP(hipStreamSynchronize(s));
+        if (*B.h_remaining == 0)
+            break;
+        if (S->mixed && (e = refine_body(false)) != AAR_OK)
+            return e;
+    }
+    // write the answers back in the caller's layout
+    AAR_HIPE(launch_compact(batch_compact_args(S, 2, false), s));
+    BatchStreamArgs sc = batch_stream(S, S->mixed ? kOpScatter : kOpScatterSel, nullptr, 0);
+    sc.user = x;
+    sc.v64 = x64;
+    sc.x64 = B.xb64;
+    AAR_HIPE(launch_stream_batched(sc, B.grid_c, s));
+    std::vector<BatchCtl> ctl(count);
+    std::vector<InstState> sts(count);
+    AAR_HIP(hipMemcpyAsync(ctl.data(), B.ctl, sizeof(BatchCtl) * count, hipMemcpyDeviceToHost, s));
+    AAR_HIP(hipMemcpyAsync(sts.data(), B.state, sizeof(InstState) * count, hipMemcpyDeviceToHost, s));
+    AAR_HIP(hipStreamSynchronize(s));
+    aar_status worst = AAR_OK;
+    for (int i = 0; i < count; ++i) {
+        aar_result r{};
+        r.status = ctl[i].status;
+        r.iterations = ctl[i].used;
+        r.outer_steps = S->mixed ? ctl[i].outer : 0;
+        r.rel_residual = ctl[i].rel;
+        results[i] = r;
+        S->last_log_count[i] = sts[i].log_count;
+        if (r.status > worst)
+            worst = (aar_status)r.status;
+    }
+    return worst;
+}
 }  // namespace
 
 // ===========================================================================
@@ -895,7 +1470,8 @@ aar_status aar_workspace_bytes(const aar_problem *problems, int32_t count, const
     for (int i = 0; i < count; ++i)
         if ((st = validate_problem(problems[i], i)) != AAR_OK)
             return st;
-    *bytes = compute_sizes(problems, count, params).bytes;
+    *bytes = batch_eligible(problems, count, params) ? batch_bytes(problems, count, params)
+                                             : compute_sizes(problems, count, params).bytes;
     return AAR_OK;
 }
 
@@ -938,6 +1514,7 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
         AAR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 
     const Sizes z = compute_sizes(problems, count, params);
+    const bool batched = batch_eligible(problems, count, params);
     S->maxN = z.maxN;
     S->q = z.q;
     S->ne = z.ne;
@@ -958,54 +1535,56 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
         S->log_cap = z.log_cap;
         S->log = S->alloc<double>(z.log_cap, &st);
     }
-    // Bulk vectors and ring slots come from one arena, each starting on a
-    // 4 KiB boundary plus an optional stagger (AAR_STAGGER_BYTES; measured
-    // to make no difference on MI355X, so 0 by default).
-    const size_t stagger = stagger_bytes();
-    auto vec_span = [&](size_t esize) { return (((size_t)N * esize + 4095) / 4096) * 4096 + stagger; };
-    size_t arena = 0;
-    if (!S->mixed) {
-        arena = vec_span(8) * (3 + slots + S->q);
-    } else {
-        arena = vec_span(4) * (3 + S->q) + vec_span(hist_bytes(S->hist)) * slots + vec_span(8) * 3 +
-                (S->hist == Prec::F32_BF16 ? vec_span(4) : 0);
+    if (!batched) {
+        // Bulk vectors and ring slots come from one arena, each starting on a
+        // 4 KiB boundary plus an optional stagger (AAR_STAGGER_BYTES; measured
+        // to make no difference on MI355X, so 0 by default).
+        const size_t stagger = stagger_bytes();
+        auto vec_span = [&](size_t esize) { return (((size_t)N * esize + 4095) / 4096) * 4096 + stagger; };
+        size_t arena = 0;
+        if (!S->mixed) {
+            arena = vec_span(8) * (3 + slots + S->q);
+        } else {
+            arena = vec_span(4) * (3 + S->q) + vec_span(hist_bytes(S->hist)) * slots + vec_span(8) * 3 +
+                    (S->hist == Prec::F32_BF16 ? vec_span(4) : 0);
+        }
+        char *base = S->alloc<char>(arena, &st);
+        if (st != AAR_OK)
+            return st;
+        size_t off = 0;
+        auto carve = [&](size_t esize, int count_vec) -> void * {
+            void *p = base + off;
+            off += vec_span(esize) * count_vec;
+            return p;
+        };
+        if (!S->mixed) {
+            Path<double> &P = S->p64;
+            P.hist = Prec::F64;
+            P.xa = (double *)carve(8, 1);
+            P.xb = (double *)carve(8, 1);
+            P.b = (double *)carve(8, 1);
+            P.fring = carve(8, slots);
+            P.dx = S->q > 0 ? (double *)carve(8, S->q) : nullptr;
+            S->slot_stride[0] = vec_span(8) / 8;
+        } else {
+            Path<float> &P = S->p32;
+            P.hist = S->hist;
+            P.xa = (float *)carve(4, 1);
+            P.xb = (float *)carve(4, 1);
+            P.b = (float *)carve(4, 1);
+            P.fring = carve(hist_bytes(S->hist), slots);
+            if (S->hist == Prec::F32_BF16)
+                P.fcur = (float *)carve(4, 1);
+            P.dx = S->q > 0 ? (float *)carve(4, S->q) : nullptr;
+            S->x64 = (double *)carve(8, 1);
+            S->b64 = (double *)carve(8, 1);
+            S->r64 = (double *)carve(8, 1);
+            S->slot_stride[1] = vec_span(hist_bytes(S->hist)) / hist_bytes(S->hist);
+            S->dx_stride = vec_span(4) / 4;
+        }
+        if (st != AAR_OK)
+            return st;
     }
-    char *base = S->alloc<char>(arena, &st);
-    if (st != AAR_OK)
-        return st;
-    size_t off = 0;
-    auto carve = [&](size_t esize, int count_vec) -> void * {
-        void *p = base + off;
-        off += vec_span(esize) * count_vec;
-        return p;
-    };
-    if (!S->mixed) {
-        Path<double> &P = S->p64;
-        P.hist = Prec::F64;
-        P.xa = (double *)carve(8, 1);
-        P.xb = (double *)carve(8, 1);
-        P.b = (double *)carve(8, 1);
-        P.fring = carve(8, slots);
-        P.dx = S->q > 0 ? (double *)carve(8, S->q) : nullptr;
-        S->slot_stride[0] = vec_span(8) / 8;
-    } else {
-        Path<float> &P = S->p32;
-        P.hist = S->hist;
-        P.xa = (float *)carve(4, 1);
-        P.xb = (float *)carve(4, 1);
-        P.b = (float *)carve(4, 1);
-        P.fring = carve(hist_bytes(S->hist), slots);
-        if (S->hist == Prec::F32_BF16)
-            P.fcur = (float *)carve(4, 1);
-        P.dx = S->q > 0 ? (float *)carve(4, S->q) : nullptr;
-        S->x64 = (double *)carve(8, 1);
-        S->b64 = (double *)carve(8, 1);
-        S->r64 = (double *)carve(8, 1);
-        S->slot_stride[1] = vec_span(hist_bytes(S->hist)) / hist_bytes(S->hist);
-        S->dx_stride = vec_span(4) / 4;
-    }
-    if (st != AAR_OK)
-        return st;
 
     for (int i = 0; i < count; ++i) {
         Operator op = build_operator(problems[i]);
@@ -1025,6 +1604,8 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
         S->ops.push_back(op);
     }
     AAR_HIP(hipStreamSynchronize(S->stream));
+    if (batched && (st = batch_setup(S.get())) != AAR_OK)
+        return st;
     if (!(params->flags & AAR_FLAG_NO_AUTOTUNE) && count == 1) {
         st = S->mixed ? autotune<float>(S.get(), 0) : autotune<double>(S.get(), 0);
         if (st != AAR_OK)
@@ -1066,6 +1647,8 @@ aar_status aar_solve_batched(aar_solver s, const double *b, double *x, const int
             return fail(AAR_ERR_INVALID_ARG, "offsets do not match the system sizes (system " +
                                                  std::to_string(i) + ")");
     }
+    if (s->B.on)
+        return batch_solve(s, b, x, offsets, results);
     aar_status worst = AAR_OK;
     for (int i = 0; i < count; ++i) {
         aar_status st = solve_one(s, i, b + offsets[i], x + offsets[i], &results[i]);
@@ -1103,15 +1686,17 @@ aar_status aar_residual_log(aar_solver s, int32_t instance, double *out, int64_t
         return fail(AAR_ERR_INVALID_ARG, "solver, out or count invalid");
     if (instance < 0 || instance >= (int)s->ops.size())
         return fail(AAR_ERR_INVALID_ARG, "instance out of range");
-    if (!s->log)
+    const double *log = s->B.on ? s->B.log : s->log;
+    if (!log)
         return fail(AAR_ERR_INVALID_ARG, "solver created without AAR_FLAG_RECORD_RESIDUALS");
-    if (instance != s->last_instance && s->ops.size() > 1)
+    if (!s->B.on && instance != s->last_instance && s->ops.size() > 1)
         return fail(AAR_ERR_UNSUPPORTED, "only the last solved system's log is kept");
     const int64_t have = std::min<int64_t>(s->last_log_count[instance], s->log_cap);
     *count = have;
     const int64_t n = std::min(have, cap);
     if (n > 0)
-        AAR_HIP(hipMemcpy(out, s->log, sizeof(double) * n, hipMemcpyDeviceToHost));
+        AAR_HIP(hipMemcpy(out, log + (s->B.on ? (int64_t)instance * s->log_cap : 0), sizeof(double) * n,
+                          hipMemcpyDeviceToHost));
     return AAR_OK;
 }
 

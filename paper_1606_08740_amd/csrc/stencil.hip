@@ -45,8 +45,11 @@ template <typename T> __device__ inline T wave_sum(T v)
     return v;
 }
 
+// One tile (64 x 4 RY columns, planes [bz*cz, bz*cz + cz)) of a stencil pass.
+// `lin` is the tile's linear index (x fastest, then y, then z chunk); the
+// reduction partial (kFk, kResid) goes to *partial_out.
 template <typename T, typename H, int R, bool CONV, int MODE, int RY>
-__global__ __launch_bounds__(kThreads) void k_stencil(const StencilArgs<T> a)
+__device__ __forceinline__ void stencil_tile(const StencilArgs<T> &a, int lin, double *partial_out)
 {
     // FP64 hot passes use the weighted-sum form (half the flops); FP32 passes
     // and the FP64 refinement residual keep the difference form.
@@ -73,7 +76,6 @@ __global__ __launch_bounds__(kThreads) void k_stencil(const StencilArgs<T> a)
 
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = tx + kTX * ty;
-    int lin = xcd_tile(blockIdx.x, gridDim.x);
     const int bx = lin % a.tiles_x;
     lin /= a.tiles_x;
     const int by = lin % a.tiles_y;
@@ -285,8 +287,127 @@ __global__ __launch_bounds__(kThreads) void k_stencil(const StencilArgs<T> a)
             double s = 0.0;
             for (int w = 0; w < kWY; ++w)
                 s += red[w];
-            a.partial[blockIdx.x] = s;
+            *partial_out = s;
         }
+    }
+}
+
+template <typename T, typename H, int R, bool CONV, int MODE, int RY>
+__global__ __launch_bounds__(kThreads) void k_stencil(const StencilArgs<T> a)
+{
+    stencil_tile<T, H, R, CONV, MODE, RY>(a, xcd_tile(blockIdx.x, gridDim.x), a.partial + blockIdx.x);
+}
+
+// Batched form: work item w = (system, tile) of the active list; the system's
+// operator, vectors and run state come from its descriptor.  Blocks stride
+// over the list (its length is read on the device).
+template <typename T, typename H, int R, bool CONV, int MODE, int RY>
+__global__ __launch_bounds__(kThreads) void k_stencil_batched(const BatchStencilArgs<T> ba)
+{
+    const int nitems = *ba.nitems;
+    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+        const int2 it = ba.items[w];
+        const BatchDesc<T> &d = ba.desc[it.x];
+        StencilArgs<T> a;
+        a.st = d.st;
+        a.x = ba.x + d.off;
+        a.b = ba.b + d.off;
+        a.out = ba.out ? ba.out + d.off : nullptr;
+        a.fring = (void *)((H *)ba.fring + d.off);
+        a.fcur = ba.fcur ? ba.fcur + d.off : nullptr;
+        a.partial = nullptr;
+        a.state = ba.state + it.x;
+        a.slot_stride = ba.slot_stride;
+        a.j = ba.j;
+        a.p = ba.p;
+        a.nslots = ba.nslots;
+        a.cz = d.cz;
+        a.tiles_x = d.tiles_x;
+        a.tiles_y = d.tiles_y;
+        a.tiles_z = d.tiles_z;
+        a.omega = ba.omega;
+        if constexpr (MODE == kResid) {
+            if (!ba.mask || ba.mask[it.x] == 0)
+                continue;
+        }
+        stencil_tile<T, H, R, CONV, MODE, RY>(a, it.y, ba.partial ? ba.partial + w : nullptr);
+        __syncthreads();   // LDS is reused by the next item
+    }
+}
+
+template <typename T, typename H, int MODE>
+static hipError_t launch_batched_radius(int radius, bool conv, int ry, const BatchStencilArgs<T> &a, int grid,
+                                        hipStream_t s)
+{
+#define AAR_BATCH_RY(R, CONV)                                                                      \
+    switch (ry) {                                                                                  \
+    case 1:                                                                                        \
+        hipLaunchKernelGGL((k_stencil_batched<T, H, R, CONV, MODE, 1>), dim3(grid), dim3(kTX, kWY), \
+                           0, s, a);                                                               \
+        return hipGetLastError();                                                                  \
+    case 2:                                                                                        \
+        hipLaunchKernelGGL((k_stencil_batched<T, H, R, CONV, MODE, 2>), dim3(grid), dim3(kTX, kWY), \
+                           0, s, a);                                                               \
+        return hipGetLastError();                                                                  \
+    case 4:                                                                                        \
+        hipLaunchKernelGGL((k_stencil_batched<T, H, R, CONV, MODE, 4>), dim3(grid), dim3(kTX, kWY), \
+                           0, s, a);                                                               \
+        return hipGetLastError();                                                                  \
+    default:                                                                                       \
+        return hipErrorInvalidValue;                                                               \
+    }
+    if (conv) {
+        if (radius != 1)
+            return hipErrorInvalidValue;
+        AAR_BATCH_RY(1, true)
+    }
+    switch (radius) {
+    case 1:
+        AAR_BATCH_RY(1, false)
+    case 2:
+        AAR_BATCH_RY(2, false)
+    case 3:
+        AAR_BATCH_RY(3, false)
+    case 4:
+        AAR_BATCH_RY(4, false)
+    case 5:
+        AAR_BATCH_RY(5, false)
+    case 6:
+        AAR_BATCH_RY(6, false)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef AAR_BATCH_RY
+}
+
+hipError_t launch_stencil_batched_f64(int mode, int radius, bool conv, int ry, const BatchStencilArgs<double> &a,
+                                      int grid, hipStream_t s)
+{
+    switch (mode) {
+    case kSweep:
+        return launch_batched_radius<double, double, kSweep>(radius, conv, ry, a, grid, s);
+    case kFk:
+        return launch_batched_radius<double, double, kFk>(radius, conv, ry, a, grid, s);
+    case kResid:
+        return launch_batched_radius<double, double, kResid>(radius, conv, ry, a, grid, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_stencil_batched_f32(int mode, Prec hist, int radius, bool conv, int ry,
+                                      const BatchStencilArgs<float> &a, int grid, hipStream_t s)
+{
+    const bool bf = hist == Prec::F32_BF16;
+    switch (mode) {
+    case kSweep:
+        return bf ? launch_batched_radius<float, bf16_t, kSweep>(radius, conv, ry, a, grid, s)
+                  : launch_batched_radius<float, float, kSweep>(radius, conv, ry, a, grid, s);
+    case kFk:
+        return bf ? launch_batched_radius<float, bf16_t, kFk>(radius, conv, ry, a, grid, s)
+                  : launch_batched_radius<float, float, kFk>(radius, conv, ry, a, grid, s);
+    default:
+        return hipErrorInvalidValue;
     }
 }
 

@@ -99,3 +99,90 @@ def test_batched_mixed_matches_solo():
         xi = xs[s.offsets[i]: s.offsets[i + 1]]
         assert res[i]["status"] == aar.AAR_OK
         assert oracle.relative_residual(p, bi, xi) < prm.tol
+
+
+def _helmholtz_batch(sizes, shifts, seed=70):
+    probs = [inputs.periodic_problem(n, 4, shift=s) for n, s in zip(sizes, shifts)]
+    bs = [inputs.normal(seed + i, 0, p.size) for i, p in enumerate(probs)]
+    return probs, bs
+
+
+def _run_batch(probs, bs, prm, x0=None):
+    s = aar.Solver(probs, prm)
+    b = to_dev(np.concatenate(bs))
+    x = to_dev(np.zeros(sum(p.size for p in probs)) if x0 is None else x0)
+    res = s.solve_batched(b, x)
+    xs = x.cpu().numpy()
+    logs = [s.residual_log(i) for i in range(len(probs))] if prm.flags & aar.AAR_FLAG_RECORD_RESIDUALS else None
+    offs = s.offsets.copy()
+    s.close()
+    return [xs[offs[i]: offs[i + 1]] for i in range(len(probs))], res, logs
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_engine_matches_oracle(precision):
+    """Uneven sizes (tiles and chunks with ragged tails, one system smaller
+    than a tile) and shifts; every system against its own oracle solve."""
+    sizes = [16, 41, 23, 70, 17, 33, 16, 52]
+    shifts = [9.0, 0.7, 3.0, 1.5, 0.2, 6.0, 4.0, 0.4]
+    probs, bs = _helmholtz_batch(sizes, shifts)
+    prm = inputs.Params(tol=1e-10, precision=precision, flags=aar.AAR_FLAG_RECORD_RESIDUALS)
+    say(f"batched engine precision={precision} systems={len(probs)}")
+    xs, res, logs = _run_batch(probs, bs, prm)
+    for i, (p, bi) in enumerate(zip(probs, bs)):
+        assert res[i]["status"] == aar.AAR_OK, (i, res[i])
+        assert oracle.relative_residual(p, bi, xs[i]) < prm.tol
+        ref = oracle.aar_solve(p, bi, m=prm.m, p=prm.p, tol=prm.tol, trace_cap=100000)
+        assert rel_err(xs[i], ref["x"]) < 1e-7
+        if precision == 0:
+            # FP64: same iteration as a single solve; residual trace tracks the oracle
+            assert abs(res[i]["iterations"] - ref["iterations"]) <= prm.p
+            np.testing.assert_allclose(logs[i][:3], ref["trace"][:3, 1], rtol=1e-8)
+        else:
+            assert res[i]["outer_steps"] >= 1
+
+
+def test_batched_engine_equals_single_solves():
+    sizes = [20, 37, 16, 29]
+    shifts = [2.0, 0.3, 5.0, 1.1]
+    probs, bs = _helmholtz_batch(sizes, shifts, seed=90)
+    prm = inputs.Params(tol=1e-10, precision=0)
+    say("batched vs single")
+    xs, res, _ = _run_batch(probs, bs, prm)
+    for i, (p, bi) in enumerate(zip(probs, bs)):
+        x1, r1, _ = gpu_solve(p, prm, bi)
+        assert res[i]["iterations"] == r1["iterations"]
+        np.testing.assert_allclose(xs[i], x1, rtol=0, atol=1e-12 * np.abs(x1).max())
+
+
+def test_batched_engine_edge_systems():
+    """A zero right-hand side and a NaN one inside a batch only affect their own results."""
+    sizes = [18, 20, 22, 16]
+    shifts = [1.0, 2.0, 0.5, 3.0]
+    probs, bs = _helmholtz_batch(sizes, shifts, seed=95)
+    bs[1] = np.zeros_like(bs[1])
+    bs[2] = bs[2].copy()
+    bs[2][7] = np.nan
+    for precision in [0, 1]:
+        prm = inputs.Params(tol=1e-10, precision=precision)
+        say(f"batched edge systems precision={precision}")
+        x0 = np.ones(sum(p.size for p in probs))
+        xs, res, _ = _run_batch(probs, bs, prm, x0=x0)
+        assert res[1]["status"] == aar.AAR_OK and (xs[1] == 0).all()
+        assert res[2]["status"] == aar.AAR_BREAKDOWN
+        for i in (0, 3):
+            assert res[i]["status"] == aar.AAR_OK
+            assert oracle.relative_residual(probs[i], bs[i], xs[i]) < prm.tol
+
+
+def test_batched_engine_deflated_small_shifts():
+    sizes = [24, 40, 16, 33]
+    shifts = [0.02, 0.05, 0.01, 0.3]
+    probs, bs = _helmholtz_batch(sizes, shifts, seed=99)
+    for precision in [0, 1]:
+        prm = inputs.Params(tol=1e-10, precision=precision, flags=aar.AAR_FLAG_DEFLATE_CONSTANT)
+        say(f"batched deflated precision={precision}")
+        xs, res, _ = _run_batch(probs, bs, prm)
+        for i, (p, bi) in enumerate(zip(probs, bs)):
+            assert res[i]["status"] == aar.AAR_OK, (i, res[i])
+            assert oracle.relative_residual(p, bi, xs[i]) < prm.tol
