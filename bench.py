@@ -34,6 +34,26 @@ HBM_PEAK_GBS = 8000.0
 # Oracle (FP64, CPU) iterations to 1e-10 on the default workload, written by
 # tests/golden/make_golden.py (oracle only).
 GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_full_size.json")
+# HBM traffic of the sweep kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+# scaled by a plain copy's counters; valid while the kernel source is unchanged.
+SWEEP_PROFILE = os.path.join(ROOT, "profiles", "k_stencil_sweep_fp64_r6_192.md")
+STENCIL_SRC = os.path.join(ROOT, "paper_1606_08740_amd", "csrc", "stencil.hip")
+
+
+def sweep_traffic(n):
+    """Counter-measured bytes per sweep launch, or None when absent or stale."""
+    import hashlib
+    import re
+    if n != 192 or not os.path.exists(SWEEP_PROFILE):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(SWEEP_PROFILE).read(), flags=re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    sha = hashlib.sha256(open(STENCIL_SRC, "rb").read()).hexdigest()[:16]
+    if rec.get("stencil_source_sha256_16") != sha:
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def parse():
@@ -46,7 +66,24 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=24)
     ap.add_argument("--kernel-timing-solves", type=int, default=1)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-count", type=int, default=512)
+    ap.add_argument("--batched-steps", type=int, default=2)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (scale for the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 2^27 doubles (1 GiB read, 1 GiB written),
+    three times: the HBM counters of this kernel calibrate those of the solver."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8}))
 
 
 def timed_solves(solver, bt, steps, warmup):
@@ -70,6 +107,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import numpy as np
     import torch
 
@@ -119,7 +159,7 @@ def main():
         "rel_residual": r64["rel_residual"],
         "status": r64["status"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic(args.n),
                      "kernel": "k_stencil<double,double,6,false,kSweep> (fused Richardson sweep)",
                      "bytes_per_launch": sweep_bytes, "mean_launch_us": sweep_us, "launches": launches},
     }
@@ -140,6 +180,40 @@ def main():
                              "rel_residual": rm["rel_residual"], "status": rm["status"],
                              "speedup_vs_fp64": dt64 / dtm,
                              "rel_diff_vs_fp64_gpu": float(np.linalg.norm(xa - xb) / np.linalg.norm(xa))}
+
+    # ---- batched: 512 shifted periodic Helmholtz systems, one call ----
+    if not args.no_batched:
+        wb = inputs.workload(5, count=args.batched_count)
+        bb = torch.as_tensor(np.concatenate(wb.b), device="cuda:0")
+        out["batched"] = {"workload": f"{args.batched_count} periodic shifted Helmholtz systems, 8th-order "
+                                      "central FD (25-point), n ~ U{16..96}, sigma ~ U(0,10), b ~ N(0,1), "
+                                      "exact constant-mode deflation, tol 1e-10",
+                          "points": int(sum(p.size for p in wb.problems))}
+        for label, prec in [("fp64", aar.AAR_FP64), ("mixed_fp32", aar.AAR_MIXED_FP32)]:
+            pb = inputs.Params(**{**wb.params.__dict__})
+            pb.precision = prec
+            sb = aar.Solver(wb.problems, pb)
+            res = None
+            for _ in range(max(args.warmup, 1)):
+                xb = torch.zeros_like(bb)
+                res = sb.solve_batched(bb, xb)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.batched_steps):
+                xb = torch.zeros_like(bb)
+                res = sb.solve_batched(bb, xb)
+            torch.cuda.synchronize()
+            dtb = (time.perf_counter() - t0) / args.batched_steps
+            sb.close()
+            its = [r["iterations"] for r in res]
+            out["batched"][label] = {"value": args.batched_count / dtb, "unit": "solves/s",
+                                     "ms_per_call": dtb * 1e3,
+                                     "converged": int(sum(r["status"] == 0 for r in res)),
+                                     "iterations_total": int(sum(its)), "iterations_max": int(max(its)),
+                                     "max_rel_residual": float(max(r["rel_residual"] for r in res))}
+        out["batched"]["mixed_speedup_vs_fp64"] = (out["batched"]["mixed_fp32"]["value"] /
+                                                   out["batched"]["fp64"]["value"])
+        del bb
 
     # ---- CPU oracle baseline (bounded sample) ----
     if not args.no_cpu_baseline:

@@ -12,6 +12,7 @@
 //
 // Mixed precision wraps the FP32 iteration in FP64 iterative refinement:
 // r = b - A x (FP64), inner FP32 AAR on A d = r / ||r||, x += ||r|| d.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,7 +20,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -628,9 +631,55 @@ template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool 
 
 // Tile autotuner: time the Richardson sweep for each candidate tile height
 // (rows per thread) and z depth on this grid, keep the fastest.  Results are
-// cached per (precision, radius, convection, grid) for the process.
+// cached per (precision, radius, convection, grid) for the process.  The
+// cache is seeded from a tile file (AAR_TUNE_CACHE, else tuned_tiles.txt next
+// to this library: lines "prec radius conv n0 n1 n2 rows_per_thread z_depth",
+// prec 0 = FP64, 1 = FP32), so tuned shapes are reproducible; with
+// AAR_TUNE_CACHE_WRITE set, new results are appended to that file.
 std::mutex g_tune_mutex;
 std::map<std::tuple<int, int, int, int, int, int>, TileShape> g_tune_cache;
+bool g_tune_loaded = false;
+
+void load_tune_file()
+{
+    if (g_tune_loaded)
+        return;
+    g_tune_loaded = true;
+    std::string path;
+    if (const char *env = getenv("AAR_TUNE_CACHE")) {
+        path = env;
+    } else {
+        Dl_info info;
+        if (dladdr((void *)&load_tune_file, &info) && info.dli_fname) {
+            std::string lib = info.dli_fname;
+            const size_t slash = lib.rfind('/');
+            path = (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/tuned_tiles.txt";
+        }
+    }
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        if (line.empty() || line[0] == '#')
+            continue;
+        std::istringstream in(line);
+        int prec, radius, conv, n0, n1, n2, ry, cz;
+        if (!(in >> prec >> radius >> conv >> n0 >> n1 >> n2 >> ry >> cz))
+            continue;
+        if ((ry != 1 && ry != 2 && ry != 4) || cz < 1)
+            continue;
+        g_tune_cache[std::make_tuple(prec, radius, conv, n0, n1, n2)] = TileShape{ry, cz};
+    }
+}
+
+void append_tune_file(const std::tuple<int, int, int, int, int, int> &key, const TileShape &ts)
+{
+    const char *path = getenv("AAR_TUNE_CACHE_WRITE");
+    if (!path)
+        return;
+    std::ofstream f(path, std::ios::app);
+    f << std::get<0>(key) << ' ' << std::get<1>(key) << ' ' << std::get<2>(key) << ' ' << std::get<3>(key) << ' '
+      << std::get<4>(key) << ' ' << std::get<5>(key) << ' ' << ts.ry << ' ' << ts.cz << '\n';
+}
 
 template <typename T> aar_status autotune(aar_solver_t *S, int idx)
 {
@@ -640,6 +689,7 @@ template <typename T> aar_status autotune(aar_solver_t *S, int idx)
                                      op.prob.n[0], op.prob.n[1], op.prob.n[2]);
     {
         std::lock_guard<std::mutex> lock(g_tune_mutex);
+        load_tune_file();
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
             op.ts[f64 ? 0 : 1] = it->second;
@@ -695,11 +745,11 @@ template <typename T> aar_status autotune(aar_solver_t *S, int idx)
                 continue;      // same grid as a smaller depth
             prev_tz = tz;
             hipError_t e = hipSuccess;
-            for (int w = 0; w < 2 && e == hipSuccess; ++w)
+            for (int w = 0; w < 3 && e == hipSuccess; ++w)
                 e = Launch<T>::stencil(kSweep, P, a, s, ts);
             if (e == hipSuccess)
                 e = hipEventRecord(e0, s);
-            for (int w = 0; w < 5 && e == hipSuccess; ++w)
+            for (int w = 0; w < 10 && e == hipSuccess; ++w)
                 e = Launch<T>::stencil(kSweep, P, a, s, ts);
             if (e == hipSuccess)
                 e = hipEventRecord(e1, s);
@@ -727,6 +777,7 @@ template <typename T> aar_status autotune(aar_solver_t *S, int idx)
     op.ts[f64 ? 0 : 1] = best;
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     g_tune_cache[key] = best;
+    append_tune_file(key, best);
     return AAR_OK;
 }
 
