@@ -170,6 +170,7 @@ struct aar_solver_t {
     InstState *state = nullptr;
     double *part_rho = nullptr, *part_gram = nullptr, *part_norm = nullptr;
     double *gram_final = nullptr;
+    int part_rho_cap = 0;      // entries of part_rho (stencil workgroups of one pass)
     double *scal = nullptr;       // [0] ||r|| of the refinement, [1] ||b|| (FP64)
     double *log = nullptr;
     int64_t log_cap = 0;
@@ -357,11 +358,15 @@ Sizes compute_sizes(const aar_problem *probs, int count, const aar_params *pa)
         const aar_problem &pr = probs[i];
         const int64_t N = (int64_t)pr.n[0] * pr.n[1] * pr.n[2];
         z.maxN = std::max(z.maxN, N);
-        for (int f64 = 0; f64 < 2; ++f64) {
-            TileShape ts = default_tile(pr.radius, f64 == 1);
-            int tx, ty, tz, blocks;
-            stencil_grid(pr.n[0], pr.n[1], pr.n[2], ts, &tx, &ty, &tz, &blocks);
-            z.max_stencil_blocks = std::max(z.max_stencil_blocks, blocks);
+        // partial sums are one per stencil workgroup: size them for the
+        // largest grid any candidate tile shape (autotuner, tile file) gives
+        for (int ry : {1, 2, 4}) {
+            for (int cz : {1, 2, 4, 8, 16, 32, 64}) {
+                TileShape ts{ry, cz};
+                int tx, ty, tz, blocks;
+                stencil_grid(pr.n[0], pr.n[1], pr.n[2], ts, &tx, &ty, &tz, &blocks);
+                z.max_stencil_blocks = std::max(z.max_stencil_blocks, blocks);
+            }
         }
         if (pr.velocity)
             vel_total += 3 * N;
@@ -801,6 +806,8 @@ aar_status solve_one(aar_solver_t *S, int idx, const double *b, double *x, aar_r
     if (!S->mixed) {
         Path<double> &P = S->p64;
         bind_path(S, P, idx, true);
+        if (P.rho_blocks > S->part_rho_cap)
+            return fail(AAR_ERR_DEVICE, "stencil grid exceeds the partial-sum workspace");
         AAR_HIP(hipMemcpyAsync(P.b, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
         AAR_HIP(hipMemcpyAsync(P.xa, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
         const int nb_blocks = stream_blocks(N);
@@ -861,6 +868,8 @@ aar_status solve_one(aar_solver_t *S, int idx, const double *b, double *x, aar_r
     bind_path(S, P, idx, false);
     Path<double> R64;
     bind_path(S, R64, idx, true);
+    if (P.rho_blocks > S->part_rho_cap || R64.rho_blocks > S->part_rho_cap)
+        return fail(AAR_ERR_DEVICE, "stencil grid exceeds the partial-sum workspace");
     AAR_HIP(hipMemcpyAsync(S->b64, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
     AAR_HIP(hipMemcpyAsync(S->x64, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
     const int nb_blocks = stream_blocks(N);
@@ -1576,6 +1585,7 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
     st = AAR_OK;
     S->state = S->alloc<InstState>(1, &st);
     S->part_rho = S->alloc<double>(z.max_stencil_blocks, &st);
+    S->part_rho_cap = z.max_stencil_blocks;
     S->part_gram = S->alloc<double>((size_t)z.gram_blocks * z.ne, &st);
     S->part_norm = S->alloc<double>(z.gram_blocks, &st);
     S->gram_final = S->alloc<double>(z.ne, &st);
