@@ -60,13 +60,18 @@ enum { AAR_BC_ZERO_DIRICHLET = 0, AAR_BC_PERIODIC = 1 };
 
 /* Arithmetic of the iteration.
  *   AAR_FP64: every step in FP64.
+ *   AAR_FP64_FP32HIST / AAR_FP64_BF16HIST: x, b and every residual in FP64,
+ *     the history ring (the f_j of Eqs. 4-5) stored in FP32 / bfloat16; Gram
+ *     products accumulated in FP64.  No refinement is needed: the iterate
+ *     and the convergence test are FP64; only the extrapolation directions
+ *     are rounded.
  *   AAR_MIXED_FP32: FP32 sweeps, history and Gram products (accumulated in
  *     FP64), FP64 m x m solve, and an outer FP64 iterative refinement:
  *     r = b - A x (FP64), inner FP32 AAR on A d = r/||r|| to inner_tol,
  *     x += ||r|| d, until ||b - A x|| / ||b|| < tol.
  *   AAR_MIXED_FP32_BF16HIST: as AAR_MIXED_FP32 with the history columns
  *     stored in bfloat16 (round to nearest even). */
-enum { AAR_FP64 = 0, AAR_MIXED_FP32 = 1, AAR_MIXED_FP32_BF16HIST = 2 };
+enum { AAR_FP64 = 0, AAR_MIXED_FP32 = 1, AAR_MIXED_FP32_BF16HIST = 2, AAR_FP64_FP32HIST = 3, AAR_FP64_BF16HIST = 4 };
 
 enum {
     AAR_FLAG_RECORD_RESIDUALS = 1, /* keep r_k of every Anderson step (aar_residual_log)        */
@@ -104,7 +109,7 @@ typedef struct {
     int32_t p;               /* Anderson every p iterations, >= 1                paper: 8    */
     double tol;              /* on ||b - A x|| / ||b||, > 0                                  */
     int64_t max_iter;        /* cap on iterations (inner iterations in mixed mode), >= 1    */
-    int32_t precision;       /* AAR_FP64 / AAR_MIXED_FP32 / AAR_MIXED_FP32_BF16HIST          */
+    int32_t precision;       /* AAR_FP64, AAR_MIXED_FP32(_BF16HIST), AAR_FP64_*HIST           */
     double inner_tol;        /* mixed: inner FP32 tolerance (0 selects 1e-5)                 */
     int32_t max_outer;       /* mixed: cap on refinement steps (0 selects 30)                */
     uint32_t flags;          /* AAR_FLAG_*                                                   */

@@ -23,7 +23,7 @@ HEADER = os.path.join(ROOT, "include", "aar.h")
 AAR_OK, AAR_NOT_CONVERGED, AAR_BREAKDOWN = 0, 1, 2
 AAR_ERR_INVALID_ARG, AAR_ERR_UNSUPPORTED, AAR_ERR_DEVICE, AAR_ERR_OUT_OF_MEMORY = -1, -2, -3, -4
 AAR_BC_ZERO_DIRICHLET, AAR_BC_PERIODIC = 0, 1
-AAR_FP64, AAR_MIXED_FP32, AAR_MIXED_FP32_BF16HIST = 0, 1, 2
+AAR_FP64, AAR_MIXED_FP32, AAR_MIXED_FP32_BF16HIST, AAR_FP64_FP32HIST, AAR_FP64_BF16HIST = 0, 1, 2, 3, 4
 AAR_FLAG_RECORD_RESIDUALS, AAR_FLAG_DEFLATE_CONSTANT, AAR_FLAG_NO_GRAPH, AAR_FLAG_NO_AUTOTUNE = 1, 2, 4, 8
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "BREAKDOWN", -1: "INVALID_ARG", -2: "UNSUPPORTED",

@@ -72,6 +72,7 @@ template <> struct Hist<double> {
 template <> struct Hist<float> {
     __device__ static inline float load(const float *p, int64_t i) { return p[i]; }
     __device__ static inline void store(float *p, int64_t i, float v) { p[i] = v; }
+    __device__ static inline void store(float *p, int64_t i, double v) { p[i] = (float)v; }
 };
 template <> struct Hist<bf16_t> {
     __device__ static inline float load(const bf16_t *p, int64_t i)
@@ -88,6 +89,7 @@ template <> struct Hist<bf16_t> {
         u += 0x7fffu + ((u >> 16) & 1u);                 // round to nearest, ties to even
         p[i].bits = (uint16_t)(u >> 16);
     }
+    __device__ static inline void store(bf16_t *p, int64_t i, double v) { store(p, i, (float)v); }
 };
 
 // Operator description passed by value to the stencil kernels.

@@ -396,10 +396,23 @@ __global__ __launch_bounds__(kThreads) void k_update(const UpdateArgs<T> a)
 hipError_t launch_update(Prec prec, const UpdateArgs<double> *a64, const UpdateArgs<float> *a32, int blocks,
                          hipStream_t s)
 {
+    if (a64) {   // FP64 iterate: history in FP64, FP32 or bf16
+        switch (prec) {
+        case Prec::F64:
+            hipLaunchKernelGGL((k_update<double, double>), dim3(blocks), dim3(kThreads), 0, s, *a64);
+            break;
+        case Prec::F32:
+            hipLaunchKernelGGL((k_update<double, float>), dim3(blocks), dim3(kThreads), 0, s, *a64);
+            break;
+        case Prec::F32_BF16:
+            hipLaunchKernelGGL((k_update<double, bf16_t>), dim3(blocks), dim3(kThreads), 0, s, *a64);
+            break;
+        }
+        return hipGetLastError();
+    }
     switch (prec) {
     case Prec::F64:
-        hipLaunchKernelGGL((k_update<double, double>), dim3(blocks), dim3(kThreads), 0, s, *a64);
-        break;
+        return hipErrorInvalidValue;
     case Prec::F32:
         hipLaunchKernelGGL((k_update<float, float>), dim3(blocks), dim3(kThreads), 0, s, *a32);
         break;

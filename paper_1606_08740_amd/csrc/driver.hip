@@ -141,6 +141,25 @@ size_t hist_bytes(Prec p)
     return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2);
 }
 
+bool is_mixed(int precision)
+{
+    return precision == AAR_MIXED_FP32 || precision == AAR_MIXED_FP32_BF16HIST;
+}
+
+Prec hist_of(int precision)
+{
+    switch (precision) {
+    case AAR_MIXED_FP32:
+    case AAR_FP64_FP32HIST:
+        return Prec::F32;
+    case AAR_MIXED_FP32_BF16HIST:
+    case AAR_FP64_BF16HIST:
+        return Prec::F32_BF16;
+    default:
+        return Prec::F64;
+    }
+}
+
 // Byte offset added between consecutive bulk vectors (multiple of 64).
 size_t stagger_bytes()
 {
@@ -180,6 +199,7 @@ struct aar_solver_t {
 
     int64_t slot_stride[2] = {0, 0};   // ring slot spacing (elements) for the FP64 and FP32 paths
     int64_t dx_stride = 0;              // FP32 path: dx slot spacing (elements)
+    int64_t dx_stride64 = 0;            // FP64 path: dx slot spacing (elements)
 
     // graphs (single system)
     hipGraphExec_t graph = nullptr;
@@ -283,7 +303,7 @@ aar_status validate_params(const aar_params *pa)
         return fail(AAR_ERR_INVALID_ARG, "max_iter must be >= 1");
     if (!std::isfinite(pa->omega) || !std::isfinite(pa->beta))
         return fail(AAR_ERR_INVALID_ARG, "omega and beta must be finite");
-    if (pa->precision < AAR_FP64 || pa->precision > AAR_MIXED_FP32_BF16HIST)
+    if (pa->precision < AAR_FP64 || pa->precision > AAR_FP64_BF16HIST)
         return fail(AAR_ERR_INVALID_ARG, "unknown precision");
     if (!(pa->inner_tol >= 0.0) || pa->inner_tol >= 1.0 || pa->max_outer < 0)
         return fail(AAR_ERR_INVALID_ARG, "inner_tol must be in [0, 1) and max_outer >= 0");
@@ -350,9 +370,8 @@ struct Sizes {
 Sizes compute_sizes(const aar_problem *probs, int count, const aar_params *pa)
 {
     Sizes z;
-    const bool mixed = pa->precision != AAR_FP64;
-    const Prec hist = pa->precision == AAR_FP64 ? Prec::F64
-                      : pa->precision == AAR_MIXED_FP32 ? Prec::F32 : Prec::F32_BF16;
+    const bool mixed = is_mixed(pa->precision);
+    const Prec hist = hist_of(pa->precision);
     int64_t vel_total = 0;
     for (int i = 0; i < count; ++i) {
         const aar_problem &pr = probs[i];
@@ -381,7 +400,7 @@ Sizes compute_sizes(const aar_problem *probs, int count, const aar_params *pa)
     b += sizeof(InstState) * (size_t)count;
     b += sizeof(double) * ((size_t)z.max_stencil_blocks + (size_t)z.gram_blocks * z.ne + z.gram_blocks + z.ne + 8);
     if (!mixed) {
-        b += vec_span(8) * (3 + slots + z.q);
+        b += vec_span(8) * (3 + z.q) + vec_span(hist_bytes(hist)) * slots + (hist != Prec::F64 ? vec_span(8) : 0);
         b += sizeof(double) * (size_t)vel_total;
     } else {
         b += vec_span(4) * (3 + z.q) + vec_span(hist_bytes(hist)) * slots + vec_span(8) * 3;
@@ -627,7 +646,7 @@ template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool 
     P.gram_blocks = gram_blocks(op.N);
     P.upd_blocks = stream_blocks(op.N);
     P.slot_stride = S->slot_stride[f64 ? 0 : 1];
-    P.dx_stride = f64 ? S->slot_stride[0] : S->dx_stride;
+    P.dx_stride = f64 ? S->dx_stride64 : S->dx_stride;
     if constexpr (std::is_same<T, double>::value)
         P.st = make_stencil<double>(op, op.vel64);
     else
@@ -977,7 +996,7 @@ constexpr int kBatchGrid = 8192;
 // batches are solved one system after another.
 bool batch_eligible(const aar_problem *probs, int count, const aar_params *pa)
 {
-    if (count < 2 || pa->m > kFastGramM)
+    if (count < 2 || pa->m > kFastGramM || pa->precision > AAR_MIXED_FP32_BF16HIST)
         return false;
     for (int i = 1; i < count; ++i) {
         if (probs[i].radius != probs[0].radius || (probs[i].velocity != nullptr) != (probs[0].velocity != nullptr))
@@ -1564,9 +1583,8 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
     std::unique_ptr<aar_solver_t> S(new aar_solver_t());
     S->params = *params;
     S->stream = (hipStream_t)hip_stream;
-    S->mixed = params->precision != AAR_FP64;
-    S->hist = params->precision == AAR_FP64 ? Prec::F64
-              : params->precision == AAR_MIXED_FP32 ? Prec::F32 : Prec::F32_BF16;
+    S->mixed = is_mixed(params->precision);
+    S->hist = hist_of(params->precision);
     AAR_HIP(hipGetDevice(&S->device));
     AAR_HIP(hipStreamCreateWithFlags(&S->capture_stream, hipStreamNonBlocking));
     AAR_HIP(hipHostMalloc((void **)&S->host_status, 2 * sizeof(int32_t), hipHostMallocDefault));
@@ -1604,7 +1622,8 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
         auto vec_span = [&](size_t esize) { return (((size_t)N * esize + 4095) / 4096) * 4096 + stagger; };
         size_t arena = 0;
         if (!S->mixed) {
-            arena = vec_span(8) * (3 + slots + S->q);
+            arena = vec_span(8) * (3 + S->q) + vec_span(hist_bytes(S->hist)) * slots +
+                    (S->hist != Prec::F64 ? vec_span(8) : 0);
         } else {
             arena = vec_span(4) * (3 + S->q) + vec_span(hist_bytes(S->hist)) * slots + vec_span(8) * 3 +
                     (S->hist == Prec::F32_BF16 ? vec_span(4) : 0);
@@ -1620,13 +1639,16 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
         };
         if (!S->mixed) {
             Path<double> &P = S->p64;
-            P.hist = Prec::F64;
+            P.hist = S->hist;
             P.xa = (double *)carve(8, 1);
             P.xb = (double *)carve(8, 1);
             P.b = (double *)carve(8, 1);
-            P.fring = carve(8, slots);
+            P.fring = carve(hist_bytes(S->hist), slots);
+            if (S->hist != Prec::F64)
+                P.fcur = (double *)carve(8, 1);      // f_k of the update in FP64
             P.dx = S->q > 0 ? (double *)carve(8, S->q) : nullptr;
-            S->slot_stride[0] = vec_span(8) / 8;
+            S->slot_stride[0] = vec_span(hist_bytes(S->hist)) / hist_bytes(S->hist);
+            S->dx_stride64 = vec_span(8) / 8;
         } else {
             Path<float> &P = S->p32;
             P.hist = S->hist;

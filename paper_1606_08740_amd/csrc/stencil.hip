@@ -480,8 +480,12 @@ static hipError_t launch_radius(int radius, bool conv, StencilArgs<T> a, const T
 hipError_t launch_stencil_f64(int mode, Prec hist, int radius, bool conv, const TileShape &ts,
                               StencilArgs<double> a, int *blocks_out, hipStream_t s)
 {
-    if (hist != Prec::F64)
-        return hipErrorInvalidValue;
+    if (hist == Prec::F32 && (mode == kSweep || mode == kFk))
+        return mode == kSweep ? launch_radius<double, float, kSweep>(radius, conv, a, ts, blocks_out, s)
+                              : launch_radius<double, float, kFk>(radius, conv, a, ts, blocks_out, s);
+    if (hist == Prec::F32_BF16 && (mode == kSweep || mode == kFk))
+        return mode == kSweep ? launch_radius<double, bf16_t, kSweep>(radius, conv, a, ts, blocks_out, s)
+                              : launch_radius<double, bf16_t, kFk>(radius, conv, a, ts, blocks_out, s);
     switch (mode) {
     case kSweep:
         return launch_radius<double, double, kSweep>(radius, conv, a, ts, blocks_out, s);

@@ -31,12 +31,20 @@ def test_workspace_bytes_scales_with_history():
     mixed = _ws(prob, inputs.Params(m=7, p=6, precision=1))
     bf = _ws(prob, inputs.Params(m=7, p=6, precision=2))
     assert bf < mixed
+    # FP64 iterate with a narrow history: 8 history slots of 4 or 2 bytes
+    # instead of 8, plus one FP64 copy of f_k
+    f64 = _ws(prob, inputs.Params(m=7, p=6, precision=0))
+    h32 = _ws(prob, inputs.Params(m=7, p=6, precision=3))
+    h16 = _ws(prob, inputs.Params(m=7, p=6, precision=4))
+    assert h16 < h32 < f64
+    assert f64 - h32 >= (8 * 4 - 8) * prob.size
 
 
 @pytest.mark.parametrize("field,value,status", [
     ("m", 0, aar.AAR_ERR_INVALID_ARG), ("m", 33, aar.AAR_ERR_INVALID_ARG), ("p", 0, aar.AAR_ERR_INVALID_ARG),
     ("tol", 0.0, aar.AAR_ERR_INVALID_ARG), ("tol", float("nan"), aar.AAR_ERR_INVALID_ARG),
-    ("max_iter", 0, aar.AAR_ERR_INVALID_ARG), ("precision", 7, aar.AAR_ERR_INVALID_ARG),
+    ("max_iter", 0, aar.AAR_ERR_INVALID_ARG), ("precision", 5, aar.AAR_ERR_INVALID_ARG),
+    ("precision", -1, aar.AAR_ERR_INVALID_ARG),
 ])
 def test_bad_params_rejected(field, value, status):
     prm = inputs.Params()

@@ -33,10 +33,10 @@ GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracl
 
 CASES = [
     ("dirichlet_poisson_7pt_32_tol1e-8", lambda: inputs.workload(1), [0]),
-    ("dirichlet_poisson_7pt_32_tol1e-10", lambda: inputs.workload(1, tol=1e-10), [0, 1, 2]),
-    ("periodic_poisson_r6_192", lambda: inputs.workload(2), [0, 1, 2]),
-    ("periodic_poisson_r6_256", lambda: inputs.workload(3), [0, 1, 2]),
-    ("convection_diffusion_upwind_128", lambda: inputs.workload(4), [0, 1, 2]),
+    ("dirichlet_poisson_7pt_32_tol1e-10", lambda: inputs.workload(1, tol=1e-10), [0, 1, 2, 3, 4]),
+    ("periodic_poisson_r6_192", lambda: inputs.workload(2), [0, 1, 2, 3, 4]),
+    ("periodic_poisson_r6_256", lambda: inputs.workload(3), [0, 1, 2, 3, 4]),
+    ("convection_diffusion_upwind_128", lambda: inputs.workload(4), [0, 1, 2, 3, 4]),
 ]
 
 
