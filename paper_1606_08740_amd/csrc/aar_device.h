@@ -65,14 +65,23 @@ struct bf16_t {
 };
 
 template <typename H> struct Hist;
+// store2: elements i and i + 1 (i even, p 16-byte aligned) in one store.
 template <> struct Hist<double> {
     __device__ static inline double load(const double *p, int64_t i) { return p[i]; }
     __device__ static inline void store(double *p, int64_t i, double v) { p[i] = v; }
+    __device__ static inline void store2(double *p, int64_t i, double v0, double v1)
+    {
+        *reinterpret_cast<double2 *>(p + i) = make_double2(v0, v1);
+    }
 };
 template <> struct Hist<float> {
     __device__ static inline float load(const float *p, int64_t i) { return p[i]; }
     __device__ static inline void store(float *p, int64_t i, float v) { p[i] = v; }
     __device__ static inline void store(float *p, int64_t i, double v) { p[i] = (float)v; }
+    template <typename V> __device__ static inline void store2(float *p, int64_t i, V v0, V v1)
+    {
+        *reinterpret_cast<float2 *>(p + i) = make_float2((float)v0, (float)v1);
+    }
 };
 template <> struct Hist<bf16_t> {
     __device__ static inline float load(const bf16_t *p, int64_t i)
@@ -90,6 +99,13 @@ template <> struct Hist<bf16_t> {
         p[i].bits = (uint16_t)(u >> 16);
     }
     __device__ static inline void store(bf16_t *p, int64_t i, double v) { store(p, i, (float)v); }
+    template <typename V> __device__ static inline void store2(bf16_t *p, int64_t i, V v0, V v1)
+    {
+        bf16_t t[2];
+        store(t, 0, (float)v0);
+        store(t, 1, (float)v1);
+        *reinterpret_cast<uint32_t *>(p + i) = (uint32_t)t[0].bits | ((uint32_t)t[1].bits << 16);
+    }
 };
 
 // Operator description passed by value to the stencil kernels.
@@ -129,6 +145,7 @@ template <typename T> struct StencilArgs {
     int32_t nslots;         // m + 1
     int32_t cz;             // z planes per workgroup
     int32_t tiles_x, tiles_y, tiles_z;
+    int32_t order;          // kOrder* bits: tile numbering and z direction
     T omega;
 };
 
@@ -337,10 +354,28 @@ __device__ inline int xcd_tile(int b, int nb)
 // Host-side launch helpers (implemented in the .hip sources)
 // ---------------------------------------------------------------------------
 
+// Tile order bits.  kOrderAltZ: odd z chunks march downwards, so two
+// z-neighbouring chunks read the planes they share at the same moment (both
+// at their start or both at their end) and the second read hits L2.
+// kOrderZFast: consecutive tile numbers (one XCD's share) run along z first,
+// so z-neighbours sit on the same XCD; otherwise along x, then y.
+constexpr int kOrderAltZ = 1;
+constexpr int kOrderZFast = 2;
+
 struct TileShape {
-    int ry;      // y rows per thread (tile height = kWY * ry)
+    int ry;      // y rows per thread (tile height = kWY * ry; 2 kWY * ry paired)
     int cz;      // z planes per workgroup
+    int order = 0;   // kOrder* bits
+    int pair = 0;    // 1: paired layout for the sweep and residual passes
 };
+
+// The paired layout (each thread owns two x-adjacent points, loaded and
+// stored as one vector) serves the Richardson sweep and the Anderson-step
+// residual of grids with an even x extent and no convection.
+inline bool paired_layout(const TileShape &ts, int n0, bool conv, int mode)
+{
+    return ts.pair != 0 && (n0 % 2) == 0 && !conv && (mode == kSweep || mode == kFk);
+}
 
 // Stencil pass; T is double for Prec::F64 and float otherwise; history type
 // follows prec.  Returns hipSuccess or the launch error.
@@ -348,7 +383,8 @@ hipError_t launch_stencil_f64(int mode, Prec hist, int radius, bool conv, const 
                               StencilArgs<double> a, int *blocks_out, hipStream_t s);
 hipError_t launch_stencil_f32(int mode, Prec hist, int radius, bool conv, const TileShape &ts,
                               StencilArgs<float> a, int *blocks_out, hipStream_t s);
-void stencil_grid(int n0, int n1, int n2, const TileShape &ts, int *tx, int *ty, int *tz, int *blocks);
+void stencil_grid(int n0, int n1, int n2, const TileShape &ts, int *tx, int *ty, int *tz, int *blocks,
+                  bool paired = false);
 hipError_t launch_stencil_batched_f64(int mode, int radius, bool conv, int ry, const BatchStencilArgs<double> &a,
                                       int grid, hipStream_t s);
 hipError_t launch_stencil_batched_f32(int mode, Prec hist, int radius, bool conv, int ry,
@@ -378,6 +414,6 @@ hipError_t launch_deflate(double *x, double *r, int64_t N, double inv_sigma, dou
                           double *scal, hipStream_t s);
 
 int stream_blocks(int64_t N);
-int gram_blocks(int64_t N);
+int gram_blocks(int64_t N, int m);
 
 }  // namespace aar

@@ -41,13 +41,18 @@ int stream_blocks(int64_t N)
 
 // Workgroups of the Gram pass: enough waves to cover HBM latency, few enough
 // that the one-workgroup solve reads its partial table in one pass.
-int gram_blocks(int64_t N)
+// Workgroups of the Gram pass: enough to cover N in 8-point strides, capped
+// at what the chip holds at once for the history length m (the register
+// footprint of the m(m+3)/2 accumulators sets 3 waves per SIMD at m = 7 and
+// 2 beyond), so no workgroup waits for a second round.
+int gram_blocks(int64_t N, int m)
 {
+    const int64_t cap = m <= 6 ? 1024 : m == 7 ? 768 : m <= kFastGramM ? 512 : 1024;
     int64_t b = (N + kThreads * 8 - 1) / (kThreads * 8);
     if (b < 1)
         b = 1;
-    if (b > 1024)
-        b = 1024;
+    if (b > cap)
+        b = cap;
     return (int)b;
 }
 
@@ -105,7 +110,40 @@ __global__ __launch_bounds__(kThreads) void k_gram(const GramArgs a)
     // slot bases are padded to 8 elements, so every V-aligned index is aligned
     const int64_t nvec = a.N / V;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvec; v += stride) {
+    if (l == MC) {
+        // Full history (every cycle after the first m iterations): all slots
+        // are read, and the loads of the next vector index are issued before
+        // the products of the current one, so each wave keeps its loads in
+        // flight while it computes.
+        using P = Pack<H, V>;
+        P cur[MC + 1], nxt[MC + 1];
+        int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (v < nvec) {
+#pragma unroll
+            for (int t = 0; t <= MC; ++t)
+                cur[t] = *reinterpret_cast<const P *>(slot[t] + v * V);
+        }
+        for (; v < nvec; v += stride) {
+            const int64_t vn = v + stride;
+            if (vn < nvec) {
+#pragma unroll
+                for (int t = 0; t <= MC; ++t)
+                    nxt[t] = *reinterpret_cast<const P *>(slot[t] + vn * V);
+            }
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                double col[MC + 1];
+#pragma unroll
+                for (int t = 0; t <= MC; ++t)
+                    col[t] = (double)Hist<H>::load(cur[t].v, u);
+                accumulate(col);
+            }
+#pragma unroll
+            for (int t = 0; t <= MC; ++t)
+                cur[t] = nxt[t];
+        }
+    }
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < MC && v < nvec; v += stride) {
         double fv[MC + 1][V];
 #pragma unroll
         for (int t = 0; t <= MC; ++t) {

@@ -390,7 +390,7 @@ Sizes compute_sizes(const aar_problem *probs, int count, const aar_params *pa)
         if (pr.velocity)
             vel_total += 3 * N;
     }
-    z.gram_blocks = std::max(gram_blocks(z.maxN), stream_blocks(z.maxN));
+    z.gram_blocks = std::max(gram_blocks(z.maxN, 1), stream_blocks(z.maxN));
     z.q = pa->m / pa->p;
     z.ne = pa->m * (pa->m + 1) / 2 + pa->m;
     const int slots = pa->m + 1;
@@ -641,9 +641,10 @@ template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool 
     P.conv = op.prob.velocity != nullptr;
     P.ts = op.ts[f64 ? 0 : 1];
     int tx, ty, tz, blocks;
-    stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], P.ts, &tx, &ty, &tz, &blocks);
+    stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], P.ts, &tx, &ty, &tz, &blocks,
+                 paired_layout(P.ts, op.prob.n[0], P.conv, kFk));
     P.rho_blocks = blocks;
-    P.gram_blocks = gram_blocks(op.N);
+    P.gram_blocks = gram_blocks(op.N, S->params.m);
     P.upd_blocks = stream_blocks(op.N);
     P.slot_stride = S->slot_stride[f64 ? 0 : 1];
     P.dx_stride = f64 ? S->dx_stride64 : S->dx_stride;
@@ -657,18 +658,20 @@ template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool 
 // (rows per thread) and z depth on this grid, keep the fastest.  Results are
 // cached per (precision, radius, convection, grid) for the process.  The
 // cache is seeded from a tile file (AAR_TUNE_CACHE, else tuned_tiles.txt next
-// to this library: lines "prec radius conv n0 n1 n2 rows_per_thread z_depth",
-// prec 0 = FP64, 1 = FP32), so tuned shapes are reproducible; with
+// to this library: lines "prec radius conv n0 n1 n2 rows_per_thread z_depth
+// [order [pair]]", prec 0 = FP64, 1 = FP32, order the kOrder* bits, pair 1
+// for the paired layout, both default 0), so tuned shapes are reproducible;
+// with
 // AAR_TUNE_CACHE_WRITE set, new results are appended to that file.
 std::mutex g_tune_mutex;
 std::map<std::tuple<int, int, int, int, int, int>, TileShape> g_tune_cache;
 bool g_tune_loaded = false;
+std::string g_tune_path;
 
+// Read the tile file once per path: a new AAR_TUNE_CACHE value is read when
+// it is first seen, its lines overriding cached shapes of the same key.
 void load_tune_file()
 {
-    if (g_tune_loaded)
-        return;
-    g_tune_loaded = true;
     std::string path;
     if (const char *env = getenv("AAR_TUNE_CACHE")) {
         path = env;
@@ -680,18 +683,27 @@ void load_tune_file()
             path = (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/tuned_tiles.txt";
         }
     }
+    if (g_tune_loaded && path == g_tune_path)
+        return;
+    g_tune_loaded = true;
+    g_tune_path = path;
     std::ifstream f(path);
     std::string line;
     while (std::getline(f, line)) {
         if (line.empty() || line[0] == '#')
             continue;
         std::istringstream in(line);
-        int prec, radius, conv, n0, n1, n2, ry, cz;
+        int prec, radius, conv, n0, n1, n2, ry, cz, order = 0, pair = 0;
         if (!(in >> prec >> radius >> conv >> n0 >> n1 >> n2 >> ry >> cz))
             continue;
-        if ((ry != 1 && ry != 2 && ry != 4) || cz < 1)
+        if (!(in >> order))
+            order = 0;
+        if (!(in >> pair))
+            pair = 0;
+        if ((ry != 1 && ry != 2 && ry != 4) || cz < 1 || order < 0 || order > 3 || pair < 0 || pair > 1 ||
+            (pair && ry > 2))
             continue;
-        g_tune_cache[std::make_tuple(prec, radius, conv, n0, n1, n2)] = TileShape{ry, cz};
+        g_tune_cache[std::make_tuple(prec, radius, conv, n0, n1, n2)] = TileShape{ry, cz, order, pair};
     }
 }
 
@@ -702,7 +714,8 @@ void append_tune_file(const std::tuple<int, int, int, int, int, int> &key, const
         return;
     std::ofstream f(path, std::ios::app);
     f << std::get<0>(key) << ' ' << std::get<1>(key) << ' ' << std::get<2>(key) << ' ' << std::get<3>(key) << ' '
-      << std::get<4>(key) << ' ' << std::get<5>(key) << ' ' << ts.ry << ' ' << ts.cz << '\n';
+      << std::get<4>(key) << ' ' << std::get<5>(key) << ' ' << ts.ry << ' ' << ts.cz << ' ' << ts.order << ' '
+      << ts.pair << '\n';
 }
 
 template <typename T> aar_status autotune(aar_solver_t *S, int idx)
@@ -756,43 +769,49 @@ template <typename T> aar_status autotune(aar_solver_t *S, int idx)
     a.out = P.xb;
     float best_ms = 1e30f;
     TileShape best = P.ts;
-    const int rys[] = {1, 2, 4};
-    const int czs[] = {2, 4, 8, 16, 32, 64};
-    aar_status result = AAR_OK;
-    for (int ry : rys) {
+    // candidates: rows per thread x z depth (skipping depths that give the
+    // same grid as a smaller one) x order bits (none when there is one chunk)
+    std::vector<TileShape> cands;
+    for (int ry : {1, 2, 4}) {
         int prev_tz = -1;
-        for (int cz : czs) {
-            TileShape ts{ry, cz};
+        for (int cz : {2, 4, 8, 16, 32, 64}) {
             int tx, ty, tz, blocks;
-            stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], ts, &tx, &ty, &tz, &blocks);
+            stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], TileShape{ry, cz, 0}, &tx, &ty, &tz, &blocks);
             if (tz == prev_tz)
-                continue;      // same grid as a smaller depth
+                continue;
             prev_tz = tz;
-            hipError_t e = hipSuccess;
-            for (int w = 0; w < 3 && e == hipSuccess; ++w)
-                e = Launch<T>::stencil(kSweep, P, a, s, ts);
-            if (e == hipSuccess)
-                e = hipEventRecord(e0, s);
-            for (int w = 0; w < 10 && e == hipSuccess; ++w)
-                e = Launch<T>::stencil(kSweep, P, a, s, ts);
-            if (e == hipSuccess)
-                e = hipEventRecord(e1, s);
-            if (e == hipSuccess)
-                e = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (e == hipSuccess)
-                e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) {
-                result = fail(AAR_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
-                break;
-            }
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = ts;
+            for (int order = 0; order < (tz > 1 ? 4 : 1); ++order) {
+                cands.push_back(TileShape{ry, cz, order, 0});
+                if (ry <= 2 && paired_layout(TileShape{ry, cz, order, 1}, op.prob.n[0], op.prob.velocity != nullptr,
+                                             kSweep))
+                    cands.push_back(TileShape{ry, cz, order, 1});
             }
         }
-        if (result != AAR_OK)
+    }
+    aar_status result = AAR_OK;
+    for (const TileShape &ts : cands) {
+        hipError_t e = hipSuccess;
+        for (int w = 0; w < 3 && e == hipSuccess; ++w)
+            e = Launch<T>::stencil(kSweep, P, a, s, ts);
+        if (e == hipSuccess)
+            e = hipEventRecord(e0, s);
+        for (int w = 0; w < 10 && e == hipSuccess; ++w)
+            e = Launch<T>::stencil(kSweep, P, a, s, ts);
+        if (e == hipSuccess)
+            e = hipEventRecord(e1, s);
+        if (e == hipSuccess)
+            e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            result = fail(AAR_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
             break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = ts;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

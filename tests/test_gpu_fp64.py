@@ -198,3 +198,67 @@ def test_repeat_solves_are_bitwise_identical():
     for it, xv in outs[1:]:
         assert it == outs[0][0]
         np.testing.assert_array_equal(xv, outs[0][1])
+
+
+ORDER_CASES = [
+    # (name, problem, (rows per thread, z depth, order bits, paired)); grids are
+    # distinct so each gets its own tile-file line
+    ("r3_zperiodic_order0", inputs.Problem(n=(70, 37, 45), h=(0.02, 0.03, 0.025), bc=(0, 0, 1), radius=3), (2, 8, 0, 0)),
+    ("r3_zperiodic_altz", inputs.Problem(n=(70, 37, 46), h=(0.02, 0.03, 0.025), bc=(0, 0, 1), radius=3), (2, 8, 1, 0)),
+    ("r3_zperiodic_zfast", inputs.Problem(n=(70, 37, 47), h=(0.02, 0.03, 0.025), bc=(0, 0, 1), radius=3), (2, 8, 2, 0)),
+    ("r3_zperiodic_both", inputs.Problem(n=(70, 37, 43), h=(0.02, 0.03, 0.025), bc=(0, 0, 1), radius=3), (2, 8, 3, 0)),
+    ("r6_dirichlet_altz", inputs.Problem(n=(65, 30, 41), h=(0.02, 0.03, 0.025), bc=(0, 0, 0), radius=6), (2, 8, 1, 0)),
+    ("upwind_altz", cd_problem((66, 35, 29)), (2, 8, 1, 0)),
+    ("upwind_both", cd_problem((66, 35, 31)), (2, 8, 3, 0)),
+    # paired layout (even n0, no convection): odd and even radii, ragged y and
+    # z tails, periodic x narrower than the 64-wide tile, both z directions
+    ("pair_r3_ry1", inputs.Problem(n=(70, 37, 44), h=(0.02, 0.03, 0.025), bc=(0, 0, 1), radius=3), (1, 8, 0, 1)),
+    ("pair_r6_ry2_dirichlet", inputs.Problem(n=(66, 30, 41), h=(0.02, 0.03, 0.025), bc=(0, 0, 0), radius=6),
+     (2, 8, 1, 1)),
+    ("pair_r1_dirichlet", inputs.Problem(n=(34, 20, 19), h=(0.03, 0.05, 0.05), bc=(0, 0, 0), radius=1), (1, 4, 0, 1)),
+    ("pair_r4_periodic_narrow", inputs.Problem(n=(26, 25, 27), h=(1 / 26, 1 / 25, 1 / 27), bc=(1, 1, 1), radius=4,
+                                               shift=0.5), (2, 8, 3, 1)),
+    ("pair_r5_mixed_bc", inputs.Problem(n=(128, 19, 29), h=(0.01, 0.05, 0.04), bc=(1, 0, 1), radius=5, diffusion=0.7),
+     (1, 16, 1, 1)),
+    ("pair_r2_zfast", inputs.Problem(n=(96, 41, 23), h=(0.01, 0.03, 0.04), bc=(0, 1, 0), radius=2, shift=0.2),
+     (2, 4, 2, 1)),
+    # an odd n0 with the paired flag falls back to the one-point layout
+    ("pair_flag_odd_n0", inputs.Problem(n=(67, 29, 33), h=(1 / 67, 1 / 29, 1 / 33), bc=(1, 1, 1), radius=6),
+     (1, 8, 0, 1)),
+]
+
+
+@pytest.mark.parametrize("name,prob,shape", ORDER_CASES, ids=[c[0] for c in ORDER_CASES])
+def test_tile_order_bits_match_oracle(name, prob, shape, tmp_path, monkeypatch):
+    """Every tile layout choice read from a tile file (rows per thread, z
+    depth, tile numbering and z direction, paired layout) gives the oracle's
+    operator and iterates, on grids whose z extent splits into an odd number
+    of chunks with a short last one."""
+    conv = 1 if prob.velocity is not None else 0
+    ry, cz, order, pair = shape
+    tile = tmp_path / "tiles.txt"
+    tile.write_text(f"0 {prob.radius} {conv} {prob.n[0]} {prob.n[1]} {prob.n[2]} {ry} {cz} {order} {pair}\n"
+                    f"1 {prob.radius} {conv} {prob.n[0]} {prob.n[1]} {prob.n[2]} {ry} {cz} {order} {pair}\n")
+    monkeypatch.setenv("AAR_TUNE_CACHE", str(tile))
+    say(f"tile shape {shape} {name} n={prob.n}")
+    x = inputs.normal(17, 0, prob.size)
+    s = aar.Solver([prob], params())
+    y = s.apply(to_dev(x)).cpu().numpy()
+    s.close()
+    ref = oracle.apply(prob, x)
+    scale = np.abs(oracle.diagonal(prob)).max() * np.abs(x).max()
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-13 * scale)
+    b = inputs.normal(5, 0, prob.size)
+    for K in (5, 7, 13):
+        prm = params(max_iter=K, tol=1e-30, m=7, p=6)
+        xs, res, _ = gpu_solve(prob, prm, b)
+        refx = oracle.aar_solve(prob, b, m=7, p=6, tol=1e-30, max_iter=K)["x"]
+        np.testing.assert_allclose(xs, refx, rtol=0, atol=1e-10 * np.abs(refx).max(), err_msg=f"K={K}")
+    if conv == 0 and prob.shift > 0:
+        # the FP32 sweeps of the mixed path and the FP32 history of the FP64
+        # path, with the same layout, reach the FP64 tolerance
+        for prec in (aar.AAR_MIXED_FP32, aar.AAR_FP64_FP32HIST):
+            prm = params(tol=1e-10, precision=prec)
+            xm, res, _ = gpu_solve(prob, prm, b)
+            assert res["status"] == aar.AAR_OK, (prec, res)
+            assert oracle.relative_residual(prob, b, xm) < 1e-10
