@@ -136,7 +136,21 @@ __global__ __launch_bounds__(kThreads) void k_gram(const GramArgs a)
 #pragma unroll
                 for (int t = 0; t <= MC; ++t)
                     col[t] = (double)Hist<H>::load(cur[t].v, u);
-                accumulate(col);
+                // l == MC: f_k is the last column and every difference is live
+                double d[MC];
+#pragma unroll
+                for (int c = 0; c < MC; ++c)
+                    d[c] = col[c + 1] - col[c];
+                int e = 0;
+#pragma unroll
+                for (int c = 0; c < MC; ++c) {
+#pragma unroll
+                    for (int c2 = c; c2 < MC; ++c2)
+                        acc[e++] += d[c] * d[c2];
+                }
+#pragma unroll
+                for (int c = 0; c < MC; ++c)
+                    acc[NP + c] += d[c] * col[MC];
             }
 #pragma unroll
             for (int t = 0; t <= MC; ++t)
@@ -172,12 +186,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(const GramArgs a)
     }
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int e = 0; e < NE; ++e) {
-        const double v = wave_sum_a(acc[e]);
-        if (lane == 0)
-            red[wave][e] = v;
-    }
+    wave_sums_to<NE>(acc, red[wave]);   // red[wave][e]: this wave's total of entry e
     __syncthreads();
     // transposed partial table: entry-major, one column per workgroup
     for (int e = threadIdx.x; e < NE; e += blockDim.x) {
@@ -317,9 +326,8 @@ hipError_t launch_gram_finish(const double *partial, int blocks, double *out, in
 __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
 {
     InstState *st = a.state;
-    if (st->status != kRunning)
-        return;
     // residual norm: thread-strided partials, fixed-order wave sum, broadcast
+    // (read before the run state is checked, so both loads overlap)
     double r = 0.0;
     for (int i = threadIdx.x; i < a.rho_blocks; i += kLsqThreads)
         r += a.rho_partial[i];

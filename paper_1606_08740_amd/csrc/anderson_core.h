@@ -17,6 +17,49 @@ template <typename T> __device__ inline T wave_sum_a(T v)
     return v;
 }
 
+// Wave sums of E (<= 64) values held by every lane, transposed: lane l
+// returns the sum over the wave of entry l (0 for l >= E).  Each of the six
+// butterfly rounds halves the entries a lane carries: the lane keeps the half
+// selected by its bit o and adds the partner's copy of that half, so the
+// rounds exchange 32 + 16 + ... + 1 = 63 values instead of 6 E.
+template <int E> __device__ inline double wave_transpose_sum(const double (&v)[E])
+{
+    static_assert(E <= 64, "at most one entry per lane");
+    double a[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i)
+        a[i] = i < E ? v[i] : 0.0;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const bool hi = (lane & o) != 0;
+#pragma unroll
+        for (int i = 0; i < o; ++i) {
+            const double keep = hi ? a[i + o] : a[i];
+            const double send = hi ? a[i] : a[i + o];
+            a[i] = keep + __shfl_xor(send, o, 64);
+        }
+    }
+    return a[0];
+}
+
+// Wave totals of E per-lane values written to dst[0 .. E) (lane e mod 64
+// writes entry e), 64 entries per transposed reduction.
+template <int E, int B = 0> __device__ inline void wave_sums_to(const double (&v)[E], double *dst)
+{
+    constexpr int C = E - B < 64 ? E - B : 64;
+    double part[C];
+#pragma unroll
+    for (int i = 0; i < C; ++i)
+        part[i] = v[B + i];
+    const double t = wave_transpose_sum<C>(part);
+    const int lane = threadIdx.x & 63;
+    if (lane < C)
+        dst[B + lane] = t;
+    if constexpr (B + 64 < E)
+        wave_sums_to<E, B + 64>(v, dst);
+}
+
 // V consecutive elements moved by one 16-byte (8-byte for bf16) access.
 template <typename E, int V> struct alignas(sizeof(E) * V) Pack {
     E v[V];
@@ -84,13 +127,28 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
     __shared__ int sh_stop;
     __shared__ int sh_fail;
 
-    if (st->status != kRunning)
-        return;
     const int tid = threadIdx.x;
-    const int64_t k = st->cycle * a.p + a.p - 1;
-    if (k >= st->max_iter) {
+    // Every input is read up front, before the first branch, so the kernel
+    // waits for one memory round trip: the Gram entries (one to nine per
+    // lane) and the run state.
+    constexpr int kNeMax = kMaxM * (kMaxM + 1) / 2 + kMaxM;
+    constexpr int kPer = (kNeMax + kLsqThreads - 1) / kLsqThreads;
+    double gv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = tid + u * kLsqThreads;
+        gv[u] = e < a.ne ? gram_vals[e] : 0.0;
+    }
+    const int status0 = st->status;
+    const int64_t cycle0 = st->cycle, max_iter0 = st->max_iter;
+    const double nb0 = st->nb, tol0 = st->tol, best_r0 = st->best_r;
+    const int log_count0 = st->log_count, since_best0 = st->since_best;
+    if (status0 != kRunning)
+        return;
+    const int64_t k = cycle0 * a.p + a.p - 1;
+    if (k >= max_iter0) {
         if (tid == 0) {
-            st->iters = st->max_iter;
+            st->iters = max_iter0;
             st->status = kMaxIter;
         }
         return;
@@ -99,8 +157,12 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
     const int np = a.m * (a.m + 1) / 2;
 
     // G (upper triangle, row-major over the m x m layout) and c
-    for (int e = tid; e < a.ne; e += kLsqThreads) {
-        const double v = gram_vals[e];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = tid + u * kLsqThreads;
+        if (e >= a.ne)
+            continue;
+        const double v = gv[u];
         if (e < np) {
             int row = 0, rem = e;
             while (rem >= a.m - row) {
@@ -118,12 +180,12 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
     }
     __syncthreads();
 
-    const double rel = sqrt(rho2) / st->nb;
+    const double rel = sqrt(rho2) / nb0;
     if (tid == 0) {
         st->last_r = rel;
-        if (a.log && st->log_count < a.log_cap)
-            a.log[st->log_count] = rel;
-        st->log_count += 1;
+        if (a.log && log_count0 < a.log_cap)
+            a.log[log_count0] = rel;
+        st->log_count = log_count0 + 1;
     }
     bool bad = !isfinite(rel);
     for (int i = 0; i < l && !bad; ++i) {
@@ -131,7 +193,7 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
         for (int j = 0; j < l && !bad; ++j)
             bad = !isfinite(S[i][j]);
     }
-    if (bad || rel < st->tol) {
+    if (bad || rel < tol0) {
         if (tid == 0) {
             st->iters = k + 1;
             st->status = bad ? kBreakdown : kConverged;
@@ -142,13 +204,13 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
         // inner solves of the refinement stop when the best residual has not
         // fallen by the given factor over the last `window` Anderson steps
         if (tid == 0) {
-            if (rel < a.stagnation_factor * st->best_r) {
+            int since = since_best0 + 1;
+            if (rel < a.stagnation_factor * best_r0) {
                 st->best_r = rel;
-                st->since_best = 0;
-            } else {
-                st->since_best += 1;
+                since = 0;
             }
-            sh_stop = st->since_best >= a.stagnation_window;
+            st->since_best = since;
+            sh_stop = since >= a.stagnation_window;
         }
         __syncthreads();
         if (sh_stop) {
@@ -364,15 +426,16 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
         }
         st->rank = rank;
         int nd = 0;
+        const int slot0 = (int)((k - l) % a.nslots);     // ring slot of column 0
+        const int pos0 = (int)((k - l + 1) % a.p);       // (j + 1) mod p of column 0
         for (int t = 0; t <= l; ++t) {
             const double gprev = t >= 1 ? gam[t - 1] : 0.0;
             const double gcur = t < l ? gam[t] : 0.0;
             double al = (t == l ? a.beta : 0.0) - a.beta * (gprev - gcur);
             if (t < l) {
-                const int64_t j = k - l + t;
-                const bool anderson = ((j + 1) % a.p) == 0;
+                const bool anderson = (pos0 + t) % a.p == 0;
                 if (anderson && a.q > 0) {
-                    const int64_t cyc = (j + 1) / a.p - 1;
+                    const int64_t cyc = (k - l + t + 1) / a.p - 1;
                     st->dslot[nd] = (int)(cyc % a.q);
                     st->delta[nd] = -gcur;
                     ++nd;
@@ -381,12 +444,12 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
                 }
             }
             st->alpha[t] = al;
-            st->fslot[t] = (int)((k - l + t) % a.nslots);
+            st->fslot[t] = (slot0 + t) % a.nslots;
         }
         st->nf = l + 1;
         st->nd = nd;
-        st->wslot = a.q > 0 ? (int)(st->cycle % a.q) : -1;
-        st->cycle = st->cycle + 1;
+        st->wslot = a.q > 0 ? (int)(cycle0 % a.q) : -1;
+        st->cycle = cycle0 + 1;
     }
 }
 

@@ -141,12 +141,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_batched(const BatchGramArgs a
             gram_point<MC>(col, l, acc);
         }
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-        for (int e = 0; e < NE; ++e) {
-            const double v = wave_sum_a(acc[e]);
-            if (lane == 0)
-                red[wave][e] = v;
-        }
+        wave_sums_to<NE>(acc, red[wave]);   // red[wave][e]: this wave's total of entry e
         __syncthreads();
         for (int e = threadIdx.x; e < NE; e += blockDim.x)
             a.partial[(int64_t)w * NE + e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
