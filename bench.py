@@ -8,12 +8,15 @@ HBM.  Default workload: periodic Poisson, 192^3 grid, 12th-order central
 differences (37-point stencil), 64 Gaussian charges minus their mean,
 Jacobi preconditioner, omega = beta = 0.6, m = 7, p = 6, tol 1e-10, FP64.
 The same grid is also solved in mixed precision (FP32 iteration inside FP64
-refinement) and reported beside it with the speedup over FP64.
+refinement) and as FP64 with an FP32 history ring, each reported beside it
+with the speedup over FP64, and the batched workload (512 shifted Helmholtz
+systems in one call) runs in FP64 and mixed precision.
 
 Prints one JSON line.  `roofline` covers the dominant kernel (the fused
 Richardson sweep): algorithmic bytes per launch (read x and b, write x and
 f: 4 values per grid point) over the mean launch time measured with HIP
-events on the solver's stream.  `cpu_baseline` times the CPU oracle on a
+events on the solver's stream, against the 8 TB/s HBM peak and against a
+measured 1 GiB device copy.  `cpu_baseline` times the CPU oracle on a
 bounded number of iterations of the same system and scales to solves/s with
 the oracle's own iteration count.
 """
@@ -36,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_full_size.json")
 # HBM traffic of the sweep kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
 # scaled by a plain copy's counters; valid while the kernel source is unchanged.
-SWEEP_PROFILE = os.path.join(ROOT, "profiles", "k_stencil_sweep_fp64_r6_192.md")
+SWEEP_PROFILE = os.path.join(ROOT, "profiles", "k_stencil2_sweep_fp64_r6_192.md")
 STENCIL_SRC = os.path.join(ROOT, "paper_1606_08740_amd", "csrc", "stencil.hip")
 
 
@@ -64,14 +67,34 @@ def parse():
     ap.add_argument("--n", type=int, default=192)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=24)
+    ap.add_argument("--cpu-sample-iters", type=int, default=180)
     ap.add_argument("--kernel-timing-solves", type=int, default=1)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-count", type=int, default=512)
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the batched part (for profiling it); prints its JSON object")
     return ap.parse_args()
+
+
+def measured_copy_gbs():
+    """Device-to-device copy of 1 GiB of random doubles (no cache reuse between
+    repetitions): the bandwidth a plain streaming kernel reaches on this GPU."""
+    import torch
+    src = torch.rand(1 << 27, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 5 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
 
 
 def copy_calibration():
@@ -102,6 +125,46 @@ def timed_solves(solver, bt, steps, warmup):
     return dt, res, xs[-1]
 
 
+def run_batched(args):
+    """The batched workload: 512 shifted periodic Helmholtz systems of uneven
+    sizes solved by one aar_solve_batched call, FP64 and mixed precision."""
+    import numpy as np
+    import torch
+
+    from paper_1606_08740_amd import aar, inputs
+    wb = inputs.workload(5, count=args.batched_count)
+    bb = torch.as_tensor(np.concatenate(wb.b), device="cuda:0")
+    res_out = {"workload": f"{args.batched_count} periodic shifted Helmholtz systems, 8th-order "
+                           "central FD (25-point), n ~ U{16..96}, sigma ~ U(0,10), b ~ N(0,1), "
+                           "exact constant-mode deflation, tol 1e-10",
+               "points": int(sum(p.size for p in wb.problems))}
+    for label, prec in [("fp64", aar.AAR_FP64), ("mixed_fp32", aar.AAR_MIXED_FP32)]:
+        pb = inputs.Params(**{**wb.params.__dict__})
+        pb.precision = prec
+        sb = aar.Solver(wb.problems, pb)
+        res = None
+        for _ in range(max(args.warmup, 1)):
+            xb = torch.zeros_like(bb)
+            res = sb.solve_batched(bb, xb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batched_steps):
+            xb = torch.zeros_like(bb)
+            res = sb.solve_batched(bb, xb)
+        torch.cuda.synchronize()
+        dtb = (time.perf_counter() - t0) / args.batched_steps
+        sb.close()
+        its = [r["iterations"] for r in res]
+        res_out[label] = {"value": args.batched_count / dtb, "unit": "solves/s",
+                          "ms_per_call": dtb * 1e3,
+                          "converged": int(sum(r["status"] == 0 for r in res)),
+                          "iterations_total": int(sum(its)), "iterations_max": int(max(its)),
+                          "max_rel_residual": float(max(r["rel_residual"] for r in res))}
+    res_out["mixed_speedup_vs_fp64"] = res_out["mixed_fp32"]["value"] / res_out["fp64"]["value"]
+    del bb
+    return res_out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -116,6 +179,9 @@ def main():
     from paper_1606_08740_amd import aar, inputs
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.batched_only:
+        print(json.dumps(run_batched(args)))
+        return
     w = inputs.workload(2, n=args.n)
     prob, b = w.problems[0], w.b[0]
     N = prob.size
@@ -126,7 +192,8 @@ def main():
     prm.precision = aar.AAR_FP64
     s64 = aar.Solver([prob], prm)
     dt64, r64, x64 = timed_solves(s64, bt, args.steps, args.warmup)
-    # kernel timing pass: HIP events around every sweep launch on the solver's stream
+    # kernel timing pass: one HIP event pair around each cycle's p - 1 consecutive
+    # sweep launches, on the solver's stream
     s64.set_timing(True)
     for _ in range(args.kernel_timing_solves):
         xt = torch.zeros_like(bt)
@@ -160,60 +227,34 @@ def main():
         "status": r64["status"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic(args.n),
-                     "kernel": "k_stencil<double,double,6,false,kSweep> (fused Richardson sweep)",
+                     "kernel": "k_stencil2 (fused Richardson sweep, paired-point layout), FP64, radius 6",
                      "bytes_per_launch": sweep_bytes, "mean_launch_us": sweep_us, "launches": launches},
     }
+    copy_gbs = measured_copy_gbs()
+    out["roofline"]["measured_copy_GBs"] = copy_gbs
+    out["roofline"]["frac_of_measured_copy"] = achieved / copy_gbs
 
-    # ---- mixed precision on the same system ----
+    # ---- other precisions on the same system ----
     if not args.no_mixed:
-        pm = inputs.Params(**{**prm.__dict__})
-        pm.precision = aar.AAR_MIXED_FP32
-        sm = aar.Solver([prob], pm)
-        dtm, rm, xm = timed_solves(sm, bt, args.steps, args.warmup)
-        sm.close()
         xa = x64.cpu().numpy()
-        xb = xm.cpu().numpy()
         xa -= xa.mean()
-        xb -= xb.mean()
-        out["mixed_fp32"] = {"value": args.steps / dtm, "unit": "solves/s", "ms_per_step": dtm / args.steps * 1e3,
-                             "iterations": rm["iterations"], "outer_steps": rm["outer_steps"],
-                             "rel_residual": rm["rel_residual"], "status": rm["status"],
-                             "speedup_vs_fp64": dt64 / dtm,
-                             "rel_diff_vs_fp64_gpu": float(np.linalg.norm(xa - xb) / np.linalg.norm(xa))}
+        for label, prec in [("mixed_fp32", aar.AAR_MIXED_FP32), ("fp64_fp32hist", aar.AAR_FP64_FP32HIST)]:
+            pm = inputs.Params(**{**prm.__dict__})
+            pm.precision = prec
+            sm = aar.Solver([prob], pm)
+            dtm, rm, xm = timed_solves(sm, bt, args.steps, args.warmup)
+            sm.close()
+            xb = xm.cpu().numpy()
+            xb -= xb.mean()
+            out[label] = {"value": args.steps / dtm, "unit": "solves/s", "ms_per_step": dtm / args.steps * 1e3,
+                          "iterations": rm["iterations"], "outer_steps": rm["outer_steps"],
+                          "rel_residual": rm["rel_residual"], "status": rm["status"],
+                          "speedup_vs_fp64": dt64 / dtm,
+                          "rel_diff_vs_fp64_gpu": float(np.linalg.norm(xa - xb) / np.linalg.norm(xa))}
 
     # ---- batched: 512 shifted periodic Helmholtz systems, one call ----
     if not args.no_batched:
-        wb = inputs.workload(5, count=args.batched_count)
-        bb = torch.as_tensor(np.concatenate(wb.b), device="cuda:0")
-        out["batched"] = {"workload": f"{args.batched_count} periodic shifted Helmholtz systems, 8th-order "
-                                      "central FD (25-point), n ~ U{16..96}, sigma ~ U(0,10), b ~ N(0,1), "
-                                      "exact constant-mode deflation, tol 1e-10",
-                          "points": int(sum(p.size for p in wb.problems))}
-        for label, prec in [("fp64", aar.AAR_FP64), ("mixed_fp32", aar.AAR_MIXED_FP32)]:
-            pb = inputs.Params(**{**wb.params.__dict__})
-            pb.precision = prec
-            sb = aar.Solver(wb.problems, pb)
-            res = None
-            for _ in range(max(args.warmup, 1)):
-                xb = torch.zeros_like(bb)
-                res = sb.solve_batched(bb, xb)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.batched_steps):
-                xb = torch.zeros_like(bb)
-                res = sb.solve_batched(bb, xb)
-            torch.cuda.synchronize()
-            dtb = (time.perf_counter() - t0) / args.batched_steps
-            sb.close()
-            its = [r["iterations"] for r in res]
-            out["batched"][label] = {"value": args.batched_count / dtb, "unit": "solves/s",
-                                     "ms_per_call": dtb * 1e3,
-                                     "converged": int(sum(r["status"] == 0 for r in res)),
-                                     "iterations_total": int(sum(its)), "iterations_max": int(max(its)),
-                                     "max_rel_residual": float(max(r["rel_residual"] for r in res))}
-        out["batched"]["mixed_speedup_vs_fp64"] = (out["batched"]["mixed_fp32"]["value"] /
-                                                   out["batched"]["fp64"]["value"])
-        del bb
+        out["batched"] = run_batched(args)
 
     # ---- CPU oracle baseline (bounded sample) ----
     if not args.no_cpu_baseline:

@@ -160,10 +160,11 @@ aar_status aar_destroy(aar_solver s);
 /* Description of the last error on this thread ("" if none). */
 const char *aar_last_error(void);
 
-/* Kernel timing for measurement: when enabled, the solver brackets every
- * Richardson sweep launch with HIP events on its stream (graphs are not used
- * while enabled) and accumulates their durations.  aar_sweep_time returns
- * the total milliseconds and launch count since the last reset. */
+/* Kernel timing for measurement: when enabled, the solver brackets each
+ * cycle's p - 1 consecutive Richardson sweep launches with one pair of HIP
+ * events on its stream (graphs are not used while enabled) and accumulates
+ * their durations.  aar_sweep_time returns the total milliseconds and the
+ * number of sweep launches timed since the last reset. */
 aar_status aar_set_timing(aar_solver s, int32_t enable);
 aar_status aar_sweep_time(aar_solver s, double *total_ms, int64_t *launches);
 

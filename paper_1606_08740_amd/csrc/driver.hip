@@ -462,7 +462,8 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
         a.j = j;
         a.x = (j & 1) ? P.xb : P.xa;
         a.out = (j & 1) ? P.xa : P.xb;
-        if (S->timing) {
+        // timing: one event pair around the cycle's p - 1 back-to-back sweeps
+        if (S->timing && j == 0) {
             if (S->tused + 2 > S->tev.size()) {
                 for (int t = 0; t < 64; ++t) {
                     hipEvent_t ev;
@@ -476,10 +477,10 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
         }
         if ((e = Launch<T>::stencil(kSweep, P, a, s)) != hipSuccess)
             return e;
-        if (S->timing) {
+        if (S->timing && j == pa.p - 2) {
             if ((e = hipEventRecord(S->tev[S->tused + 1], s)) != hipSuccess)
                 return e;
-            S->tcycle.push_back(cycle_tag * pa.p + j);
+            S->tcycle.push_back(cycle_tag * pa.p + j);   // the group's last sweep
             S->tused += 2;
         }
     }
@@ -608,11 +609,11 @@ aar_status run_cycles(aar_solver_t *S, const Path<T> &P, int64_t max_iter, bool 
                                    : out->iters - 1;
         for (size_t t = 0; t < S->tcycle.size(); ++t) {
             if (S->tcycle[t] > last_k)
-                continue;
+                continue;      // a group that stopped early (or never ran)
             float ms = 0.0f;
             AAR_HIP(hipEventElapsedTime(&ms, S->tev[2 * t], S->tev[2 * t + 1]));
             S->t_total_ms += ms;
-            S->t_launches += 1;
+            S->t_launches += S->params.p - 1;
         }
         S->tcycle.clear();
         S->tused = 0;
