@@ -127,7 +127,8 @@ def timed_solves(solver, bt, steps, warmup):
 
 def run_batched(args):
     """The batched workload: 512 shifted periodic Helmholtz systems of uneven
-    sizes solved by one aar_solve_batched call, FP64 and mixed precision."""
+    sizes solved by one aar_solve_batched call: FP64, mixed precision, and
+    FP64 with an FP32 history ring."""
     import numpy as np
     import torch
 
@@ -138,7 +139,8 @@ def run_batched(args):
                            "central FD (25-point), n ~ U{16..96}, sigma ~ U(0,10), b ~ N(0,1), "
                            "exact constant-mode deflation, tol 1e-10",
                "points": int(sum(p.size for p in wb.problems))}
-    for label, prec in [("fp64", aar.AAR_FP64), ("mixed_fp32", aar.AAR_MIXED_FP32)]:
+    for label, prec in [("fp64", aar.AAR_FP64), ("mixed_fp32", aar.AAR_MIXED_FP32),
+                        ("fp64_fp32hist", aar.AAR_FP64_FP32HIST)]:
         pb = inputs.Params(**{**wb.params.__dict__})
         pb.precision = prec
         sb = aar.Solver(wb.problems, pb)
@@ -161,6 +163,7 @@ def run_batched(args):
                           "iterations_total": int(sum(its)), "iterations_max": int(max(its)),
                           "max_rel_residual": float(max(r["rel_residual"] for r in res))}
     res_out["mixed_speedup_vs_fp64"] = res_out["mixed_fp32"]["value"] / res_out["fp64"]["value"]
+    res_out["fp64_fp32hist_speedup_vs_fp64"] = res_out["fp64_fp32hist"]["value"] / res_out["fp64"]["value"]
     del bb
     return res_out
 

@@ -385,8 +385,8 @@ hipError_t launch_stencil_f32(int mode, Prec hist, int radius, bool conv, const 
                               StencilArgs<float> a, int *blocks_out, hipStream_t s);
 void stencil_grid(int n0, int n1, int n2, const TileShape &ts, int *tx, int *ty, int *tz, int *blocks,
                   bool paired = false);
-hipError_t launch_stencil_batched_f64(int mode, int radius, bool conv, int ry, const BatchStencilArgs<double> &a,
-                                      int grid, hipStream_t s);
+hipError_t launch_stencil_batched_f64(int mode, Prec hist, int radius, bool conv, int ry,
+                                      const BatchStencilArgs<double> &a, int grid, hipStream_t s);
 hipError_t launch_stencil_batched_f32(int mode, Prec hist, int radius, bool conv, int ry,
                                       const BatchStencilArgs<float> &a, int grid, hipStream_t s);
 

@@ -347,10 +347,23 @@ __global__ __launch_bounds__(kThreads) void k_update_batched(const BatchUpdateAr
 hipError_t launch_update_batched(Prec prec, const BatchUpdateArgs<double> *a64, const BatchUpdateArgs<float> *a32,
                                  int grid, hipStream_t s)
 {
+    if (a64) {   // FP64 iterate; the history is FP64, FP32 or bfloat16
+        switch (prec) {
+        case Prec::F64:
+            hipLaunchKernelGGL((k_update_batched<double, double>), dim3(grid), dim3(kThreads), 0, s, *a64);
+            break;
+        case Prec::F32:
+            hipLaunchKernelGGL((k_update_batched<double, float>), dim3(grid), dim3(kThreads), 0, s, *a64);
+            break;
+        case Prec::F32_BF16:
+            hipLaunchKernelGGL((k_update_batched<double, bf16_t>), dim3(grid), dim3(kThreads), 0, s, *a64);
+            break;
+        }
+        return hipGetLastError();
+    }
     switch (prec) {
     case Prec::F64:
-        hipLaunchKernelGGL((k_update_batched<double, double>), dim3(grid), dim3(kThreads), 0, s, *a64);
-        break;
+        return hipErrorInvalidValue;
     case Prec::F32:
         hipLaunchKernelGGL((k_update_batched<float, float>), dim3(grid), dim3(kThreads), 0, s, *a32);
         break;

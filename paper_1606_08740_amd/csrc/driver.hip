@@ -243,6 +243,7 @@ struct aar_solver_t {
         int *c_sb = nullptr, *c_cb = nullptr, *a_sb = nullptr, *a_cb = nullptr;
         double *p_rho = nullptr, *p_gram = nullptr, *p_s = nullptr, *p_c = nullptr;
         double *xa64 = nullptr, *xb64 = nullptr, *b64 = nullptr, *r64 = nullptr, *dx64 = nullptr;
+        double *fcur64 = nullptr;   // FP64 f_k when an FP64 iteration keeps a narrow history
         float *xa32 = nullptr, *xb32 = nullptr, *rhs32 = nullptr, *fcur32 = nullptr, *dx32 = nullptr;
         void *fring = nullptr;
         double *log = nullptr;
@@ -1016,7 +1017,7 @@ constexpr int kBatchGrid = 8192;
 // batches are solved one system after another.
 bool batch_eligible(const aar_problem *probs, int count, const aar_params *pa)
 {
-    if (count < 2 || pa->m > kFastGramM || pa->precision > AAR_MIXED_FP32_BF16HIST)
+    if (count < 2 || pa->m > kFastGramM)
         return false;
     for (int i = 1; i < count; ++i) {
         if (probs[i].radius != probs[0].radius || (probs[i].velocity != nullptr) != (probs[0].velocity != nullptr))
@@ -1055,9 +1056,10 @@ size_t batch_bytes(const aar_problem *probs, int count, const aar_params *pa)
     }
     const int slots = pa->m + 1, q = pa->m / pa->p, ne = pa->m * (pa->m + 1) / 2 + pa->m;
     size_t b = 0;
-    if (pa->precision == AAR_FP64)
-        b += 8 * (size_t)total * (3 + slots + q);
-    else
+    if (!is_mixed(pa->precision)) {
+        const Prec h = hist_of(pa->precision);
+        b += (size_t)total * (8 * (3 + q) + hist_bytes(h) * slots + (h != Prec::F64 ? 8 : 0));
+    } else
         b += (size_t)total * (4 * (3 + q) + hist_bytes(pa->precision == AAR_MIXED_FP32 ? Prec::F32 : Prec::F32_BF16) * slots +
                               8 * 3 + (pa->precision == AAR_MIXED_FP32_BF16HIST ? 4 : 0));
     b += sizeof(double) * (size_t)(2 * tiles + chunks * (ne + 1));
@@ -1136,7 +1138,13 @@ aar_status batch_setup(aar_solver_t *S)
         B.xa64 = S->alloc<double>(total, &st);
         B.xb64 = S->alloc<double>(total, &st);
         B.b64 = S->alloc<double>(total, &st);
-        B.fring = S->alloc<double>((size_t)total * slots, &st);
+        if (S->hist == Prec::F64) {
+            B.fring = S->alloc<double>((size_t)total * slots, &st);
+        } else {
+            B.fring = S->hist == Prec::F32 ? (void *)S->alloc<float>((size_t)total * slots, &st)
+                                           : (void *)S->alloc<bf16_t>((size_t)total * slots, &st);
+            B.fcur64 = S->alloc<double>(total, &st);
+        }
         B.dx64 = S->q > 0 ? S->alloc<double>((size_t)total * S->q, &st) : nullptr;
     } else {
         B.xa64 = S->alloc<double>(total, &st);      // x in FP64 (refinement)
@@ -1251,6 +1259,7 @@ template <typename T> hipError_t batch_enqueue_cycle(aar_solver_t *S, hipStream_
         xb = B.xb64;
         b = B.b64;
         dx = B.dx64;
+        fcur = B.fcur64;
     } else {
         xa = B.xa32;
         xb = B.xb32;
@@ -1274,13 +1283,13 @@ template <typename T> hipError_t batch_enqueue_cycle(aar_solver_t *S, hipStream_
     a.nslots = pa.m + 1;
     a.omega = (T)pa.omega;
     hipError_t e;
-    const Prec hist = f64 ? Prec::F64 : S->hist;
+    const Prec hist = S->hist;   // history storage of this path (F64 for the plain FP64 solve)
     for (int j = 0; j < pa.p - 1; ++j) {
         a.j = j;
         a.x = (j & 1) ? xb : xa;
         a.out = (j & 1) ? xa : xb;
         if constexpr (std::is_same<T, double>::value)
-            e = launch_stencil_batched_f64(kSweep, B.radius, B.conv, B.ry, a, B.grid_s, s);
+            e = launch_stencil_batched_f64(kSweep, hist, B.radius, B.conv, B.ry, a, B.grid_s, s);
         else
             e = launch_stencil_batched_f32(kSweep, hist, B.radius, B.conv, B.ry, a, B.grid_s, s);
         if (e != hipSuccess)
@@ -1294,7 +1303,7 @@ template <typename T> hipError_t batch_enqueue_cycle(aar_solver_t *S, hipStream_
     a.fcur = fcur;
     a.partial = B.p_rho;
     if constexpr (std::is_same<T, double>::value)
-        e = launch_stencil_batched_f64(kFk, B.radius, B.conv, B.ry, a, B.grid_s, s);
+        e = launch_stencil_batched_f64(kFk, hist, B.radius, B.conv, B.ry, a, B.grid_s, s);
     else
         e = launch_stencil_batched_f32(kFk, hist, B.radius, B.conv, B.ry, a, B.grid_s, s);
     if (e != hipSuccess)
@@ -1382,7 +1391,7 @@ aar_status batch_residual(aar_solver_t *S, double *x, const double *b, double *r
     a.partial = B.p_s;
     a.mask = B.refine;
     a.slot_stride = B.stride;
-    AAR_HIPE(launch_stencil_batched_f64(kResid, B.radius, B.conv, B.ry, a, B.grid_s, S->stream));
+    AAR_HIPE(launch_stencil_batched_f64(kResid, Prec::F64, B.radius, B.conv, B.ry, a, B.grid_s, S->stream));
     return AAR_OK;
 }
 

@@ -744,9 +744,15 @@ static hipError_t launch_batched_radius(int radius, bool conv, int ry, const Bat
 #undef AAR_BATCH_RY
 }
 
-hipError_t launch_stencil_batched_f64(int mode, int radius, bool conv, int ry, const BatchStencilArgs<double> &a,
-                                      int grid, hipStream_t s)
+hipError_t launch_stencil_batched_f64(int mode, Prec hist, int radius, bool conv, int ry,
+                                      const BatchStencilArgs<double> &a, int grid, hipStream_t s)
 {
+    if (hist == Prec::F32 && (mode == kSweep || mode == kFk))
+        return mode == kSweep ? launch_batched_radius<double, float, kSweep>(radius, conv, ry, a, grid, s)
+                              : launch_batched_radius<double, float, kFk>(radius, conv, ry, a, grid, s);
+    if (hist == Prec::F32_BF16 && (mode == kSweep || mode == kFk))
+        return mode == kSweep ? launch_batched_radius<double, bf16_t, kSweep>(radius, conv, ry, a, grid, s)
+                              : launch_batched_radius<double, bf16_t, kFk>(radius, conv, ry, a, grid, s);
     switch (mode) {
     case kSweep:
         return launch_batched_radius<double, double, kSweep>(radius, conv, ry, a, grid, s);

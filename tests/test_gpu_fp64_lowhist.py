@@ -70,14 +70,16 @@ def test_lowhist_first_cycle_close_to_fp64():
     assert logs[aar.AAR_FP64][0] == pytest.approx(logs[aar.AAR_FP64_BF16HIST][0], rel=5e-2)
 
 
-def test_lowhist_not_batched_engine_but_correct():
-    """Several systems in one call with a low-precision history run one after
-    another; each answer is checked with the oracle's operator."""
+@pytest.mark.parametrize("precision", [aar.AAR_FP64_FP32HIST, aar.AAR_FP64_BF16HIST], ids=["fp32hist", "bf16hist"])
+def test_lowhist_batched_engine(precision):
+    """Several systems of uneven sizes and shifts in one call run on the
+    batched engine with the narrow history; each answer is checked with the
+    oracle's operator and against the same system solved alone."""
     import torch
-    probs = [inputs.periodic_problem(n, 4, shift=s) for n, s in [(20, 1.0), (27, 3.0), (33, 0.5)]]
+    probs = [inputs.periodic_problem(n, 4, shift=s) for n, s in [(20, 1.0), (27, 3.0), (33, 0.5), (16, 7.0)]]
     bs = [inputs.normal(30 + i, 0, p.size) for i, p in enumerate(probs)]
-    prm = params(tol=1e-10, precision=aar.AAR_FP64_FP32HIST)
-    say("lowhist multi-system call")
+    prm = params(tol=1e-10, precision=precision, flags=aar.AAR_FLAG_DEFLATE_CONSTANT)
+    say(f"lowhist batched engine precision {precision}")
     s = aar.Solver(probs, prm)
     bt = torch.as_tensor(np.concatenate(bs), device="cuda:0")
     xt = torch.zeros_like(bt)
@@ -87,5 +89,9 @@ def test_lowhist_not_batched_engine_but_correct():
     x = xt.cpu().numpy()
     off = np.concatenate([[0], np.cumsum([p.size for p in probs])])
     for i, p in enumerate(probs):
-        assert res[i]["status"] == aar.AAR_OK
-        assert oracle.relative_residual(p, bs[i], x[off[i]:off[i + 1]]) < prm.tol
+        assert res[i]["status"] == aar.AAR_OK, (i, res[i])
+        xi = x[off[i]:off[i + 1]]
+        assert oracle.relative_residual(p, bs[i], xi) < prm.tol
+        xs, rs, _ = gpu_solve(p, prm, bs[i])
+        assert rs["status"] == aar.AAR_OK
+        assert rel_err(xi, xs) < 1e-7

@@ -74,7 +74,7 @@ def test_full_size_batch_of_512():
     import torch
     w = inputs.workload(5)
     b = to_dev(np.concatenate(w.b))
-    for prec in [aar.AAR_FP64, aar.AAR_MIXED_FP32]:
+    for prec in [aar.AAR_FP64, aar.AAR_MIXED_FP32, aar.AAR_FP64_FP32HIST]:
         prm = inputs.Params(**{**w.params.__dict__})
         prm.precision = prec
         say(f"batch of 512 precision={prec}")
