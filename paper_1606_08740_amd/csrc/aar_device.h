@@ -366,7 +366,7 @@ struct TileShape {
     int ry;      // y rows per thread (tile height = kWY * ry; 2 kWY * ry paired)
     int cz;      // z planes per workgroup
     int order = 0;   // kOrder* bits
-    int pair = 0;    // 1: paired layout for the sweep and residual passes
+    int pair = 0;    // paired layout for the sweep and residual passes: 1 (4 waves), 2 (8 waves)
 };
 
 // The paired layout (each thread owns two x-adjacent points, loaded and
@@ -409,6 +409,8 @@ hipError_t launch_correct(double *x, const float *d, const double *scale, int64_
 hipError_t launch_copy_f64(const double *in, double *out, int64_t N, hipStream_t s);
 hipError_t launch_cast_f64_f32_plain(const double *in, float *out, int64_t N, hipStream_t s);
 hipError_t launch_zero_f64(double *v, int64_t N, hipStream_t s);
+hipError_t launch_fill_pattern_f64(double *v, int64_t N, hipStream_t s);
+hipError_t launch_fill_pattern_f32(float *v, int64_t N, hipStream_t s);
 // constant-mode deflation: mean of r -> scal[2]; x += mean * inv_sigma; r -= mean; partial ||r||^2
 hipError_t launch_deflate(double *x, double *r, int64_t N, double inv_sigma, double *partial, int blocks,
                           double *scal, hipStream_t s);

@@ -662,7 +662,8 @@ template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool 
 // cache is seeded from a tile file (AAR_TUNE_CACHE, else tuned_tiles.txt next
 // to this library: lines "prec radius conv n0 n1 n2 rows_per_thread z_depth
 // [order [pair]]", prec 0 = FP64, 1 = FP32, order the kOrder* bits, pair 1
-// for the paired layout, both default 0), so tuned shapes are reproducible;
+// (2) for the paired layout with 256 (512) threads per workgroup, both
+// default 0), so tuned shapes are reproducible;
 // with
 // AAR_TUNE_CACHE_WRITE set, new results are appended to that file.
 std::mutex g_tune_mutex;
@@ -702,8 +703,8 @@ void load_tune_file()
             order = 0;
         if (!(in >> pair))
             pair = 0;
-        if ((ry != 1 && ry != 2 && ry != 4) || cz < 1 || order < 0 || order > 3 || pair < 0 || pair > 1 ||
-            (pair && ry > 2))
+        if ((ry != 1 && ry != 2 && ry != 4) || cz < 1 || order < 0 || order > 3 || pair < 0 || pair > 2 ||
+            (pair == 1 && ry > 2) || (pair == 2 && ry != 1))
             continue;
         g_tune_cache[std::make_tuple(prec, radius, conv, n0, n1, n2)] = TileShape{ry, cz, order, pair};
     }
@@ -744,11 +745,11 @@ template <typename T> aar_status autotune(aar_solver_t *S, int idx)
     hipStream_t s = S->stream;
     const int64_t N = op.N;
     if constexpr (std::is_same<T, double>::value) {
-        AAR_HIP(launch_zero_f64(P.xa, N, s));
-        AAR_HIP(launch_zero_f64(P.b, N, s));
+        AAR_HIP(launch_fill_pattern_f64(P.xa, N, s));
+        AAR_HIP(launch_fill_pattern_f64(P.b, N, s));
     } else {
-        AAR_HIP(launch_zero_f32(P.xa, N, s));
-        AAR_HIP(launch_zero_f32(P.b, N, s));
+        AAR_HIP(launch_fill_pattern_f32(P.xa, N, s));
+        AAR_HIP(launch_fill_pattern_f32(P.b, N, s));
     }
     const int nb_blocks = stream_blocks(N);
     AAR_HIP(launch_norm_partial(f64, P.b, N, S->part_norm, nb_blocks, s));
@@ -776,7 +777,7 @@ template <typename T> aar_status autotune(aar_solver_t *S, int idx)
     std::vector<TileShape> cands;
     for (int ry : {1, 2, 4}) {
         int prev_tz = -1;
-        for (int cz : {2, 4, 8, 16, 32, 64}) {
+        for (int cz : {2, 4, 6, 8, 12, 16, 20, 24, 28, 32, 40, 48, 64}) {
             int tx, ty, tz, blocks;
             stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], TileShape{ry, cz, 0}, &tx, &ty, &tz, &blocks);
             if (tz == prev_tz)
@@ -784,9 +785,11 @@ template <typename T> aar_status autotune(aar_solver_t *S, int idx)
             prev_tz = tz;
             for (int order = 0; order < (tz > 1 ? 4 : 1); ++order) {
                 cands.push_back(TileShape{ry, cz, order, 0});
-                if (ry <= 2 && paired_layout(TileShape{ry, cz, order, 1}, op.prob.n[0], op.prob.velocity != nullptr,
-                                             kSweep))
+                const bool conv = op.prob.velocity != nullptr;
+                if (ry <= 2 && paired_layout(TileShape{ry, cz, order, 1}, op.prob.n[0], conv, kSweep))
                     cands.push_back(TileShape{ry, cz, order, 1});
+                if (ry == 1 && paired_layout(TileShape{ry, cz, order, 2}, op.prob.n[0], conv, kSweep))
+                    cands.push_back(TileShape{ry, cz, order, 2});   // 512-thread workgroups
             }
         }
     }

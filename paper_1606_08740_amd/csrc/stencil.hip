@@ -348,20 +348,21 @@ template <> struct Pair<float> { using type = float2; };
 // column pair per row, shared by the RY rows.  This halves the LDS requests
 // per point of the one-point layout.  The z taps come from a register queue
 // per point, as there.
-template <typename T, typename H, int R, int MODE, int RY>
+template <typename T, typename H, int R, int MODE, int RY, int NW>
 __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, double *partial_out)
 {
     using V = typename Pair<T>::type;
-    constexpr int TY = 2 * kWY * RY;
+    constexpr int kThr = 64 * NW;            // NW waves: 2 NW lane rows of 32
+    constexpr int TY = 2 * NW * RY;
     constexpr int RP = R + (R & 1);          // x halo width rounded to even (LDS pair alignment)
     constexpr int LX = kTX + 2 * RP;
     constexpr int LY = TY + 2 * R;
     constexpr int kHaloRows = 2 * R * (kTX + 2 * R);
     constexpr int kHalo = kHaloRows + TY * 2 * R;
-    constexpr int NH = (kHalo + kThreads - 1) / kThreads;
+    constexpr int NH = (kHalo + kThr - 1) / kThr;
     constexpr int Q = 2 * R + 1;
     __shared__ __align__(16) T sh[LY][LX];
-    __shared__ double red[kWY];
+    __shared__ double red[NW];
 
     const StencilDev<T> &st = a.st;
     const InstState *s = a.state;
@@ -424,7 +425,7 @@ __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, 
     int hoff[NH], hlds[NH];
 #pragma unroll
     for (int j = 0; j < NH; ++j) {
-        const int h = tid + j * kThreads;
+        const int h = tid + j * kThr;
         hoff[j] = -1;
         hlds[j] = -1;
         if (h < kHalo) {
@@ -642,17 +643,17 @@ __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, 
         __syncthreads();
         if (tid == 0) {
             double sum = 0.0;
-            for (int w = 0; w < kWY; ++w)
+            for (int w = 0; w < NW; ++w)
                 sum += red[w];
             *partial_out = sum;
         }
     }
 }
 
-template <typename T, typename H, int R, int MODE, int RY>
-__global__ __launch_bounds__(kThreads) void k_stencil2(const StencilArgs<T> a)
+template <typename T, typename H, int R, int MODE, int RY, int NW>
+__global__ __launch_bounds__(64 * NW) void k_stencil2(const StencilArgs<T> a)
 {
-    stencil_tile2<T, H, R, MODE, RY>(a, xcd_tile(blockIdx.x, gridDim.x), a.partial + blockIdx.x);
+    stencil_tile2<T, H, R, MODE, RY, NW>(a, xcd_tile(blockIdx.x, gridDim.x), a.partial + blockIdx.x);
 }
 
 template <typename T, typename H, int R, bool CONV, int MODE, int RY>
@@ -783,7 +784,8 @@ hipError_t launch_stencil_batched_f32(int mode, Prec hist, int radius, bool conv
 
 void stencil_grid(int n0, int n1, int n2, const TileShape &ts, int *tx, int *ty, int *tz, int *blocks, bool paired)
 {
-    const int TY = (paired ? 2 * kWY : kWY) * ts.ry;
+    // paired layout: 2 lane rows per wave, 4 waves (pair 1) or 8 waves (pair 2)
+    const int TY = (paired ? 2 * kWY * ts.pair : kWY) * ts.ry;
     *tx = (n0 + kTX - 1) / kTX;
     *ty = (n1 + TY - 1) / TY;
     *tz = (n2 + ts.cz - 1) / ts.cz;
@@ -806,7 +808,7 @@ static hipError_t launch_one(StencilArgs<T> a, const TileShape &ts, int *blocks_
     return hipGetLastError();
 }
 
-template <typename T, typename H, int R, int MODE, int RY>
+template <typename T, typename H, int R, int MODE, int RY, int NW>
 static hipError_t launch_one2(StencilArgs<T> a, const TileShape &ts, int *blocks_out, hipStream_t s)
 {
     int tx, ty, tz, blocks;
@@ -818,7 +820,7 @@ static hipError_t launch_one2(StencilArgs<T> a, const TileShape &ts, int *blocks
     a.order = ts.order;
     if (blocks_out)
         *blocks_out = blocks;
-    hipLaunchKernelGGL((k_stencil2<T, H, R, MODE, RY>), dim3(blocks), dim3(kTX, kWY), 0, s, a);
+    hipLaunchKernelGGL((k_stencil2<T, H, R, MODE, RY, NW>), dim3(blocks), dim3(kTX, NW), 0, s, a);
     return hipGetLastError();
 }
 
@@ -826,11 +828,13 @@ template <typename T, typename H, int MODE>
 static hipError_t launch_paired(int radius, StencilArgs<T> a, const TileShape &ts, int *blocks_out, hipStream_t s)
 {
 #define AAR_PAIR_RY(R)                                                      \
-    switch (ts.ry) {                                                        \
-    case 1:                                                                 \
-        return launch_one2<T, H, R, MODE, 1>(a, ts, blocks_out, s);         \
-    case 2:                                                                 \
-        return launch_one2<T, H, R, MODE, 2>(a, ts, blocks_out, s);         \
+    switch (ts.ry + 4 * ts.pair) {                                          \
+    case 1 + 4:                                                             \
+        return launch_one2<T, H, R, MODE, 1, 4>(a, ts, blocks_out, s);      \
+    case 2 + 4:                                                             \
+        return launch_one2<T, H, R, MODE, 2, 4>(a, ts, blocks_out, s);      \
+    case 1 + 8:                                                             \
+        return launch_one2<T, H, R, MODE, 1, 8>(a, ts, blocks_out, s);      \
     default:                                                                \
         return hipErrorInvalidValue;                                        \
     }

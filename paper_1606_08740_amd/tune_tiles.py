@@ -36,7 +36,7 @@ def main(path):
     if os.path.exists(path):
         os.remove(path)
     with open(path, "w") as f:
-        f.write("# prec radius conv n0 n1 n2 rows_per_thread z_depth  (prec 0 = FP64, 1 = FP32)\n")
+        f.write("# prec radius conv n0 n1 n2 rows_per_thread z_depth order pair  (prec 0 = FP64, 1 = FP32)\n")
     from paper_1606_08740_amd import aar, inputs
     for prob in shapes():
         for precision in (aar.AAR_FP64, aar.AAR_MIXED_FP32):
