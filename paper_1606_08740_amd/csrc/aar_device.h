@@ -366,7 +366,7 @@ struct TileShape {
     int ry;      // y rows per thread (tile height = kWY * ry; 2 kWY * ry paired)
     int cz;      // z planes per workgroup
     int order = 0;   // kOrder* bits
-    int pair = 0;    // paired layout for the sweep and residual passes: 1 (4 waves), 2 (8 waves)
+    int pair = 0;    // paired layout for the sweep and residual passes: 1, 2, 3 = 4, 8, 16 waves
 };
 
 // The paired layout (each thread owns two x-adjacent points, loaded and
@@ -375,6 +375,25 @@ struct TileShape {
 inline bool paired_layout(const TileShape &ts, int n0, bool conv, int mode)
 {
     return ts.pair != 0 && (n0 % 2) == 0 && !conv && (mode == kSweep || mode == kFk);
+}
+
+// Paired shapes that are compiled: pair p uses 4 << (p - 1) waves per
+// workgroup; FP64 keeps at most 8 waves and 2 rows per thread (its register
+// queue would not fit more), FP32 also has 8 waves x 2 rows and 16 waves.
+inline bool paired_shape_ok(const TileShape &ts, bool f64)
+{
+    switch (ts.pair) {
+    case 0:
+        return true;
+    case 1:
+        return ts.ry == 1 || ts.ry == 2;
+    case 2:
+        return ts.ry == 1 || (!f64 && ts.ry == 2);
+    case 3:
+        return !f64 && ts.ry == 1;
+    default:
+        return false;
+    }
 }
 
 // Stencil pass; T is double for Prec::F64 and float otherwise; history type

@@ -661,8 +661,8 @@ template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool 
 // cached per (precision, radius, convection, grid) for the process.  The
 // cache is seeded from a tile file (AAR_TUNE_CACHE, else tuned_tiles.txt next
 // to this library: lines "prec radius conv n0 n1 n2 rows_per_thread z_depth
-// [order [pair]]", prec 0 = FP64, 1 = FP32, order the kOrder* bits, pair 1
-// (2) for the paired layout with 256 (512) threads per workgroup, both
+// [order [pair]]", prec 0 = FP64, 1 = FP32, order the kOrder* bits, pair 1,
+// 2, 3 for the paired layout with 256, 512, 1024 threads per workgroup, both
 // default 0), so tuned shapes are reproducible;
 // with
 // AAR_TUNE_CACHE_WRITE set, new results are appended to that file.
@@ -703,8 +703,8 @@ void load_tune_file()
             order = 0;
         if (!(in >> pair))
             pair = 0;
-        if ((ry != 1 && ry != 2 && ry != 4) || cz < 1 || order < 0 || order > 3 || pair < 0 || pair > 2 ||
-            (pair == 1 && ry > 2) || (pair == 2 && ry != 1))
+        if ((ry != 1 && ry != 2 && ry != 4) || cz < 1 || order < 0 || order > 3 ||
+            !paired_shape_ok(TileShape{ry, cz, order, pair}, prec == 0))
             continue;
         g_tune_cache[std::make_tuple(prec, radius, conv, n0, n1, n2)] = TileShape{ry, cz, order, pair};
     }
@@ -784,12 +784,12 @@ template <typename T> aar_status autotune(aar_solver_t *S, int idx)
                 continue;
             prev_tz = tz;
             for (int order = 0; order < (tz > 1 ? 4 : 1); ++order) {
-                cands.push_back(TileShape{ry, cz, order, 0});
                 const bool conv = op.prob.velocity != nullptr;
-                if (ry <= 2 && paired_layout(TileShape{ry, cz, order, 1}, op.prob.n[0], conv, kSweep))
-                    cands.push_back(TileShape{ry, cz, order, 1});
-                if (ry == 1 && paired_layout(TileShape{ry, cz, order, 2}, op.prob.n[0], conv, kSweep))
-                    cands.push_back(TileShape{ry, cz, order, 2});   // 512-thread workgroups
+                for (int pair = 0; pair <= 3; ++pair) {
+                    const TileShape ts{ry, cz, order, pair};
+                    if (paired_shape_ok(ts, f64) && (pair == 0 || paired_layout(ts, op.prob.n[0], conv, kSweep)))
+                        cands.push_back(ts);
+                }
             }
         }
     }

@@ -784,8 +784,8 @@ hipError_t launch_stencil_batched_f32(int mode, Prec hist, int radius, bool conv
 
 void stencil_grid(int n0, int n1, int n2, const TileShape &ts, int *tx, int *ty, int *tz, int *blocks, bool paired)
 {
-    // paired layout: 2 lane rows per wave, 4 waves (pair 1) or 8 waves (pair 2)
-    const int TY = (paired ? 2 * kWY * ts.pair : kWY) * ts.ry;
+    // paired layout: 2 lane rows per wave, 4 << (pair - 1) waves
+    const int TY = (paired ? 2 * (kWY << (ts.pair - 1)) : kWY) * ts.ry;
     *tx = (n0 + kTX - 1) / kTX;
     *ty = (n1 + TY - 1) / TY;
     *tz = (n2 + ts.cz - 1) / ts.cz;
@@ -827,6 +827,8 @@ static hipError_t launch_one2(StencilArgs<T> a, const TileShape &ts, int *blocks
 template <typename T, typename H, int MODE>
 static hipError_t launch_paired(int radius, StencilArgs<T> a, const TileShape &ts, int *blocks_out, hipStream_t s)
 {
+    if (!paired_shape_ok(ts, sizeof(T) == 8))
+        return hipErrorInvalidValue;
 #define AAR_PAIR_RY(R)                                                      \
     switch (ts.ry + 4 * ts.pair) {                                          \
     case 1 + 4:                                                             \
@@ -835,6 +837,14 @@ static hipError_t launch_paired(int radius, StencilArgs<T> a, const TileShape &t
         return launch_one2<T, H, R, MODE, 2, 4>(a, ts, blocks_out, s);      \
     case 1 + 8:                                                             \
         return launch_one2<T, H, R, MODE, 1, 8>(a, ts, blocks_out, s);      \
+    case 2 + 8:                                                             \
+        if constexpr (sizeof(T) == 4)                                       \
+            return launch_one2<T, H, R, MODE, 2, 8>(a, ts, blocks_out, s);  \
+        return hipErrorInvalidValue;                                        \
+    case 1 + 12:                                                            \
+        if constexpr (sizeof(T) == 4)                                       \
+            return launch_one2<T, H, R, MODE, 1, 16>(a, ts, blocks_out, s); \
+        return hipErrorInvalidValue;                                        \
     default:                                                                \
         return hipErrorInvalidValue;                                        \
     }

@@ -222,6 +222,14 @@ ORDER_CASES = [
      (1, 16, 1, 1)),
     ("pair_r2_zfast", inputs.Problem(n=(96, 41, 23), h=(0.01, 0.03, 0.04), bc=(0, 1, 0), radius=2, shift=0.2),
      (2, 4, 2, 1)),
+    # 512- and 1024-thread paired workgroups (the wider ones compile for FP32
+    # only: the FP64 line of such a shape is rejected and FP64 is autotuned)
+    ("pair8w_r6_ry1", inputs.Problem(n=(70, 37, 44), h=(0.02, 0.03, 0.025), bc=(0, 0, 1), radius=6, shift=0.3),
+     (1, 8, 1, 2)),
+    ("pair8w_fp32_ry2", inputs.Problem(n=(96, 45, 29), h=(0.01, 0.02, 0.03), bc=(1, 1, 1), radius=4, shift=2.0),
+     (2, 8, 0, 2)),
+    ("pair16w_fp32", inputs.Problem(n=(64, 70, 33), h=(0.015, 0.015, 0.03), bc=(0, 1, 0), radius=3, shift=1.0),
+     (1, 12, 3, 3)),
     # an odd n0 with the paired flag falls back to the one-point layout
     ("pair_flag_odd_n0", inputs.Problem(n=(67, 29, 33), h=(1 / 67, 1 / 29, 1 / 33), bc=(1, 1, 1), radius=6),
      (1, 8, 0, 1)),
