@@ -89,3 +89,27 @@ def test_full_size_batch_of_512():
         worst = max(oracle.relative_residual(p, bi, xs[offs[i]: offs[i + 1]])
                     for i, (p, bi) in enumerate(zip(w.problems, w.b)))
         assert worst < prm.tol
+
+
+def test_large_grid_512():
+    """A 512^3 Dirichlet Poisson system (134M points, 1 GiB per FP64 vector):
+    the solve reaches its tolerance and the residual the solver decided on is
+    the one the oracle's operator measures for the returned x."""
+    import torch
+    prob = inputs.dirichlet_poisson_problem(512)
+    b = inputs.normal(11, 0, prob.size)
+    prm = inputs.Params(tol=1e-6)
+    say("large grid 512^3 FP64")
+    s = aar.Solver([prob], prm)
+    bt = to_dev(b)
+    xt = torch.zeros_like(bt)
+    res = s.solve(bt, xt)
+    torch.cuda.synchronize()
+    s.close()
+    x = xt.cpu().numpy()
+    del xt, bt
+    assert res["status"] == aar.AAR_OK, res
+    assert res["iterations"] % prm.p == 0
+    rr = oracle.relative_residual(prob, b, x)
+    assert rr < prm.tol
+    assert rr == pytest.approx(res["rel_residual"], rel=1e-6)
