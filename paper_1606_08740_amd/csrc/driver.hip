@@ -1029,13 +1029,32 @@ bool batch_eligible(const aar_problem *probs, int count, const aar_params *pa)
     return true;
 }
 
-template <typename T> BatchDesc<T> batch_desc(const Operator &op, int64_t off, int ry, const T *vel)
+// Tile of the batched stencil passes (one-point layout): the tile file's
+// batch line (grid fields 0 0 0) for this precision, radius and convection,
+// else 4 rows per thread and z depth 16 (FP64 iterate) or 32 (FP32 iterate),
+// the fastest of rows {1, 2, 4} x depth {4, 8, 16, 32} on the 512-system
+// Helmholtz batch.
+TileShape batch_tile(const aar_params *pa, int radius, bool conv)
+{
+    const bool mixed = is_mixed(pa->precision);
+    TileShape ts{4, mixed ? 32 : 16, 0, 0};
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    load_tune_file();
+    const auto it = g_tune_cache.find(std::make_tuple(mixed ? 1 : 0, radius, conv ? 1 : 0, 0, 0, 0));
+    if (it != g_tune_cache.end()) {
+        ts.ry = it->second.ry;
+        ts.cz = it->second.cz;
+    }
+    return ts;
+}
+
+template <typename T> BatchDesc<T> batch_desc(const Operator &op, int64_t off, const TileShape &bt, const T *vel)
 {
     BatchDesc<T> d;
     std::memset(&d, 0, sizeof(d));
     d.st = make_stencil<T>(op, vel);
     d.off = off;
-    TileShape ts{ry, std::min(8, op.prob.n[2])};
+    TileShape ts{bt.ry, std::min(bt.cz, op.prob.n[2])};
     int tx, ty, tz, blocks;
     stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], ts, &tx, &ty, &tz, &blocks);
     d.tiles_x = tx;
@@ -1051,10 +1070,14 @@ size_t batch_bytes(const aar_problem *probs, int count, const aar_params *pa)
 {
     int64_t total = 0;
     int64_t tiles = 0, chunks = 0;
+    const TileShape bt = batch_tile(pa, probs[0].radius, probs[0].velocity != nullptr);
     for (int i = 0; i < count; ++i) {
         const int64_t N = (int64_t)probs[i].n[0] * probs[i].n[1] * probs[i].n[2];
         total += (N + 15) / 16 * 16;
-        tiles += (int64_t)((probs[i].n[0] + kTX - 1) / kTX) * ((probs[i].n[1] + 7) / 8) * ((probs[i].n[2] + 7) / 8);
+        int tx, ty, tz, blocks;
+        stencil_grid(probs[i].n[0], probs[i].n[1], probs[i].n[2], TileShape{bt.ry, std::min(bt.cz, probs[i].n[2])},
+                     &tx, &ty, &tz, &blocks);
+        tiles += blocks;
         chunks += (N + kChunk - 1) / kChunk;
     }
     const int slots = pa->m + 1, q = pa->m / pa->p, ne = pa->m * (pa->m + 1) / 2 + pa->m;
@@ -1081,7 +1104,8 @@ aar_status batch_setup(aar_solver_t *S)
     B.count = count;
     B.radius = S->ops[0].prob.radius;
     B.conv = S->ops[0].prob.velocity != nullptr;
-    B.ry = B.radius <= 2 ? 4 : 2;
+    const TileShape bt = batch_tile(&pa, B.radius, B.conv);
+    B.ry = bt.ry;
     B.offs.resize(count);
     B.sizes.resize(count);
     B.ntiles.resize(count);
@@ -1095,8 +1119,8 @@ aar_status batch_setup(aar_solver_t *S)
         B.offs[i] = total;
         B.sizes[i] = op.N;
         total += (op.N + 15) / 16 * 16;
-        d64[i] = batch_desc<double>(op, B.offs[i], B.ry, op.vel64);
-        d32[i] = batch_desc<float>(op, B.offs[i], B.ry, op.vel32);
+        d64[i] = batch_desc<double>(op, B.offs[i], bt, op.vel64);
+        d32[i] = batch_desc<float>(op, B.offs[i], bt, op.vel32);
         B.ntiles[i] = d64[i].ntiles;
         B.nchunks[i] = d64[i].nchunks;
         B.sum_tiles += B.ntiles[i];

@@ -6,7 +6,12 @@ AAR_TUNE_CACHE_WRITE at the output, so every shape is timed afresh and its
 choice appended.  The library reads tuned_tiles.txt next to itself at
 creation, so committing the output makes tile choices reproducible.
 
-Usage: python -m paper_1606_08740_amd.tune_tiles [output path]
+The batched engine uses one tile shape for all systems of a batch; with
+--batched the shape is chosen by timing whole batched solves of the 512-system
+Helmholtz workload for rows per thread {1, 2, 4} x z depth {4, 8, 16, 32}, and
+the winner is appended as a batch line (grid fields 0 0 0).
+
+Usage: python -m paper_1606_08740_amd.tune_tiles [--batched] [output path]
 """
 import os
 import sys
@@ -48,5 +53,50 @@ def main(path):
     print(open(path).read())
 
 
+def tune_batched(path):
+    import time
+
+    import numpy as np
+    import torch
+
+    from paper_1606_08740_amd import aar, inputs
+    wb = inputs.workload(5)
+    bb = torch.as_tensor(np.concatenate(wb.b), device="cuda:0")
+    radius = wb.problems[0].radius
+    lines = []
+    for precision in (aar.AAR_FP64, aar.AAR_MIXED_FP32):
+        prec = 0 if precision == aar.AAR_FP64 else 1
+        best = None
+        for ry in (1, 2, 4):
+            for cz in (4, 8, 16, 32):
+                tile = tempfile.NamedTemporaryFile("w", suffix=".txt", delete=False)
+                tile.write(f"{prec} {radius} 0 0 0 0 {ry} {cz} 0 0\n")
+                tile.close()
+                os.environ["AAR_TUNE_CACHE"] = tile.name
+                pb = inputs.Params(**{**wb.params.__dict__})
+                pb.precision = precision
+                s = aar.Solver(wb.problems, pb)
+                s.solve_batched(bb, torch.zeros_like(bb))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s.solve_batched(bb, torch.zeros_like(bb))
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                s.close()
+                os.remove(tile.name)
+                print(f"batched precision={precision} rows={ry} depth={cz}: {dt * 1e3:.1f} ms", flush=True)
+                if best is None or dt < best[0]:
+                    best = (dt, ry, cz)
+        lines.append(f"{prec} {radius} 0 0 0 0 {best[1]} {best[2]} 0 0\n")
+    with open(path, "a") as f:
+        f.writelines(lines)
+    print("".join(lines))
+
+
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else os.path.join(HERE, "tuned_tiles.txt"))
+    args = [a for a in sys.argv[1:] if a != "--batched"]
+    out = args[0] if args else os.path.join(HERE, "tuned_tiles.txt")
+    if "--batched" in sys.argv[1:]:
+        tune_batched(out)
+    else:
+        main(out)
