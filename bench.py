@@ -38,14 +38,23 @@ HBM_PEAK_GBS = 8000.0
 # tests/golden/make_golden.py (oracle only).
 GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_full_size.json")
 # HBM traffic of the sweep kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
-# scaled by a plain copy's counters; valid while the kernel source is unchanged.
+# scaled by a plain copy's counters; valid while the stencil sources are unchanged.
 SWEEP_PROFILE = os.path.join(ROOT, "profiles", "k_stencil2_sweep_fp64_r6_192.md")
-STENCIL_SRC = os.path.join(ROOT, "paper_1606_08740_amd", "csrc", "stencil.hip")
+STENCIL_SRCS = [os.path.join(ROOT, "paper_1606_08740_amd", "csrc", f)
+                for f in ("stencil_kernels.h", "stencil.hip", "stencil_narrow.hip", "stencil_f32.hip")]
+
+
+def stencil_sha():
+    """First 16 hex digits of the SHA-256 of the stencil sources, concatenated."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in STENCIL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def sweep_traffic(n):
     """Counter-measured bytes per sweep launch, or None when absent or stale."""
-    import hashlib
     import re
     if n != 192 or not os.path.exists(SWEEP_PROFILE):
         return None
@@ -53,8 +62,7 @@ def sweep_traffic(n):
     if not m:
         return None
     rec = json.loads(m.group(1))
-    sha = hashlib.sha256(open(STENCIL_SRC, "rb").read()).hexdigest()[:16]
-    if rec.get("stencil_source_sha256_16") != sha:
+    if rec.get("stencil_source_sha256_16") != stencil_sha():
         return None
     return rec.get("traffic_bytes_per_launch")
 

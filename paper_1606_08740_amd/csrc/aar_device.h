@@ -147,7 +147,13 @@ template <typename T> struct StencilArgs {
     int32_t tiles_x, tiles_y, tiles_z;
     int32_t order;          // kOrder* bits: tile numbering and z direction
     T omega;
+    double *gram_partial;   // kFk, paired layout, m = kFusedGramM: [ne][blocks] Gram partials, else null
 };
+
+// History length whose Gram products the paired Anderson-residual pass forms
+// itself (the evaluation workloads' m) when iterate and history are FP64;
+// other lengths and precisions use the separate Gram pass.
+constexpr int kFusedGramM = 7;
 
 // Batched systems: one descriptor per system; packed vectors hold system i
 // at element offset `off` (64-byte aligned) in every array.
@@ -402,10 +408,15 @@ hipError_t launch_stencil_f64(int mode, Prec hist, int radius, bool conv, const 
                               StencilArgs<double> a, int *blocks_out, hipStream_t s);
 hipError_t launch_stencil_f32(int mode, Prec hist, int radius, bool conv, const TileShape &ts,
                               StencilArgs<float> a, int *blocks_out, hipStream_t s);
+// FP64 iterate with an FP32 or bfloat16 history (kSweep, kFk)
+hipError_t launch_stencil_f64_narrow(int mode, Prec hist, int radius, bool conv, const TileShape &ts,
+                                     StencilArgs<double> a, int *blocks_out, hipStream_t s);
 void stencil_grid(int n0, int n1, int n2, const TileShape &ts, int *tx, int *ty, int *tz, int *blocks,
                   bool paired = false);
 hipError_t launch_stencil_batched_f64(int mode, Prec hist, int radius, bool conv, int ry,
                                       const BatchStencilArgs<double> &a, int grid, hipStream_t s);
+hipError_t launch_stencil_batched_f64_narrow(int mode, Prec hist, int radius, bool conv, int ry,
+                                             const BatchStencilArgs<double> &a, int grid, hipStream_t s);
 hipError_t launch_stencil_batched_f32(int mode, Prec hist, int radius, bool conv, int ry,
                                       const BatchStencilArgs<float> &a, int grid, hipStream_t s);
 

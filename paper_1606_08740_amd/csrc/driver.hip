@@ -134,6 +134,7 @@ template <typename T> struct Path {
     bool conv = false;
     int rho_blocks = 0, gram_blocks = 0, upd_blocks = 0;
     int64_t dx_stride = 0;     // elements between dx slots
+    bool gram_fused = false;   // the Anderson-residual pass forms the Gram products
 };
 
 size_t hist_bytes(Prec p)
@@ -399,7 +400,8 @@ Sizes compute_sizes(const aar_problem *probs, int count, const aar_params *pa)
     auto vec_span = [&](size_t esize) { return (((size_t)z.maxN * esize + 4095) / 4096) * 4096 + stagger; };
     size_t b = 0;
     b += sizeof(InstState) * (size_t)count;
-    b += sizeof(double) * ((size_t)z.max_stencil_blocks + (size_t)z.gram_blocks * z.ne + z.gram_blocks + z.ne + 8);
+    b += sizeof(double) * ((size_t)z.max_stencil_blocks + (size_t)std::max(z.gram_blocks, z.max_stencil_blocks) * z.ne +
+                           z.gram_blocks + z.ne + 8);
     if (!mixed) {
         b += vec_span(8) * (3 + z.q) + vec_span(hist_bytes(hist)) * slots + (hist != Prec::F64 ? vec_span(8) : 0);
         b += sizeof(double) * (size_t)vel_total;
@@ -492,6 +494,7 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
     a.out = nullptr;
     a.fcur = P.fcur;
     a.partial = S->part_rho;
+    a.gram_partial = P.gram_fused ? S->part_gram : nullptr;
     if ((e = Launch<T>::stencil(kFk, P, a, s)) != hipSuccess)
         return e;
 
@@ -505,10 +508,10 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
     g.p = pa.p;
     g.nslots = pa.m + 1;
     g.ne = S->ne;
-    if ((e = launch_gram(P.hist, g, P.gram_blocks, s)) != hipSuccess)
+    if (!P.gram_fused && (e = launch_gram(P.hist, g, P.gram_blocks, s)) != hipSuccess)
         return e;
-    if ((e = launch_gram_finish(S->part_gram, P.gram_blocks, S->gram_final, S->ne, S->state, pa.p, s)) !=
-        hipSuccess)
+    if ((e = launch_gram_finish(S->part_gram, P.gram_fused ? P.rho_blocks : P.gram_blocks, S->gram_final, S->ne,
+                                S->state, pa.p, s)) != hipSuccess)
         return e;
 
     LsqArgs l;
@@ -643,9 +646,10 @@ template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool 
     P.conv = op.prob.velocity != nullptr;
     P.ts = op.ts[f64 ? 0 : 1];
     int tx, ty, tz, blocks;
-    stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], P.ts, &tx, &ty, &tz, &blocks,
-                 paired_layout(P.ts, op.prob.n[0], P.conv, kFk));
+    const bool paired_fk = paired_layout(P.ts, op.prob.n[0], P.conv, kFk);
+    stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], P.ts, &tx, &ty, &tz, &blocks, paired_fk);
     P.rho_blocks = blocks;
+    P.gram_fused = paired_fk && S->params.m == kFusedGramM && P.ts.pair <= 2 && f64 && P.hist == Prec::F64;
     P.gram_blocks = gram_blocks(op.N, S->params.m);
     P.upd_blocks = stream_blocks(op.N);
     P.slot_stride = S->slot_stride[f64 ? 0 : 1];
@@ -1660,7 +1664,9 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
     S->state = S->alloc<InstState>(1, &st);
     S->part_rho = S->alloc<double>(z.max_stencil_blocks, &st);
     S->part_rho_cap = z.max_stencil_blocks;
-    S->part_gram = S->alloc<double>((size_t)z.gram_blocks * z.ne, &st);
+    // Gram partials: one column per Gram-pass workgroup, or per stencil
+    // workgroup when the Anderson-residual pass forms the products
+    S->part_gram = S->alloc<double>((size_t)std::max(z.gram_blocks, z.max_stencil_blocks) * z.ne, &st);
     S->part_norm = S->alloc<double>(z.gram_blocks, &st);
     S->gram_final = S->alloc<double>(z.ne, &st);
     S->scal = S->alloc<double>(8, &st);
