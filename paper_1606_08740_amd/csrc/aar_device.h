@@ -154,6 +154,7 @@ template <typename T> struct StencilArgs {
 // itself (the evaluation workloads' m) when iterate and history are FP64;
 // other lengths and precisions use the separate Gram pass.
 constexpr int kFusedGramM = 7;
+constexpr int kFusedGramNE = kFusedGramM * (kFusedGramM + 1) / 2 + kFusedGramM;
 
 // Batched systems: one descriptor per system; packed vectors hold system i
 // at element offset `off` (64-byte aligned) in every array.
@@ -326,6 +327,11 @@ struct LsqArgs {
     int32_t rho_blocks;
     const double *gram_final;    // G (upper triangle) and c, summed by k_gram_finish
     int32_t ne;
+    // non-null: the per-workgroup partials of the fused Gram pass (entry-major,
+    // gram_blocks per entry, kFusedGramNE entries), summed by the solve kernel
+    // itself in place of gram_final
+    const double *gram_partial = nullptr;
+    int32_t gram_blocks = 0;
     int32_t m, p, nslots, q;     // q: dx ring slots (0: none kept)
     double omega, beta;
     double rcond;                // pseudoinverse threshold factor (times l * lambda_max)

@@ -9,7 +9,8 @@
 //             stencil pass this is the single global reduction per Anderson
 //             step of Secs. 3.2-3.3.
 //   k_gram_finish  sums each entry's per-workgroup partials (fixed order).
-//   k_lsq     one wave: finishes the residual norm, tests convergence on
+//   k_lsq     one wave: finishes the residual norm (and, after the fused
+//             Gram pass, the Gram entries), tests convergence on
 //             ||b - A x_k|| / ||b|| (Sec. 2), solves gamma = (F^T F)^+ F^T f_k
 //             (Moore-Penrose pseudoinverse, Sec. 3.2) and writes the update
 //             as a linear combination of history slots.  The pseudoinverse
@@ -325,6 +326,7 @@ hipError_t launch_gram_finish(const double *partial, int blocks, double *out, in
 
 __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
 {
+    __shared__ double gsum[kFusedGramNE];
     InstState *st = a.state;
     // residual norm: thread-strided partials, fixed-order wave sum, broadcast
     // (read before the run state is checked, so both loads overlap)
@@ -332,7 +334,42 @@ __global__ __launch_bounds__(kLsqThreads) void k_lsq(const LsqArgs a)
     for (int i = threadIdx.x; i < a.rho_blocks; i += kLsqThreads)
         r += a.rho_partial[i];
     r = wave_sum_a(r);
-    lsq_core(a, st, __shfl(r, 0, 64), a.gram_final);
+    const double *gv = a.gram_final;
+    if (a.gram_partial) {
+        // Gram entries of the fused pass: lane-strided partial sums in a
+        // fixed order, then one transposed wave reduction into LDS.  Two
+        // workgroups per lane are loaded at once (70 loads in flight), so
+        // the table of a 256-workgroup pass takes two memory round trips;
+        // indices past the table are clamped and their values dropped.
+        constexpr int kBatch = 2;
+        const int nb = a.gram_blocks;
+        double acc[kFusedGramNE];
+#pragma unroll
+        for (int e = 0; e < kFusedGramNE; ++e)
+            acc[e] = 0.0;
+        for (int b0 = 0; b0 < nb; b0 += kBatch * kLsqThreads) {
+            double v[kBatch][kFusedGramNE];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int b = b0 + (int)threadIdx.x + u * kLsqThreads;
+                const int bc = b < nb ? b : nb - 1;
+#pragma unroll
+                for (int e = 0; e < kFusedGramNE; ++e)
+                    v[u][e] = a.gram_partial[(int64_t)e * nb + bc];
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const bool in = b0 + (int)threadIdx.x + u * kLsqThreads < nb;
+#pragma unroll
+                for (int e = 0; e < kFusedGramNE; ++e)
+                    acc[e] += in ? v[u][e] : 0.0;
+            }
+        }
+        wave_sums_to<kFusedGramNE>(acc, gsum);
+        __syncthreads();
+        gv = gsum;
+    }
+    lsq_core(a, st, __shfl(r, 0, 64), gv);
 }
 
 hipError_t launch_lsq(const LsqArgs &a, hipStream_t s)

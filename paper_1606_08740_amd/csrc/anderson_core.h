@@ -108,11 +108,24 @@ template <int MC> __device__ inline void gram_point(const double *col, int l, do
 }
 
 constexpr int kLsqThreads = 64;   // one wave: barriers are cheap
+constexpr int kRegM = 8;          // history lengths whose m x m solve runs in registers
+
+// Position of entry (i, j), i <= j, in the upper triangle of an m x m matrix
+// stored row by row.
+__device__ inline int tri_index(int i, int j, int m)
+{
+    return i * m - i * (i - 1) / 2 + (j - i);
+}
 
 // The least-squares step of one system: convergence test, gamma and the
 // update plan.  rho2 = ||b - A x_k||^2 and gram_vals (the m(m+1)/2 entries of
 // the upper triangle of F^T F, then F^T f_k) are already summed.  Run by one
 // wave; every early return is uniform across it.
+//
+// For m <= kRegM every lane holds the whole matrix and factors it in
+// registers (no LDS traffic, no barriers); larger m use LDS.  Either way the
+// Cholesky solve is taken only when it provably equals the pseudoinverse
+// solve, else the Jacobi eigendecomposition runs.
 __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, const double *gram_vals)
 {
     __shared__ double S[kMaxM][kMaxM + 1];
@@ -128,16 +141,31 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
     __shared__ int sh_fail;
 
     const int tid = threadIdx.x;
-    // Every input is read up front, before the first branch, so the kernel
-    // waits for one memory round trip: the Gram entries (one to nine per
-    // lane) and the run state.
+    const bool small = a.m <= kRegM;
+    const int np = a.m * (a.m + 1) / 2;
+    // Every input is read up front, before the first branch on the run
+    // state, so the kernel waits for one memory round trip: in registers the
+    // lower triangle of S and c (small m, every lane), else the Gram entries
+    // spread over the lanes (one to nine each), and the run state.
+    double R[kRegM][kRegM];
+    double cr[kRegM];
     constexpr int kNeMax = kMaxM * (kMaxM + 1) / 2 + kMaxM;
     constexpr int kPer = (kNeMax + kLsqThreads - 1) / kLsqThreads;
     double gv[kPer];
+    if (small) {
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int e = tid + u * kLsqThreads;
-        gv[u] = e < a.ne ? gram_vals[e] : 0.0;
+        for (int i = 0; i < kRegM; ++i) {
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                R[i][j] = i < a.m ? gram_vals[tri_index(j, i, a.m)] : 0.0;
+            cr[i] = i < a.m ? gram_vals[np + i] : 0.0;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + u * kLsqThreads;
+            gv[u] = e < a.ne ? gram_vals[e] : 0.0;
+        }
     }
     const int status0 = st->status;
     const int64_t cycle0 = st->cycle, max_iter0 = st->max_iter;
@@ -154,31 +182,6 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
         return;
     }
     const int l = (int)(k < a.m ? k : a.m);
-    const int np = a.m * (a.m + 1) / 2;
-
-    // G (upper triangle, row-major over the m x m layout) and c
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int e = tid + u * kLsqThreads;
-        if (e >= a.ne)
-            continue;
-        const double v = gv[u];
-        if (e < np) {
-            int row = 0, rem = e;
-            while (rem >= a.m - row) {
-                rem -= a.m - row;
-                ++row;
-            }
-            const int col = row + rem;
-            if (row < l && col < l) {
-                S[row][col] = v;
-                S[col][row] = v;
-            }
-        } else if (e - np < l) {
-            cvec[e - np] = v;
-        }
-    }
-    __syncthreads();
 
     const double rel = sqrt(rho2) / nb0;
     if (tid == 0) {
@@ -187,11 +190,44 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
             a.log[log_count0] = rel;
         st->log_count = log_count0 + 1;
     }
+    // breakdown: a NaN or Inf in the residual or in the l x l Gram system
     bool bad = !isfinite(rel);
-    for (int i = 0; i < l && !bad; ++i) {
-        bad = !isfinite(cvec[i]);
-        for (int j = 0; j < l && !bad; ++j)
-            bad = !isfinite(S[i][j]);
+    if (small) {
+#pragma unroll
+        for (int i = 0; i < kRegM; ++i) {
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                bad = bad || (i < l && !isfinite(R[i][j]));
+            bad = bad || (i < l && !isfinite(cr[i]));
+        }
+    } else {
+        // G (upper triangle, row-major over the m x m layout) and c into LDS
+        bool mine = false;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + u * kLsqThreads;
+            if (e >= a.ne)
+                continue;
+            const double v = gv[u];
+            if (e < np) {
+                int row = 0, rem = e;
+                while (rem >= a.m - row) {
+                    rem -= a.m - row;
+                    ++row;
+                }
+                const int col = row + rem;
+                if (row < l && col < l) {
+                    S[row][col] = v;
+                    S[col][row] = v;
+                    mine = mine || !isfinite(v);
+                }
+            } else if (e - np < l) {
+                cvec[e - np] = v;
+                mine = mine || !isfinite(v);
+            }
+        }
+        bad = bad || __any(mine);
+        __syncthreads();
     }
     if (bad || rel < tol0) {
         if (tid == 0) {
@@ -228,7 +264,81 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
     // gamma = L^-T L^-1 c.  The proof: lambda_min >= 1 / ||L^-1||_F^2 and
     // lambda_max <= trace(S).  Otherwise the eigendecomposition below runs.
     int fast = 0;
-    if (l > 0) {
+    double gr[kRegM];   // gamma of the register path (every lane)
+    if (small) {
+        // rows and columns l .. kRegM-1 become the identity, so the factor
+        // and its inverse are block diagonal and the padding adds nothing
+        double tr = 0.0;
+#pragma unroll
+        for (int i = 0; i < kRegM; ++i) {
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                R[i][j] = i < l ? R[i][j] : (i == j ? 1.0 : 0.0);
+            cr[i] = i < l ? cr[i] : 0.0;
+            tr += i < l ? R[i][i] : 0.0;
+        }
+        bool ok = true;
+        double id[kRegM];   // 1 / L_jj
+#pragma unroll
+        for (int j = 0; j < kRegM; ++j) {
+            const double piv = R[j][j];
+            ok = ok && piv > 0.0;
+            const double d = sqrt(piv);
+            R[j][j] = d;
+            id[j] = 1.0 / d;
+#pragma unroll
+            for (int i = j + 1; i < kRegM; ++i)
+                R[i][j] *= id[j];
+#pragma unroll
+            for (int i = j + 1; i < kRegM; ++i)
+#pragma unroll
+                for (int kk = j + 1; kk <= i; ++kk)
+                    R[i][kk] -= R[i][j] * R[kk][j];
+        }
+        // L^-1 column by column (forward substitution) and ||L^-1||_F^2
+        double Lr[kRegM][kRegM];
+        double fro = 0.0;
+#pragma unroll
+        for (int c = 0; c < kRegM; ++c)
+#pragma unroll
+            for (int i = c; i < kRegM; ++i) {
+                double acc = i == c ? 1.0 : 0.0;
+#pragma unroll
+                for (int kk = c; kk < i; ++kk)
+                    acc -= R[i][kk] * Lr[kk][c];
+                Lr[i][c] = acc * id[i];
+                fro += i < l ? Lr[i][c] * Lr[i][c] : 0.0;
+            }
+        fast = l > 0 && ok && (1.0 / fro > a.rcond * (double)l * tr) && fro == fro;
+        if (fast) {
+            double y[kRegM];   // y = L^-1 c, gamma = L^-T y
+#pragma unroll
+            for (int i = 0; i < kRegM; ++i) {
+                double v = 0.0;
+#pragma unroll
+                for (int kk = 0; kk <= i; ++kk)
+                    v += Lr[i][kk] * cr[kk];
+                y[i] = v;
+            }
+#pragma unroll
+            for (int i = 0; i < kRegM; ++i) {
+                double g = 0.0;
+#pragma unroll
+                for (int kk = i; kk < kRegM; ++kk)
+                    g += Lr[kk][i] * y[kk];
+                gr[i] = g;
+            }
+        } else {
+            // the Jacobi path works on S and c in LDS
+            for (int idx = tid; idx < l * l; idx += kLsqThreads) {
+                const int i = idx / l, j = idx % l;
+                S[i][j] = gram_vals[i <= j ? tri_index(i, j, a.m) : tri_index(j, i, a.m)];
+            }
+            for (int i = tid; i < l; i += kLsqThreads)
+                cvec[i] = gram_vals[np + i];
+            __syncthreads();
+        }
+    } else if (l > 0) {
         for (int i = tid; i < l * l; i += kLsqThreads)
             V[i / l][i % l] = S[i / l][i % l];
         if (tid == 0)
@@ -417,6 +527,41 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
     // x_{k+1} = x_k + beta f_k - sum_i gamma_i (dX_i + beta dF_i), column i
     // covering iteration j_i = k - l + i:  dF_i = f_{j_i+1} - f_{j_i},
     // dX_i = omega f_{j_i} (Richardson j_i) or the stored increment (Anderson j_i).
+    // Lane t writes the coefficient of history position t (t <= l).
+    const bool regs = small && fast;
+    const int t = tid;
+    double gcur = 0.0, gprev = 0.0;
+    if (regs) {
+#pragma unroll
+        for (int u = 0; u < kRegM; ++u) {
+            gcur = u == t ? gr[u] : gcur;
+            gprev = u + 1 == t ? gr[u] : gprev;
+        }
+    } else {
+        gcur = t < l ? gam[t] : 0.0;
+        gprev = t >= 1 && t <= l ? gam[t - 1] : 0.0;
+    }
+    // k + 1 is a multiple of p, so (j_0 + 1) mod p = (p - l) mod p, and an
+    // Anderson column i (j_i + 1 a multiple of p) belongs to the cycle
+    // (j_i + 1) / p - 1 = cycle0 - 1 + (p - l + i) / p, an exact division.
+    const int pos0 = ((a.p - l) % a.p + a.p) % a.p;
+    const int slot0 = (int)((k - l) % a.nslots);     // ring slot of column 0
+    const int cyc0 = a.q > 0 ? (int)(cycle0 % a.q) : 0;
+    const bool anderson = t < l && a.q > 0 && (pos0 + t) % a.p == 0;
+    double al = (t == l ? a.beta : 0.0) - a.beta * (gprev - gcur);
+    if (t < l && !anderson)
+        al -= a.omega * gcur;
+    const unsigned long long amask = __ballot(anderson);
+    if (anderson) {
+        const int nd = __popcll(amask & ((1ull << t) - 1ull));
+        const int c = cyc0 - 1 + (a.p - l + t) / a.p;   // (cycle mod q) up to a multiple of q
+        st->dslot[nd] = ((c % a.q) + a.q) % a.q;
+        st->delta[nd] = -gcur;
+    }
+    if (t <= l) {
+        st->alpha[t] = al;
+        st->fslot[t] = (slot0 + t) % a.nslots;
+    }
     if (tid == 0) {
         int rank = l;
         if (!fast) {
@@ -425,30 +570,9 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
                 rank += S[e][e] > sh_off;
         }
         st->rank = rank;
-        int nd = 0;
-        const int slot0 = (int)((k - l) % a.nslots);     // ring slot of column 0
-        const int pos0 = (int)((k - l + 1) % a.p);       // (j + 1) mod p of column 0
-        for (int t = 0; t <= l; ++t) {
-            const double gprev = t >= 1 ? gam[t - 1] : 0.0;
-            const double gcur = t < l ? gam[t] : 0.0;
-            double al = (t == l ? a.beta : 0.0) - a.beta * (gprev - gcur);
-            if (t < l) {
-                const bool anderson = (pos0 + t) % a.p == 0;
-                if (anderson && a.q > 0) {
-                    const int64_t cyc = (k - l + t + 1) / a.p - 1;
-                    st->dslot[nd] = (int)(cyc % a.q);
-                    st->delta[nd] = -gcur;
-                    ++nd;
-                } else {
-                    al -= a.omega * gcur;
-                }
-            }
-            st->alpha[t] = al;
-            st->fslot[t] = (slot0 + t) % a.nslots;
-        }
         st->nf = l + 1;
-        st->nd = nd;
-        st->wslot = a.q > 0 ? (int)(cycle0 % a.q) : -1;
+        st->nd = __popcll(amask);
+        st->wslot = a.q > 0 ? cyc0 : -1;
         st->cycle = cycle0 + 1;
     }
 }

@@ -510,8 +510,8 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
     g.ne = S->ne;
     if (!P.gram_fused && (e = launch_gram(P.hist, g, P.gram_blocks, s)) != hipSuccess)
         return e;
-    if ((e = launch_gram_finish(S->part_gram, P.gram_fused ? P.rho_blocks : P.gram_blocks, S->gram_final, S->ne,
-                                S->state, pa.p, s)) != hipSuccess)
+    if (!P.gram_fused && (e = launch_gram_finish(S->part_gram, P.gram_blocks, S->gram_final, S->ne, S->state, pa.p,
+                                                 s)) != hipSuccess)
         return e;
 
     LsqArgs l;
@@ -520,6 +520,10 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
     l.rho_blocks = P.rho_blocks;
     l.gram_final = S->gram_final;
     l.ne = S->ne;
+    // the fused pass leaves one partial per workgroup and entry; the solve
+    // kernel sums them itself
+    l.gram_partial = P.gram_fused ? S->part_gram : nullptr;
+    l.gram_blocks = P.gram_fused ? P.rho_blocks : 0;
     l.m = pa.m;
     l.p = pa.p;
     l.nslots = pa.m + 1;
