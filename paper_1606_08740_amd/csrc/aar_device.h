@@ -351,6 +351,9 @@ template <typename T> struct UpdateArgs {
     int64_t N;
     int64_t slot_stride;    // elements between f slots, a multiple of 8
     int64_t dx_stride;      // elements between dx slots, a multiple of 8
+    // non-null: pinned host word that workgroup 0 sets to the run status on
+    // entry, so the host polls it without a copy on the stream
+    int32_t *status_out = nullptr;
 };
 
 // Workgroup index -> logical tile index so that each XCD (and its L2) gets a

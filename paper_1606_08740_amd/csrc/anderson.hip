@@ -391,7 +391,10 @@ __global__ __launch_bounds__(kThreads) void k_update(const UpdateArgs<T> a)
     __shared__ T de[kMaxM];
     __shared__ int nf_s, nd_s, ws_s;
     const InstState *st = a.state;
-    if (st->status != kRunning)
+    const int status = st->status;
+    if (a.status_out && blockIdx.x == 0 && threadIdx.x == 0)
+        *a.status_out = status;
+    if (status != kRunning)
         return;
     const H *ring = reinterpret_cast<const H *>(a.fring);
     if (threadIdx.x == 0) {

@@ -208,7 +208,8 @@ struct aar_solver_t {
     int graph_instance = -1;
 
     // pinned status mailbox
-    int32_t *host_status = nullptr;
+    int32_t *host_status = nullptr;     // pinned: the run status written by the update kernels
+    int32_t *status_dev = nullptr;      // its device address
     hipEvent_t poll_ev[2] = {nullptr, nullptr};
 
     // sweep timing
@@ -548,6 +549,7 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
     u.N = P.N;
     u.slot_stride = P.slot_stride;
     u.dx_stride = P.dx_stride;
+    u.status_out = S->status_dev;
     if constexpr (std::is_same<T, double>::value)
         return launch_update(P.hist, &u, nullptr, P.upd_blocks, s);
     else
@@ -596,15 +598,15 @@ aar_status run_cycles(aar_solver_t *S, const Path<T> &P, int64_t max_iter, bool 
                     return fail(AAR_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
             }
         }
-        AAR_HIP(hipMemcpyAsync(&S->host_status[slot], &S->state->status, sizeof(int32_t),
-                               hipMemcpyDeviceToHost, s));
+        // every update kernel stores the run status into pinned host memory
+        // (the latest one to run wins; a status that left kRunning stays so)
         AAR_HIP(hipEventRecord(S->poll_ev[slot], s));
         slot ^= 1;
         ++inflight;
         if (inflight == 2) {
             AAR_HIP(hipEventSynchronize(S->poll_ev[slot]));
             --inflight;
-            if (S->host_status[slot] != kRunning)
+            if (*reinterpret_cast<volatile int32_t *>(S->host_status) != kRunning)
                 break;
         }
     }
@@ -1651,7 +1653,11 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
     S->hist = hist_of(params->precision);
     AAR_HIP(hipGetDevice(&S->device));
     AAR_HIP(hipStreamCreateWithFlags(&S->capture_stream, hipStreamNonBlocking));
-    AAR_HIP(hipHostMalloc((void **)&S->host_status, 2 * sizeof(int32_t), hipHostMallocDefault));
+    // coherent pinned memory: the update kernels' stores reach the host without caching
+    AAR_HIP(hipHostMalloc((void **)&S->host_status, 2 * sizeof(int32_t),
+                          hipHostMallocMapped | hipHostMallocCoherent));
+    S->host_status[0] = S->host_status[1] = kRunning;
+    AAR_HIP(hipHostGetDevicePointer((void **)&S->status_dev, S->host_status, 0));
     for (auto &e : S->poll_ev)
         AAR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 

@@ -63,6 +63,12 @@ ITER_CASES = [
     ("periodic_r4_p1", inputs.periodic_problem(24, 4, shift=2.0), dict(m=5, p=1)),
     ("dirichlet_p_gt_m", inputs.dirichlet_poisson_problem(17), dict(m=3, p=5)),
     ("long_history_m20", inputs.Problem(n=(70, 9, 11), h=(0.02, 0.1, 0.1), bc=(0, 0, 0), radius=1), dict(m=20, p=2)),
+    # the m x m solve runs in registers up to m = 8 and in LDS from m = 9
+    ("register_solve_m8", inputs.Problem(n=(30, 22, 17), h=(0.03, 0.04, 0.05), bc=(1, 0, 0), radius=2, shift=0.4),
+     dict(m=8, p=3)),
+    ("lds_solve_m9", inputs.Problem(n=(30, 22, 17), h=(0.03, 0.04, 0.05), bc=(1, 0, 0), radius=2, shift=0.4),
+     dict(m=9, p=3)),
+    ("single_column_m1", inputs.dirichlet_poisson_problem(19), dict(m=1, p=1)),
 ]
 
 
