@@ -84,6 +84,8 @@ def parse():
                     help="only run a plain 1 GiB device copy (scale for the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the batched part (for profiling it); prints its JSON object")
+    ap.add_argument("--precision-only", choices=["mixed_fp32", "fp64_fp32hist"],
+                    help="only time this precision mode on the headline system (for profiling it)")
     return ap.parse_args()
 
 
@@ -197,6 +199,17 @@ def main():
     prob, b = w.problems[0], w.b[0]
     N = prob.size
     bt = torch.as_tensor(b, device="cuda:0")
+    if args.precision_only:
+        pm = w.params
+        pm.precision = {"mixed_fp32": aar.AAR_MIXED_FP32, "fp64_fp32hist": aar.AAR_FP64_FP32HIST}[args.precision_only]
+        sm = aar.Solver([prob], pm)
+        dtm, rm, _ = timed_solves(sm, bt, args.steps, args.warmup)
+        sm.close()
+        print(json.dumps({"precision": args.precision_only, "value": args.steps / dtm, "unit": "solves/s",
+                          "ms_per_step": dtm / args.steps * 1e3, "iterations": rm["iterations"],
+                          "outer_steps": rm["outer_steps"], "rel_residual": rm["rel_residual"],
+                          "status": rm["status"]}))
+        return
 
     # ---- FP64 (headline) ----
     prm = w.params
