@@ -38,7 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # tests/golden/make_golden.py (oracle only).
 GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_full_size.json")
 # HBM traffic of the sweep kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
-# scaled by a plain copy's counters; valid while the stencil sources are unchanged.
+# scaled by a plain copy's counters; valid while the stencil sources and the
+# grid's tile shape are those it was measured with.
 SWEEP_PROFILE = os.path.join(ROOT, "profiles", "k_stencil2_sweep_fp64_r6_192.md")
 STENCIL_SRCS = [os.path.join(ROOT, "paper_1606_08740_amd", "csrc", f)
                 for f in ("stencil_kernels.h", "stencil.hip", "stencil_narrow.hip", "stencil_f32.hip")]
@@ -53,6 +54,21 @@ def stencil_sha():
     return h.hexdigest()[:16]
 
 
+def fp64_tile(n, radius=6):
+    """The FP64 tile shape the library reads for an n^3 grid (the tile file
+    named by AAR_TUNE_CACHE, else the one beside it), or None."""
+    path = os.environ.get("AAR_TUNE_CACHE") or os.path.join(ROOT, "paper_1606_08740_amd", "tuned_tiles.txt")
+    if not os.path.exists(path):
+        return None
+    tile = None
+    for line in open(path):
+        f = line.split()
+        if len(f) >= 8 and not line.startswith("#") and f[:6] == ["0", str(radius), "0", str(n), str(n), str(n)]:
+            v = [int(t) for t in f[6:10]] + [0] * (10 - len(f))
+            tile = {"rows_per_thread": v[0], "z_depth": v[1], "order": v[2], "pair": v[3]}
+    return tile
+
+
 def sweep_traffic(n):
     """Counter-measured bytes per sweep launch, or None when absent or stale."""
     import re
@@ -62,7 +78,7 @@ def sweep_traffic(n):
     if not m:
         return None
     rec = json.loads(m.group(1))
-    if rec.get("stencil_source_sha256_16") != stencil_sha():
+    if rec.get("stencil_source_sha256_16") != stencil_sha() or rec.get("tile") != fp64_tile(n):
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -117,6 +133,22 @@ def copy_calibration():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8}))
+
+
+def oracle_sample_error(x, n):
+    """Max |x - x_oracle| over the 64 seeded sample points stored in the golden
+    file (the oracle's FP64 solution of the same system, mean-free when the
+    system is singular periodic), divided by the RMS of the oracle's solution;
+    None when no stored solution exists for this size."""
+    import numpy as np
+    if not os.path.exists(GOLDEN):
+        return None
+    g = json.load(open(GOLDEN)).get(f"periodic_poisson_r6_{n}")
+    if g is None:
+        return None
+    xs = x - x.mean() if g["mean_free"] else x
+    rms = g["x_norm"] / np.sqrt(x.size)
+    return float(np.max(np.abs(xs[g["sample_index"]] - np.asarray(g["sample_x"]))) / rms)
 
 
 def timed_solves(solver, bt, steps, warmup):
@@ -254,13 +286,17 @@ def main():
                      "kernel": "k_stencil2 (fused Richardson sweep, paired-point layout), FP64, radius 6",
                      "bytes_per_launch": sweep_bytes, "mean_launch_us": sweep_us, "launches": launches},
     }
+    xa = x64.cpu().numpy()
+    out["error_vs_oracle"] = {
+        "fp64": oracle_sample_error(xa, args.n),
+        "measure": "max abs error at 64 seeded sample points over the RMS of the oracle's FP64 solution "
+                   "(mean-free), stored in tests/golden/oracle_full_size.json by tests/golden/make_golden.py"}
     copy_gbs = measured_copy_gbs()
     out["roofline"]["measured_copy_GBs"] = copy_gbs
     out["roofline"]["frac_of_measured_copy"] = achieved / copy_gbs
 
     # ---- other precisions on the same system ----
     if not args.no_mixed:
-        xa = x64.cpu().numpy()
         xa -= xa.mean()
         for label, prec in [("mixed_fp32", aar.AAR_MIXED_FP32), ("fp64_fp32hist", aar.AAR_FP64_FP32HIST)]:
             pm = inputs.Params(**{**prm.__dict__})
@@ -269,11 +305,12 @@ def main():
             dtm, rm, xm = timed_solves(sm, bt, args.steps, args.warmup)
             sm.close()
             xb = xm.cpu().numpy()
+            err = oracle_sample_error(xb, args.n)
             xb -= xb.mean()
             out[label] = {"value": args.steps / dtm, "unit": "solves/s", "ms_per_step": dtm / args.steps * 1e3,
                           "iterations": rm["iterations"], "outer_steps": rm["outer_steps"],
                           "rel_residual": rm["rel_residual"], "status": rm["status"],
-                          "speedup_vs_fp64": dt64 / dtm,
+                          "speedup_vs_fp64": dt64 / dtm, "error_vs_oracle": err,
                           "rel_diff_vs_fp64_gpu": float(np.linalg.norm(xa - xb) / np.linalg.norm(xa))}
 
     # ---- batched: 512 shifted periodic Helmholtz systems, one call ----

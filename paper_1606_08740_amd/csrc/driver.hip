@@ -643,6 +643,14 @@ aar_status status_of(const InstState &st)
     }
 }
 
+// Whether the Anderson-residual pass of this tile shape also forms the Gram
+// products (the paired layout's fused variant: FP64 iterate and history, up
+// to 8 waves, history length kFusedGramM); otherwise the separate Gram pass runs.
+bool gram_fusable(const TileShape &ts, bool paired_fk, int m, bool f64, Prec hist)
+{
+    return paired_fk && m == kFusedGramM && ts.pair <= 2 && f64 && hist == Prec::F64;
+}
+
 // Point Path<T> at the workspace for system `idx`.
 template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool f64)
 {
@@ -655,7 +663,7 @@ template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool 
     const bool paired_fk = paired_layout(P.ts, op.prob.n[0], P.conv, kFk);
     stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], P.ts, &tx, &ty, &tz, &blocks, paired_fk);
     P.rho_blocks = blocks;
-    P.gram_fused = paired_fk && S->params.m == kFusedGramM && P.ts.pair <= 2 && f64 && P.hist == Prec::F64;
+    P.gram_fused = gram_fusable(P.ts, paired_fk, S->params.m, f64, P.hist);
     P.gram_blocks = gram_blocks(op.N, S->params.m);
     P.upd_blocks = stream_blocks(op.N);
     P.slot_stride = S->slot_stride[f64 ? 0 : 1];
