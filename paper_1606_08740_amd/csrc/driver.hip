@@ -404,7 +404,7 @@ Sizes compute_sizes(const aar_problem *probs, int count, const aar_params *pa)
     b += sizeof(double) * ((size_t)z.max_stencil_blocks + (size_t)std::max(z.gram_blocks, z.max_stencil_blocks) * z.ne +
                            z.gram_blocks + z.ne + 8);
     if (!mixed) {
-        b += vec_span(8) * (3 + z.q) + vec_span(hist_bytes(hist)) * slots + (hist != Prec::F64 ? vec_span(8) : 0);
+        b += vec_span(8) * (3 + z.q) + vec_span(hist_bytes(hist)) * slots + (hist == Prec::F32_BF16 ? vec_span(8) : 0);
         b += sizeof(double) * (size_t)vel_total;
     } else {
         b += vec_span(4) * (3 + z.q) + vec_span(hist_bytes(hist)) * slots + vec_span(8) * 3;
@@ -1102,7 +1102,7 @@ size_t batch_bytes(const aar_problem *probs, int count, const aar_params *pa)
     size_t b = 0;
     if (!is_mixed(pa->precision)) {
         const Prec h = hist_of(pa->precision);
-        b += (size_t)total * (8 * (3 + q) + hist_bytes(h) * slots + (h != Prec::F64 ? 8 : 0));
+        b += (size_t)total * (8 * (3 + q) + hist_bytes(h) * slots + (h == Prec::F32_BF16 ? 8 : 0));
     } else
         b += (size_t)total * (4 * (3 + q) + hist_bytes(pa->precision == AAR_MIXED_FP32 ? Prec::F32 : Prec::F32_BF16) * slots +
                               8 * 3 + (pa->precision == AAR_MIXED_FP32_BF16HIST ? 4 : 0));
@@ -1188,7 +1188,8 @@ aar_status batch_setup(aar_solver_t *S)
         } else {
             B.fring = S->hist == Prec::F32 ? (void *)S->alloc<float>((size_t)total * slots, &st)
                                            : (void *)S->alloc<bf16_t>((size_t)total * slots, &st);
-            B.fcur64 = S->alloc<double>(total, &st);
+            if (S->hist == Prec::F32_BF16)
+                B.fcur64 = S->alloc<double>(total, &st);
         }
         B.dx64 = S->q > 0 ? S->alloc<double>((size_t)total * S->q, &st) : nullptr;
     } else {
@@ -1703,7 +1704,7 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
         size_t arena = 0;
         if (!S->mixed) {
             arena = vec_span(8) * (3 + S->q) + vec_span(hist_bytes(S->hist)) * slots +
-                    (S->hist != Prec::F64 ? vec_span(8) : 0);
+                    (S->hist == Prec::F32_BF16 ? vec_span(8) : 0);
         } else {
             arena = vec_span(4) * (3 + S->q) + vec_span(hist_bytes(S->hist)) * slots + vec_span(8) * 3 +
                     (S->hist == Prec::F32_BF16 ? vec_span(4) : 0);
@@ -1724,7 +1725,7 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
             P.xb = (double *)carve(8, 1);
             P.b = (double *)carve(8, 1);
             P.fring = carve(hist_bytes(S->hist), slots);
-            if (S->hist != Prec::F64)
+            if (S->hist == Prec::F32_BF16)
                 P.fcur = (double *)carve(8, 1);      // f_k of the update in FP64
             P.dx = S->q > 0 ? (double *)carve(8, S->q) : nullptr;
             S->slot_stride[0] = vec_span(hist_bytes(S->hist)) / hist_bytes(S->hist);
