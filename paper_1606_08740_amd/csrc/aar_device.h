@@ -151,8 +151,8 @@ template <typename T> struct StencilArgs {
 };
 
 // History length whose Gram products the paired Anderson-residual pass forms
-// itself (the evaluation workloads' m) when iterate and history are FP64;
-// other lengths and precisions use the separate Gram pass.
+// itself (the evaluation workloads' m) when the iterate is FP64 and the
+// history FP64 or FP32; other lengths and precisions use the separate Gram pass.
 constexpr int kFusedGramM = 7;
 constexpr int kFusedGramNE = kFusedGramM * (kFusedGramM + 1) / 2 + kFusedGramM;
 

@@ -644,11 +644,12 @@ aar_status status_of(const InstState &st)
 }
 
 // Whether the Anderson-residual pass of this tile shape also forms the Gram
-// products (the paired layout's fused variant: FP64 iterate and history, up
-// to 8 waves, history length kFusedGramM); otherwise the separate Gram pass runs.
+// products (the paired layout's fused variant: FP64 iterate, FP64 or FP32
+// history, up to 8 waves, history length kFusedGramM); otherwise the separate
+// Gram pass runs.
 bool gram_fusable(const TileShape &ts, bool paired_fk, int m, bool f64, Prec hist)
 {
-    return paired_fk && m == kFusedGramM && ts.pair <= 2 && f64 && hist == Prec::F64;
+    return paired_fk && m == kFusedGramM && ts.pair <= 2 && f64 && hist != Prec::F32_BF16;
 }
 
 // Point Path<T> at the workspace for system `idx`.

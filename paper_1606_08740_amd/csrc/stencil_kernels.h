@@ -652,31 +652,28 @@ __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, 
                 }
                 acc += (double)r0 * (double)r0 + (double)r1 * (double)r1;
                 if constexpr (GM > 0) {
-                    // the Gram pass sees f_k as stored in the ring (history precision)
+                    // the Gram pass sees f_k as stored in the ring (history
+                    // precision); positions t >= l hold f_k itself, so their
+                    // differences are exactly zero and the products take the
+                    // fixed layout of a full history
                     H hk[2];
                     Hist<H>::store(hk, 0, f0);
                     Hist<H>::store(hk, 1, f1);
-                    double col0[GM + 1], col1[GM + 1];
+                    Pack<H, 2> sv[GM];
 #pragma unroll
-                    for (int t = 0; t < GM; ++t) {
-                        col0[t] = 0.0;
-                        col1[t] = 0.0;
-                        if (t < gl) {
-                            const Pack<H, 2> hv2 = *reinterpret_cast<const Pack<H, 2> *>(gslot[t] + id);
-                            col0[t] = (double)Hist<H>::load(hv2.v, 0);
-                            col1[t] = (double)Hist<H>::load(hv2.v, 1);
-                        }
-                    }
-                    col0[GM] = 0.0;
-                    col1[GM] = 0.0;
-                    const double fk0 = (double)Hist<H>::load(hk, 0), fk1 = (double)Hist<H>::load(hk, 1);
+                    for (int t = 0; t < GM; ++t)
+                        if (t < gl)
+                            sv[t] = *reinterpret_cast<const Pack<H, 2> *>(gslot[t] + id);
 #pragma unroll
-                    for (int t = 0; t <= GM; ++t) {
-                        col0[t] = t == gl ? fk0 : col0[t];
-                        col1[t] = t == gl ? fk1 : col1[t];
+                    for (int e = 0; e < 2; ++e) {
+                        const double fe = (double)Hist<H>::load(hk, e);
+                        double col[GM + 1];
+#pragma unroll
+                        for (int t = 0; t < GM; ++t)
+                            col[t] = t < gl ? (double)Hist<H>::load(sv[t].v, e) : fe;
+                        col[GM] = fe;
+                        gram_point<GM>(col, GM, gacc);
                     }
-                    gram_point<GM>(col0, gl, gacc);
-                    gram_point<GM>(col1, gl, gacc);
                 }
             }
         }
@@ -838,10 +835,10 @@ static hipError_t launch_one2(StencilArgs<T> a, const TileShape &ts, int *blocks
     a.order = ts.order;
     if (blocks_out)
         *blocks_out = blocks;
-    // the fused Gram variant: FP64 iterate and history, up to 8 waves (16-wave
-    // workgroups would spill its accumulators; with a narrow history or an
-    // FP32 iterate the separate Gram pass is as fast or faster)
-    constexpr int GM = (MODE == kFk && NW <= 8 && sizeof(T) == 8 && sizeof(H) == 8) ? kFusedGramM : 0;
+    // the fused Gram variant: FP64 iterate, FP64 or FP32 history, up to 8
+    // waves (16-wave workgroups would spill its accumulators; with a bfloat16
+    // history or an FP32 iterate the separate Gram pass runs)
+    constexpr int GM = (MODE == kFk && NW <= 8 && sizeof(T) == 8 && sizeof(H) >= 4) ? kFusedGramM : 0;
     if (a.gram_partial && GM == 0)
         return hipErrorInvalidValue;
     if (a.gram_partial)
