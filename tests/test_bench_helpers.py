@@ -1,0 +1,48 @@
+"""Host-side helpers of bench.py: the tile lookup that decides whether the
+profiled sweep traffic applies, and the error against the oracle's stored
+solution samples (tests/golden/oracle_full_size.json, written by the oracle
+only)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import bench
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_full_size.json")
+
+
+def test_fp64_tile_reads_the_tile_file(tmp_path, monkeypatch):
+    f = tmp_path / "tiles.txt"
+    f.write_text("# comment\n1 6 0 192 192 192 2 8 1 1\n0 6 0 192 192 192 1 20 3 2\n0 4 0 192 192 192 4 4\n")
+    monkeypatch.setenv("AAR_TUNE_CACHE", str(f))
+    assert bench.fp64_tile(192) == {"rows_per_thread": 1, "z_depth": 20, "order": 3, "pair": 2}
+    assert bench.fp64_tile(192, radius=4) == {"rows_per_thread": 4, "z_depth": 4, "order": 0, "pair": 0}
+    assert bench.fp64_tile(256) is None
+
+
+def test_sweep_traffic_only_for_the_profiled_tile(tmp_path, monkeypatch):
+    monkeypatch.delenv("AAR_TUNE_CACHE", raising=False)
+    t = bench.sweep_traffic(192)
+    if t is not None:   # the committed profile matches the committed tile and sources
+        assert 2.0e8 < t < 4.0e8
+    assert bench.sweep_traffic(128) is None
+    f = tmp_path / "tiles.txt"
+    f.write_text("0 6 0 192 192 192 4 2 0 0\n")   # a shape no profile was taken with
+    monkeypatch.setenv("AAR_TUNE_CACHE", str(f))
+    assert bench.sweep_traffic(192) is None
+
+
+def test_oracle_sample_error():
+    g = json.load(open(GOLDEN))["periodic_poisson_r6_192"]
+    n = 192 ** 3
+    rms = g["x_norm"] / np.sqrt(n)
+    x = np.zeros(n)
+    idx = np.asarray(g["sample_index"])
+    x[idx] = g["sample_x"]
+    x += 0.25          # a constant offset is invisible in a mean-free comparison
+    assert bench.oracle_sample_error(x, 192) < 1e-5
+    x[idx[3]] += 1e-3 * rms
+    assert bench.oracle_sample_error(x, 192) == pytest.approx(1e-3, rel=1e-2)
+    assert bench.oracle_sample_error(x, 100) is None
