@@ -64,10 +64,12 @@ enum { AAR_BC_ZERO_DIRICHLET = 0, AAR_BC_PERIODIC = 1 };
  *     the history ring (the f_j of Eqs. 4-5) stored in FP32 / bfloat16; Gram
  *     products accumulated in FP64.  No refinement is needed: the iterate
  *     and the convergence test are FP64; only the extrapolation directions
- *     are rounded.  The Anderson update takes f_k from the ring when it is
- *     FP32 (a perturbation of the step relative to the current residual,
- *     which leaves the fixed point and the FP64 test exact) and from an FP64
- *     copy when it is bfloat16.
+ *     are rounded.  With an FP32 ring the Anderson update also takes f_k
+ *     from the ring and the increments of Anderson steps (the X_k columns
+ *     of Eq. 4) are stored in FP32: perturbations of the step relative to
+ *     the current residual, which leave the fixed point and the FP64 test
+ *     exact.  With a bfloat16 ring f_k comes from an FP64 copy and the
+ *     increments stay FP64.
  *   AAR_MIXED_FP32: FP32 sweeps, history and Gram products (accumulated in
  *     FP64), FP64 m x m solve, and an outer FP64 iterative refinement:
  *     r = b - A x (FP64), inner FP32 AAR on A d = r/||r|| to inner_tol,

@@ -251,7 +251,7 @@ template <typename T> struct BatchUpdateArgs {
     T *xout;
     const void *fring;
     const T *fcur;
-    T *dxring;
+    void *dxring;           // DxOf<T, H> elements
     int64_t slot_stride;
     int64_t dx_stride;
 };
@@ -341,12 +341,23 @@ struct LsqArgs {
     int64_t log_cap;
 };
 
+// Element type of the ring of Anderson increments x_{k+1} - x_k (the X_k
+// columns of Anderson steps, Eq. 4): the iterate's type, except FP32 beside an
+// FP32 history ring of an FP64 iteration, where like the f_j it is only an
+// extrapolation direction.
+template <typename T, typename H> struct DxOf {
+    using type = T;
+};
+template <> struct DxOf<double, float> {
+    using type = float;
+};
+
 template <typename T> struct UpdateArgs {
     const T *xin;
     T *xout;
     const void *fring;
     const T *fcur;          // non-null: use instead of the ring slot for f_k
-    T *dxring;              // slots slot_stride elements apart
+    void *dxring;           // DxOf<T, H> elements, slots dx_stride elements apart
     const InstState *state;
     int64_t N;
     int64_t slot_stride;    // elements between f slots, a multiple of 8

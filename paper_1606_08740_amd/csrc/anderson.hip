@@ -385,9 +385,10 @@ template <typename T, typename H>
 __global__ __launch_bounds__(kThreads) void k_update(const UpdateArgs<T> a)
 {
     constexpr int V = 16 / (int)sizeof(T);
+    using D = typename DxOf<T, H>::type;
     __shared__ const H *fs[kMaxSlots];
     __shared__ T al[kMaxSlots];
-    __shared__ const T *ds[kMaxM];
+    __shared__ const D *ds[kMaxM];
     __shared__ T de[kMaxM];
     __shared__ int nf_s, nd_s, ws_s;
     const InstState *st = a.state;
@@ -410,12 +411,12 @@ __global__ __launch_bounds__(kThreads) void k_update(const UpdateArgs<T> a)
         }
     }
     if (threadIdx.x < kMaxM && (int)threadIdx.x < st->nd) {
-        ds[threadIdx.x] = a.dxring + (int64_t)st->dslot[threadIdx.x] * a.dx_stride;
+        ds[threadIdx.x] = reinterpret_cast<const D *>(a.dxring) + (int64_t)st->dslot[threadIdx.x] * a.dx_stride;
         de[threadIdx.x] = (T)st->delta[threadIdx.x];
     }
     __syncthreads();
     const int nf = nf_s, nd = nd_s;
-    T *dxw = ws_s >= 0 ? a.dxring + (int64_t)ws_s * a.dx_stride : nullptr;
+    D *dxw = ws_s >= 0 ? reinterpret_cast<D *>(a.dxring) + (int64_t)ws_s * a.dx_stride : nullptr;
     const T *fk_ptr = a.fcur;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t nvec = a.N / V;
@@ -447,21 +448,22 @@ __global__ __launch_bounds__(kThreads) void k_update(const UpdateArgs<T> a)
         for (int u = 0; u < V; ++u)
             d[u] += al[nf - 1] * fk[u];
         for (int t = 0; t < nd; ++t) {
-            const Pack<T, V> h = *reinterpret_cast<const Pack<T, V> *>(ds[t] + i);
+            const Pack<D, V> h = *reinterpret_cast<const Pack<D, V> *>(ds[t] + i);
 #pragma unroll
             for (int u = 0; u < V; ++u)
-                d[u] += de[t] * h.v[u];
+                d[u] += de[t] * (T)h.v[u];
         }
         const Pack<T, V> xk = *reinterpret_cast<const Pack<T, V> *>(a.xin + i);
-        Pack<T, V> xn, dx;
+        Pack<T, V> xn;
+        Pack<D, V> dx;
 #pragma unroll
         for (int u = 0; u < V; ++u) {
             xn.v[u] = xk.v[u] + d[u];
-            dx.v[u] = xn.v[u] - xk.v[u];     // the increment actually taken
+            dx.v[u] = (D)(xn.v[u] - xk.v[u]);     // the increment actually taken
         }
         *reinterpret_cast<Pack<T, V> *>(a.xout + i) = xn;
         if (dxw)
-            *reinterpret_cast<Pack<T, V> *>(dxw + i) = dx;
+            *reinterpret_cast<Pack<D, V> *>(dxw + i) = dx;
     }
     for (int64_t i = nvec * V + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.N; i += stride) {
         T d = 0;
@@ -470,12 +472,12 @@ __global__ __launch_bounds__(kThreads) void k_update(const UpdateArgs<T> a)
         const T fk = fk_ptr ? fk_ptr[i] : (T)Hist<H>::load(fs[nf - 1], i);
         d += al[nf - 1] * fk;
         for (int t = 0; t < nd; ++t)
-            d += de[t] * ds[t][i];
+            d += de[t] * (T)ds[t][i];
         const T xk = a.xin[i];
         const T xn = xk + d;
         a.xout[i] = xn;
         if (dxw)
-            dxw[i] = xn - xk;
+            dxw[i] = (D)(xn - xk);
     }
 }
 

@@ -249,7 +249,8 @@ __global__ __launch_bounds__(kThreads) void k_update_batched(const BatchUpdateAr
     constexpr int V = 16 / (int)sizeof(T);
     __shared__ const H *fs[kMaxSlots];
     __shared__ T al[kMaxSlots];
-    __shared__ const T *ds[kMaxM];
+    using D = typename DxOf<T, H>::type;
+    __shared__ const D *ds[kMaxM];
     __shared__ T de[kMaxM];
     __shared__ int nf_s, nd_s, ws_s;
     const int nitems = *a.nitems;
@@ -270,12 +271,12 @@ __global__ __launch_bounds__(kThreads) void k_update_batched(const BatchUpdateAr
             al[threadIdx.x] = (T)st->alpha[threadIdx.x];
         }
         if (threadIdx.x < kMaxM && (int)threadIdx.x < st->nd) {
-            ds[threadIdx.x] = a.dxring + off + (int64_t)st->dslot[threadIdx.x] * a.dx_stride;
+            ds[threadIdx.x] = reinterpret_cast<const D *>(a.dxring) + off + (int64_t)st->dslot[threadIdx.x] * a.dx_stride;
             de[threadIdx.x] = (T)st->delta[threadIdx.x];
         }
         __syncthreads();
         const int nf = nf_s, nd = nd_s;
-        T *dxw = ws_s >= 0 ? a.dxring + off + (int64_t)ws_s * a.dx_stride : nullptr;
+        D *dxw = ws_s >= 0 ? reinterpret_cast<D *>(a.dxring) + off + (int64_t)ws_s * a.dx_stride : nullptr;
         const T *xin = a.xin + off;
         T *xout = a.xout + off;
         const T *fk_ptr = a.fcur ? a.fcur + off : nullptr;
@@ -310,21 +311,22 @@ __global__ __launch_bounds__(kThreads) void k_update_batched(const BatchUpdateAr
             for (int u = 0; u < V; ++u)
                 d[u] += al[nf - 1] * fk[u];
             for (int t = 0; t < nd; ++t) {
-                const Pack<T, V> h = *reinterpret_cast<const Pack<T, V> *>(ds[t] + i);
+                const Pack<D, V> h = *reinterpret_cast<const Pack<D, V> *>(ds[t] + i);
 #pragma unroll
                 for (int u = 0; u < V; ++u)
-                    d[u] += de[t] * h.v[u];
+                    d[u] += de[t] * (T)h.v[u];
             }
             const Pack<T, V> xk = *reinterpret_cast<const Pack<T, V> *>(xin + i);
-            Pack<T, V> xn, dx;
+            Pack<T, V> xn;
+            Pack<D, V> dx;
 #pragma unroll
             for (int u = 0; u < V; ++u) {
                 xn.v[u] = xk.v[u] + d[u];
-                dx.v[u] = xn.v[u] - xk.v[u];
+                dx.v[u] = (D)(xn.v[u] - xk.v[u]);
             }
             *reinterpret_cast<Pack<T, V> *>(xout + i) = xn;
             if (dxw)
-                *reinterpret_cast<Pack<T, V> *>(dxw + i) = dx;
+                *reinterpret_cast<Pack<D, V> *>(dxw + i) = dx;
         }
         for (int64_t i = vhi + threadIdx.x; i < hi; i += blockDim.x) {
             T d = 0;
@@ -333,12 +335,12 @@ __global__ __launch_bounds__(kThreads) void k_update_batched(const BatchUpdateAr
             const T fk = fk_ptr ? fk_ptr[i] : (T)Hist<H>::load(fs[nf - 1], i);
             d += al[nf - 1] * fk;
             for (int t = 0; t < nd; ++t)
-                d += de[t] * ds[t][i];
+                d += de[t] * (T)ds[t][i];
             const T xk = xin[i];
             const T xn = xk + d;
             xout[i] = xn;
             if (dxw)
-                dxw[i] = xn - xk;
+                dxw[i] = (D)(xn - xk);
         }
         __syncthreads();
     }

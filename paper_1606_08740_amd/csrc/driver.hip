@@ -125,7 +125,8 @@ TileShape default_tile(int radius, bool fp64)
 // Buffers and launch arguments of the AAR iteration in precision T.
 template <typename T> struct Path {
     Prec hist = Prec::F64;
-    T *xa = nullptr, *xb = nullptr, *b = nullptr, *fcur = nullptr, *dx = nullptr;
+    T *xa = nullptr, *xb = nullptr, *b = nullptr, *fcur = nullptr;
+    void *dx = nullptr;        // Anderson increments, DxOf<T, hist> elements
     void *fring = nullptr;
     int64_t N = 0, slot_stride = 0;
     TileShape ts{};
@@ -244,7 +245,8 @@ struct aar_solver_t {
         int *c_n = nullptr, *a_n = nullptr;
         int *c_sb = nullptr, *c_cb = nullptr, *a_sb = nullptr, *a_cb = nullptr;
         double *p_rho = nullptr, *p_gram = nullptr, *p_s = nullptr, *p_c = nullptr;
-        double *xa64 = nullptr, *xb64 = nullptr, *b64 = nullptr, *r64 = nullptr, *dx64 = nullptr;
+        double *xa64 = nullptr, *xb64 = nullptr, *b64 = nullptr, *r64 = nullptr;
+        void *dx64 = nullptr;   // FP64 iterate's increments (FP32 beside an FP32 ring)
         double *fcur64 = nullptr;   // FP64 f_k when an FP64 iteration keeps a narrow history
         float *xa32 = nullptr, *xb32 = nullptr, *rhs32 = nullptr, *fcur32 = nullptr, *dx32 = nullptr;
         void *fring = nullptr;
@@ -404,7 +406,8 @@ Sizes compute_sizes(const aar_problem *probs, int count, const aar_params *pa)
     b += sizeof(double) * ((size_t)z.max_stencil_blocks + (size_t)std::max(z.gram_blocks, z.max_stencil_blocks) * z.ne +
                            z.gram_blocks + z.ne + 8);
     if (!mixed) {
-        b += vec_span(8) * (3 + z.q) + vec_span(hist_bytes(hist)) * slots + (hist == Prec::F32_BF16 ? vec_span(8) : 0);
+        b += vec_span(8) * 3 + vec_span(hist == Prec::F32 ? 4 : 8) * z.q + vec_span(hist_bytes(hist)) * slots +
+             (hist == Prec::F32_BF16 ? vec_span(8) : 0);
         b += sizeof(double) * (size_t)vel_total;
     } else {
         b += vec_span(4) * (3 + z.q) + vec_span(hist_bytes(hist)) * slots + vec_span(8) * 3;
@@ -1103,7 +1106,7 @@ size_t batch_bytes(const aar_problem *probs, int count, const aar_params *pa)
     size_t b = 0;
     if (!is_mixed(pa->precision)) {
         const Prec h = hist_of(pa->precision);
-        b += (size_t)total * (8 * (3 + q) + hist_bytes(h) * slots + (h == Prec::F32_BF16 ? 8 : 0));
+        b += (size_t)total * (8 * 3 + (h == Prec::F32 ? 4 : 8) * q + hist_bytes(h) * slots + (h == Prec::F32_BF16 ? 8 : 0));
     } else
         b += (size_t)total * (4 * (3 + q) + hist_bytes(pa->precision == AAR_MIXED_FP32 ? Prec::F32 : Prec::F32_BF16) * slots +
                               8 * 3 + (pa->precision == AAR_MIXED_FP32_BF16HIST ? 4 : 0));
@@ -1192,7 +1195,9 @@ aar_status batch_setup(aar_solver_t *S)
             if (S->hist == Prec::F32_BF16)
                 B.fcur64 = S->alloc<double>(total, &st);
         }
-        B.dx64 = S->q > 0 ? S->alloc<double>((size_t)total * S->q, &st) : nullptr;
+        if (S->q > 0)
+            B.dx64 = S->hist == Prec::F32 ? (void *)S->alloc<float>((size_t)total * S->q, &st)
+                                          : (void *)S->alloc<double>((size_t)total * S->q, &st);
     } else {
         B.xa64 = S->alloc<double>(total, &st);      // x in FP64 (refinement)
         B.b64 = S->alloc<double>(total, &st);
@@ -1299,7 +1304,7 @@ template <typename T> hipError_t batch_enqueue_cycle(aar_solver_t *S, hipStream_
     const aar_params &pa = S->params;
     const bool f64 = std::is_same<T, double>::value;
     T *xa, *xb, *b;
-    T *dx;
+    void *dx;
     T *fcur = nullptr;
     if constexpr (std::is_same<T, double>::value) {
         xa = B.xa64;
@@ -1703,8 +1708,10 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
         const size_t stagger = stagger_bytes();
         auto vec_span = [&](size_t esize) { return (((size_t)N * esize + 4095) / 4096) * 4096 + stagger; };
         size_t arena = 0;
+        // Anderson increments of an FP64 iteration: FP32 beside an FP32 ring
+        const size_t dx_bytes = S->hist == Prec::F32 ? 4 : 8;
         if (!S->mixed) {
-            arena = vec_span(8) * (3 + S->q) + vec_span(hist_bytes(S->hist)) * slots +
+            arena = vec_span(8) * 3 + vec_span(dx_bytes) * S->q + vec_span(hist_bytes(S->hist)) * slots +
                     (S->hist == Prec::F32_BF16 ? vec_span(8) : 0);
         } else {
             arena = vec_span(4) * (3 + S->q) + vec_span(hist_bytes(S->hist)) * slots + vec_span(8) * 3 +
@@ -1728,9 +1735,9 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
             P.fring = carve(hist_bytes(S->hist), slots);
             if (S->hist == Prec::F32_BF16)
                 P.fcur = (double *)carve(8, 1);      // f_k of the update in FP64
-            P.dx = S->q > 0 ? (double *)carve(8, S->q) : nullptr;
+            P.dx = S->q > 0 ? carve(dx_bytes, S->q) : nullptr;
             S->slot_stride[0] = vec_span(hist_bytes(S->hist)) / hist_bytes(S->hist);
-            S->dx_stride64 = vec_span(8) / 8;
+            S->dx_stride64 = vec_span(dx_bytes) / dx_bytes;
         } else {
             Path<float> &P = S->p32;
             P.hist = S->hist;
@@ -1740,7 +1747,7 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
             P.fring = carve(hist_bytes(S->hist), slots);
             if (S->hist == Prec::F32_BF16)
                 P.fcur = (float *)carve(4, 1);
-            P.dx = S->q > 0 ? (float *)carve(4, S->q) : nullptr;
+            P.dx = S->q > 0 ? carve(4, S->q) : nullptr;
             S->x64 = (double *)carve(8, 1);
             S->b64 = (double *)carve(8, 1);
             S->r64 = (double *)carve(8, 1);

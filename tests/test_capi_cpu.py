@@ -32,7 +32,8 @@ def test_workspace_bytes_scales_with_history():
     bf = _ws(prob, inputs.Params(m=7, p=6, precision=2))
     assert bf < mixed
     # FP64 iterate with a narrow history: 8 history slots of 4 or 2 bytes
-    # instead of 8 (the bfloat16 ring plus one FP64 copy of f_k)
+    # instead of 8 (FP32 increments beside the FP32 ring; the bfloat16 ring
+    # plus one FP64 copy of f_k)
     f64 = _ws(prob, inputs.Params(m=7, p=6, precision=0))
     h32 = _ws(prob, inputs.Params(m=7, p=6, precision=3))
     h16 = _ws(prob, inputs.Params(m=7, p=6, precision=4))
