@@ -46,11 +46,16 @@ STENCIL_SRCS = [os.path.join(ROOT, "paper_1606_08740_amd", "csrc", f)
 
 
 def stencil_sha():
-    """First 16 hex digits of the SHA-256 of the stencil sources, concatenated."""
+    """First 16 hex digits of the SHA-256 of the stencil sources' code: the
+    files concatenated with // comments, trailing blanks and empty lines
+    removed, so editing a comment keeps a profile valid."""
     import hashlib
     h = hashlib.sha256()
     for f in STENCIL_SRCS:
-        h.update(open(f, "rb").read())
+        for line in open(f):
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

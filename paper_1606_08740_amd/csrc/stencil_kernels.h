@@ -348,9 +348,10 @@ template <> struct Pair<float> { using type = float2; };
 
 // Paired layout of the Richardson sweep and the Anderson-step residual
 // (MODE kSweep or kFk, no convection, even n0, 16-byte aligned vectors).
-// The 256 threads form 32 lanes along x by 8 lane rows; a thread owns the two
-// x-adjacent points (gx, gx + 1) in RY contiguous rows, so the tile is 64 x
-// 8 RY.  Global loads and stores move both points as one vector, and the
+// The 64 NW threads (NW = 4, 8 or 16 waves) form 32 lanes along x by 2 NW
+// lane rows; a thread owns the two x-adjacent points (gx, gx + 1) in RY
+// contiguous rows, so the tile is 64 x 2 NW RY.  Global loads and stores move
+// both points as one vector, and the
 // taps read pairs from LDS: for x the 2R + 2 values around the pair, for y a
 // column pair per row, shared by the RY rows.  This halves the LDS requests
 // per point of the one-point layout.  The z taps come from a register queue
@@ -358,7 +359,8 @@ template <> struct Pair<float> { using type = float2; };
 // GM > 0 (MODE kFk only): the pass also forms the Gram products of the
 // extrapolation step (Eqs. 4-5) for history length GM at its own points:
 // the GM preceding ring slots are read beside f_k, and per-workgroup partials
-// of the GM(GM+1)/2 + GM entries go to a.gram_partial (entry-major).
+// of the GM(GM+1)/2 + GM entries go to a.gram_partial (entry-major), which
+// the one-wave solve kernel sums.
 template <typename T, typename H, int R, int MODE, int RY, int NW, int GM = 0>
 __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, double *partial_out)
 {
