@@ -263,7 +263,15 @@ def main():
     s64.set_timing(False)
     s64.close()
     sweep_us = ms_tot / max(launches, 1) * 1e3
-    sweep_bytes = 4 * 8 * N
+    # algorithmic bytes of the p - 1 Richardson sweeps of a cycle, per launch.
+    # With the paired layout (and m + 1 >= p) the first sweep of a cycle reads
+    # x and b and writes f (24 B per point); the others follow the residual
+    # recursion f_{j+1} = f_j - omega D^-1 A f_j: read f_j, write f_{j+1}
+    # (16 B).  Otherwise every sweep reads x, b and writes x, f (32 B).
+    tile = fp64_tile(args.n)
+    recursion = tile is not None and tile["pair"] > 0 and prm.m + 1 >= prm.p >= 2
+    p = prm.p
+    sweep_bytes = (3 * 8 + (p - 2) * 2 * 8) * N / (p - 1) if recursion else 4 * 8 * N
     achieved = sweep_bytes / (sweep_us * 1e-6) / 1e9
 
     out = {
@@ -288,7 +296,9 @@ def main():
         "status": r64["status"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic(args.n),
-                     "kernel": "k_stencil2 (fused Richardson sweep, paired-point layout), FP64, radius 6",
+                     "kernel": ("k_stencil2 Richardson sweeps, paired-point layout, FP64, radius 6: " +
+                                ("a cycle's first from x and b, the others by the residual recursion"
+                                 if recursion else "each from x and b")),
                      "bytes_per_launch": sweep_bytes, "mean_launch_us": sweep_us, "launches": launches},
     }
     xa = x64.cpu().numpy()

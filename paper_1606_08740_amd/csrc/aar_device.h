@@ -148,6 +148,11 @@ template <typename T> struct StencilArgs {
     int32_t order;          // kOrder* bits: tile numbering and z direction
     T omega;
     double *gram_partial;   // kFk, paired layout, m = kFusedGramM: [ne][blocks] Gram partials, else null
+    // kSweep / kFk, paired layout, ring type T: the residual recursion of
+    // Richardson steps.  The input is ring slot k - 1 (f_{k-1}) instead of x,
+    // b is not read, f_k = f_{k-1} - omega D^-1 A f_{k-1}, and kFk's norm is
+    // that of D f_k (= b - A x_k); kSweep then writes no x (out may be null).
+    int32_t recur;
 };
 
 // History length whose Gram products the paired Anderson-residual pass forms
@@ -365,6 +370,12 @@ template <typename T> struct UpdateArgs {
     // non-null: pinned host word that workgroup 0 sets to the run status on
     // entry, so the host polls it without a copy on the stream
     int32_t *status_out = nullptr;
+    // p_rich > 0 (residual recursion): xin is the cycle's first iterate x_c,
+    // and the p_rich - 1 Richardson steps of the cycle are applied first,
+    // x_k = x_c + omega_rich sum f_j over history positions nf - p_rich ..
+    // nf - 2; the increment kept is then x_{k+1} - x_k
+    T omega_rich = 0;
+    int32_t p_rich = 0;
 };
 
 // Workgroup index -> logical tile index so that each XCD (and its L2) gets a
@@ -448,6 +459,10 @@ hipError_t launch_gram_finish(const double *partial, int blocks, double *out, in
                               int p, hipStream_t s);
 hipError_t launch_update(Prec prec, const UpdateArgs<double> *a64, const UpdateArgs<float> *a32, int blocks,
                          hipStream_t s);
+// Residual recursion: x += omega * (the Richardson f_j of the unfinished cycle)
+// once a run has stopped (FP64 iterate and ring).
+hipError_t launch_finalize_f64(double *x, const void *fring, const InstState *state, int p, int nslots,
+                               int64_t slot_stride, double omega, int64_t N, hipStream_t s);
 hipError_t launch_norm_partial(bool f64, const void *v, int64_t N, double *partial, int blocks, hipStream_t s);
 hipError_t launch_init_state(InstState *st, const double *partial, int blocks, int64_t max_iter, double tol,
                              hipStream_t s);

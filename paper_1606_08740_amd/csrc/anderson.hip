@@ -416,21 +416,36 @@ __global__ __launch_bounds__(kThreads) void k_update(const UpdateArgs<T> a)
     }
     __syncthreads();
     const int nf = nf_s, nd = nd_s;
+    // residual recursion: history positions tr0 .. nf - 2 are the cycle's
+    // Richardson steps (none when p_rich is 0)
+    const int tr0 = a.p_rich > 0 ? nf - a.p_rich : nf;
     D *dxw = ws_s >= 0 ? reinterpret_cast<D *>(a.dxring) + (int64_t)ws_s * a.dx_stride : nullptr;
     const T *fk_ptr = a.fcur;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t nvec = a.N / V;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvec; v += stride) {
         const int64_t i = v * V;
-        T d[V];
+        T d[V], dr[V];
 #pragma unroll
-        for (int u = 0; u < V; ++u)
+        for (int u = 0; u < V; ++u) {
             d[u] = T(0);
-        for (int t = 0; t < nf - 1; ++t) {
+            dr[u] = T(0);
+        }
+        const int t1 = tr0 < nf - 1 ? tr0 : nf - 1;
+        for (int t = 0; t < t1; ++t) {
             const Pack<H, V> h = *reinterpret_cast<const Pack<H, V> *>(fs[t] + i);
 #pragma unroll
             for (int u = 0; u < V; ++u)
                 d[u] += al[t] * (T)Hist<H>::load(h.v, u);
+        }
+        for (int t = t1; t < nf - 1; ++t) {   // the cycle's Richardson steps (residual recursion)
+            const Pack<H, V> h = *reinterpret_cast<const Pack<H, V> *>(fs[t] + i);
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                const T fv = (T)Hist<H>::load(h.v, u);
+                d[u] += al[t] * fv;
+                dr[u] += fv;
+            }
         }
         T fk[V];
         if (fk_ptr) {
@@ -453,27 +468,31 @@ __global__ __launch_bounds__(kThreads) void k_update(const UpdateArgs<T> a)
             for (int u = 0; u < V; ++u)
                 d[u] += de[t] * (T)h.v[u];
         }
-        const Pack<T, V> xk = *reinterpret_cast<const Pack<T, V> *>(a.xin + i);
+        const Pack<T, V> xc = *reinterpret_cast<const Pack<T, V> *>(a.xin + i);
         Pack<T, V> xn;
         Pack<D, V> dx;
 #pragma unroll
         for (int u = 0; u < V; ++u) {
-            xn.v[u] = xk.v[u] + d[u];
-            dx.v[u] = (D)(xn.v[u] - xk.v[u]);     // the increment actually taken
+            const T xk = xc.v[u] + a.omega_rich * dr[u];
+            xn.v[u] = xk + d[u];
+            dx.v[u] = (D)(xn.v[u] - xk);     // the increment actually taken
         }
         *reinterpret_cast<Pack<T, V> *>(a.xout + i) = xn;
         if (dxw)
             *reinterpret_cast<Pack<D, V> *>(dxw + i) = dx;
     }
     for (int64_t i = nvec * V + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.N; i += stride) {
-        T d = 0;
-        for (int t = 0; t < nf - 1; ++t)
-            d += al[t] * (T)Hist<H>::load(fs[t], i);
+        T d = 0, dr = 0;
+        for (int t = 0; t < nf - 1; ++t) {
+            const T fv = (T)Hist<H>::load(fs[t], i);
+            d += al[t] * fv;
+            dr += t >= tr0 ? fv : T(0);
+        }
         const T fk = fk_ptr ? fk_ptr[i] : (T)Hist<H>::load(fs[nf - 1], i);
         d += al[nf - 1] * fk;
         for (int t = 0; t < nd; ++t)
             d += de[t] * (T)ds[t][i];
-        const T xk = a.xin[i];
+        const T xk = a.xin[i] + a.omega_rich * dr;
         const T xn = xk + d;
         a.xout[i] = xn;
         if (dxw)
@@ -757,6 +776,44 @@ hipError_t launch_deflate(double *x, double *r, int64_t N, double inv_sigma, dou
     hipLaunchKernelGGL(k_sum_partial, dim3(blocks), dim3(kThreads), 0, s, r, N, partial);
     hipLaunchKernelGGL(k_mean_finish, dim3(1), dim3(64), 0, s, scal + 2, partial, blocks, N);
     hipLaunchKernelGGL(k_deflate_apply, dim3(blocks), dim3(kThreads), 0, s, x, r, N, inv_sigma, scal + 2, partial);
+    return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Residual recursion: the returned iterate.  The sweeps of a cycle do not
+// write x, so when a run stops, x (the cycle's first iterate x_c) receives the
+// Richardson steps the unfinished cycle has taken: x_n = x_c + omega sum
+// f_j, j = cycle p .. n - 1, with n the iterate being returned (k for a
+// decision at Anderson step k, the cap for a capped run).
+template <typename T, typename H>
+__global__ __launch_bounds__(kThreads) void k_finalize(T *x, const void *fring, const InstState *state, int p,
+                                                     int nslots, int64_t slot_stride, T omega, int64_t N)
+{
+    const int status = state->status;
+    if (status == kRunning)
+        return;
+    const int64_t base = state->cycle * p;
+    int64_t n = (status == kMaxIter ? state->iters : state->iters - 1) - base;
+    if (n > p - 1)
+        n = p - 1;
+    if (n <= 0)
+        return;
+    const H *ring = reinterpret_cast<const H *>(fring);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+        T v = x[i];
+        for (int64_t s = 0; s < n; ++s)
+            v += omega * (T)Hist<H>::load(ring + (int64_t)((base + s) % nslots) * slot_stride, i);
+        x[i] = v;
+    }
+}
+
+hipError_t launch_finalize_f64(double *x, const void *fring, const InstState *state, int p, int nslots,
+                               int64_t slot_stride, double omega, int64_t N, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_finalize<double, double>), dim3(stream_blocks(N)), dim3(kThreads), 0, s, x, fring, state,
+                       p, nslots, slot_stride, omega, N);
     return hipGetLastError();
 }
 

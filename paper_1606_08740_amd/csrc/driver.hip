@@ -136,6 +136,7 @@ template <typename T> struct Path {
     int rho_blocks = 0, gram_blocks = 0, upd_blocks = 0;
     int64_t dx_stride = 0;     // elements between dx slots
     bool gram_fused = false;   // the Anderson-residual pass forms the Gram products
+    bool recur = false;        // sweeps after a cycle's first use the residual recursion
 };
 
 size_t hist_bytes(Prec p)
@@ -467,8 +468,16 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
     hipError_t e;
     for (int j = 0; j < pa.p - 1; ++j) {
         a.j = j;
-        a.x = (j & 1) ? P.xb : P.xa;
-        a.out = (j & 1) ? P.xa : P.xb;
+        if (P.recur) {
+            // x stays the cycle's first iterate; the first sweep reads it and
+            // b, the others continue from the previous f
+            a.recur = j > 0 ? 1 : 0;
+            a.x = P.xa;
+            a.out = nullptr;
+        } else {
+            a.x = (j & 1) ? P.xb : P.xa;
+            a.out = (j & 1) ? P.xa : P.xb;
+        }
         // timing: one event pair around the cycle's p - 1 back-to-back sweeps
         if (S->timing && j == 0) {
             if (S->tused + 2 > S->tev.size()) {
@@ -492,9 +501,10 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
         }
     }
     const int jk = pa.p - 1;
-    T *xk = (jk & 1) ? P.xb : P.xa;
+    T *xk = P.recur ? P.xa : (jk & 1) ? P.xb : P.xa;
     a.j = jk;
     a.x = xk;
+    a.recur = P.recur && jk > 0 ? 1 : 0;
     a.out = nullptr;
     a.fcur = P.fcur;
     a.partial = S->part_rho;
@@ -553,6 +563,12 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
     u.slot_stride = P.slot_stride;
     u.dx_stride = P.dx_stride;
     u.status_out = S->status_dev;
+    if (P.recur) {
+        // xk is the cycle's first iterate: the update applies the cycle's
+        // Richardson steps before the extrapolation
+        u.omega_rich = (T)pa.omega;
+        u.p_rich = pa.p;
+    }
     if constexpr (std::is_same<T, double>::value)
         return launch_update(P.hist, &u, nullptr, P.upd_blocks, s);
     else
@@ -668,6 +684,12 @@ template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool 
     stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], P.ts, &tx, &ty, &tz, &blocks, paired_fk);
     P.rho_blocks = blocks;
     P.gram_fused = gram_fusable(P.ts, paired_fk, S->params.m, f64, P.hist);
+    // Residual recursion (FP64 iterate and ring, paired layout): within a
+    // cycle, f_{j+1} = f_j - omega D^-1 A f_j from the ring, no x or b traffic;
+    // the ring must hold the cycle's p f's, so m + 1 >= p
+    P.recur = f64 && !S->mixed && P.hist == Prec::F64 && paired_fk &&
+              paired_layout(P.ts, op.prob.n[0], P.conv, kSweep) && S->params.p >= 2 &&
+              S->params.m + 1 >= S->params.p;
     P.gram_blocks = gram_blocks(op.N, S->params.m);
     P.upd_blocks = stream_blocks(op.N);
     P.slot_stride = S->slot_stride[f64 ? 0 : 1];
@@ -905,6 +927,20 @@ aar_status solve_one(aar_solver_t *S, int idx, const double *b, double *x, aar_r
         aar_status e = run_cycles<double>(S, P, pa.max_iter, false, use_graph, &st);
         if (e != AAR_OK)
             return e;
+        if (P.recur) {
+            // the sweeps wrote no x: add the unfinished cycle's Richardson steps
+            AAR_HIP(launch_finalize_f64(P.xa, P.fring, S->state, pa.p, pa.m + 1, P.slot_stride, pa.omega, N, s));
+            AAR_HIP(hipMemcpyAsync(x, P.xa, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+            AAR_HIP(hipStreamSynchronize(s));
+            r.status = status_of(st);
+            r.iterations = (st.status == kMaxIter || st.status == kRunning) ? pa.max_iter : st.iters;
+            r.rel_residual = st.last_r;
+            r.outer_steps = 0;
+            S->last_log_count[idx] = st.log_count;
+            if (res)
+                *res = r;
+            return (aar_status)r.status;
+        }
         // where x ended: after j sweeps of a cycle it is in xb when j is odd
         const int64_t done = (st.status == kMaxIter || st.status == kRunning) ? pa.max_iter : st.iters;
         const int64_t j = (done - 1) % pa.p;     // last iteration's position in its cycle

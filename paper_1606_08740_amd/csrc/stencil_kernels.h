@@ -423,6 +423,14 @@ __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, 
     const int nz = z1 - z0;
     const int64_t plane = (int64_t)st.n0 * st.n1;
     H *fout = reinterpret_cast<H *>(a.fring) + (int64_t)(k % a.nslots) * a.slot_stride;
+    // the stencil's input: x, or f_{k-1} from the ring for the recursion
+    bool recur = false;
+    const T *xin = a.x;
+    if constexpr (std::is_same<T, H>::value) {
+        recur = a.recur != 0;
+        if (recur)
+            xin = reinterpret_cast<const T *>(a.fring) + (int64_t)((k - 1) % a.nslots) * a.slot_stride;
+    }
 
     // offset of this thread's pair in each of its rows (-1: outside a
     // Dirichlet boundary).  n0 is even, so a pair is never split by the
@@ -494,7 +502,7 @@ __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, 
     };
     auto ld2 = [&](int off, int zp) -> V {
         if (off >= 0 && zp >= 0)
-            return *reinterpret_cast<const V *>(a.x + off + plane * zp);
+            return *reinterpret_cast<const V *>(xin + off + plane * zp);
         V v;
         v.x = T(0);
         v.y = T(0);
@@ -512,42 +520,56 @@ __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, 
             q[r][1][d] = v.y;
         }
 
-    V front[RY], bv[RY];
-    T hv[NH];
-    auto fetch = [&](int i) {
+    // Loads of plane i (front plane of the z queue, halo cells, b) are issued
+    // ahead of its step, into register set i mod NB.  With an FP64 iterate and
+    // ring NB = 2: they go two plane steps ahead, so each has two steps of taps
+    // to arrive (the z loop is unrolled by two so that both sets keep fixed
+    // registers); the narrower types, which rely on more resident workgroups
+    // instead, go one step ahead into one set.
+    constexpr int NB = sizeof(T) == 8 && sizeof(H) == 8 ? 2 : 1;
+    V front[NB][RY], bv[NB][RY];
+    T hv[NB][NH];
+    auto fetch = [&](int i, int u) {
         const int z = zs + dir * i;
         const int zf = zplane(z + dir * R);
 #pragma unroll
         for (int r = 0; r < RY; ++r)
-            front[r] = ld2(coff[r], zf);
+            front[u][r] = ld2(coff[r], zf);
 #pragma unroll
         for (int j = 0; j < NH; ++j)
-            hv[j] = hoff[j] >= 0 ? a.x[hoff[j] + plane * z] : T(0);
+            hv[u][j] = hoff[j] >= 0 ? xin[hoff[j] + plane * z] : T(0);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            if (own[r]) {
-                bv[r] = *reinterpret_cast<const V *>(a.b + coff[r] + plane * z);
+            if (own[r] && !recur) {
+                bv[u][r] = *reinterpret_cast<const V *>(a.b + coff[r] + plane * z);
             } else {
-                bv[r].x = T(0);
-                bv[r].y = T(0);
+                bv[u][r].x = T(0);
+                bv[u][r].y = T(0);
             }
         }
     };
-    if (nz > 0)
-        fetch(0);
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+        if (u < nz)
+            fetch(u, u);
 
     double acc = 0.0;
-    for (int i = 0; i < nz; ++i) {
+    for (int i0 = 0; i0 < nz; i0 += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int i = i0 + u;
+        if (NB > 1 && i >= nz)
+            break;
         const int z = zs + dir * i;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            q[r][0][2 * R] = front[r].x;
-            q[r][1][2 * R] = front[r].y;
+            q[r][0][2 * R] = front[u][r].x;
+            q[r][1][2 * R] = front[u][r].y;
         }
         V bcur[RY];
 #pragma unroll
         for (int r = 0; r < RY; ++r)
-            bcur[r] = bv[r];
+            bcur[r] = bv[u][r];
         __syncthreads();   // the previous plane's taps have been read
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
@@ -559,10 +581,10 @@ __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, 
 #pragma unroll
         for (int j = 0; j < NH; ++j)
             if (hlds[j] >= 0)
-                (&sh[0][0])[hlds[j]] = hv[j];
+                (&sh[0][0])[hlds[j]] = hv[u][j];
         __syncthreads();
-        if (i + 1 < nz)
-            fetch(i + 1);
+        if (i + NB < nz)
+            fetch(i + NB, u);   // set u's plane is in the queue, LDS and bcur now
 
         T ax[RY][2];
         // x taps: the 2 RP + 2 values from column 2 lx2 hold x - RP .. x + 1 + RP
@@ -637,14 +659,27 @@ __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, 
             if (!own[r])
                 continue;
             const int64_t id = coff[r] + plane * z;
-            const T r0 = bcur[r].x - ax[r][0], r1 = bcur[r].y - ax[r][1];
-            const T f0 = r0 * st.inv_diag, f1 = r1 * st.inv_diag;
+            T r0, r1, f0, f1;
+            if (recur) {
+                // f_k = f_{k-1} - omega D^-1 A f_{k-1}; b - A x_k = D f_k
+                f0 = q[r][0][R] - a.omega * (st.inv_diag * ax[r][0]);
+                f1 = q[r][1][R] - a.omega * (st.inv_diag * ax[r][1]);
+                r0 = st.diag * f0;
+                r1 = st.diag * f1;
+            } else {
+                r0 = bcur[r].x - ax[r][0];
+                r1 = bcur[r].y - ax[r][1];
+                f0 = r0 * st.inv_diag;
+                f1 = r1 * st.inv_diag;
+            }
             Hist<H>::store2(fout, id, f0, f1);
             if constexpr (MODE == kSweep) {
-                V o;
-                o.x = q[r][0][R] + a.omega * f0;
-                o.y = q[r][1][R] + a.omega * f1;
-                *reinterpret_cast<V *>(a.out + id) = o;
+                if (a.out) {
+                    V o;
+                    o.x = q[r][0][R] + a.omega * f0;
+                    o.y = q[r][1][R] + a.omega * f1;
+                    *reinterpret_cast<V *>(a.out + id) = o;
+                }
             } else {
                 if (a.fcur) {
                     V o;
@@ -687,6 +722,7 @@ __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, 
 #pragma unroll
                 for (int d = 0; d < 2 * R; ++d)
                     q[r][e][d] = q[r][e][d + 1];
+    }
     }
 
     if constexpr (MODE == kFk) {
