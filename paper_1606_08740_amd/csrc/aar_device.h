@@ -148,7 +148,7 @@ template <typename T> struct StencilArgs {
     int32_t order;          // kOrder* bits: tile numbering and z direction
     T omega;
     double *gram_partial;   // kFk, paired layout, m = kFusedGramM: [ne][blocks] Gram partials, else null
-    // kSweep / kFk, paired layout, ring type T: the residual recursion of
+    // kSweep / kFk, ring type T (either layout): the residual recursion of
     // Richardson steps.  The input is ring slot k - 1 (f_{k-1}) instead of x,
     // b is not read, f_k = f_{k-1} - omega D^-1 A f_{k-1}, and kFk's norm is
     // that of D f_k (= b - A x_k); kSweep then writes no x (out may be null).

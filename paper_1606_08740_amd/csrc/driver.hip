@@ -684,12 +684,10 @@ template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool 
     stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], P.ts, &tx, &ty, &tz, &blocks, paired_fk);
     P.rho_blocks = blocks;
     P.gram_fused = gram_fusable(P.ts, paired_fk, S->params.m, f64, P.hist);
-    // Residual recursion (FP64 iterate and ring, paired layout): within a
-    // cycle, f_{j+1} = f_j - omega D^-1 A f_j from the ring, no x or b traffic;
-    // the ring must hold the cycle's p f's, so m + 1 >= p
-    P.recur = f64 && !S->mixed && P.hist == Prec::F64 && paired_fk &&
-              paired_layout(P.ts, op.prob.n[0], P.conv, kSweep) && S->params.p >= 2 &&
-              S->params.m + 1 >= S->params.p;
+    // Residual recursion (FP64 iterate and ring): within a cycle,
+    // f_{j+1} = f_j - omega D^-1 A f_j from the ring, no x or b traffic; the
+    // ring must hold the cycle's p f's, so m + 1 >= p
+    P.recur = f64 && !S->mixed && P.hist == Prec::F64 && S->params.p >= 2 && S->params.m + 1 >= S->params.p;
     P.gram_blocks = gram_blocks(op.N, S->params.m);
     P.upd_blocks = stream_blocks(op.N);
     P.slot_stride = S->slot_stride[f64 ? 0 : 1];

@@ -110,6 +110,14 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs<T> &a, int lin, d
     H *fout = nullptr;
     if constexpr (MODE == kSweep || MODE == kFk)
         fout = reinterpret_cast<H *>(a.fring) + (int64_t)(k % a.nslots) * a.slot_stride;
+    // the stencil's input: x, or f_{k-1} from the ring for the recursion
+    bool recur = false;
+    const T *xin = a.x;
+    if constexpr (std::is_same<T, H>::value && (MODE == kSweep || MODE == kFk)) {
+        recur = a.recur != 0;
+        if (recur)
+            xin = reinterpret_cast<const T *>(a.fring) + (int64_t)((k - 1) % a.nslots) * a.slot_stride;
+    }
 
     // In-plane offsets (boundary rule applied; -1: outside a Dirichlet
     // boundary, value 0) of this thread's columns and of its halo cells.
@@ -176,7 +184,7 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs<T> &a, int lin, d
             return st.per2 ? wrap_index(z, st.n2) : -1;
         return z;
     };
-    auto ld = [&](int off, int zp) -> T { return (off >= 0 && zp >= 0) ? a.x[off + plane * zp] : T(0); };
+    auto ld = [&](int off, int zp) -> T { return (off >= 0 && zp >= 0) ? xin[off + plane * zp] : T(0); };
 
     // z-queue: q[ry][d] = x at plane z + dir (d - R) of this thread's column
     T q[RY][2 * R + 1];
@@ -208,7 +216,7 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs<T> &a, int lin, d
         if constexpr (MODE != kApply) {
 #pragma unroll
             for (int ry = 0; ry < RY; ++ry)
-                bv[u][ry] = own[ry] ? a.b[coff[ry] + plane * z] : T(0);
+                bv[u][ry] = own[ry] && !recur ? a.b[coff[ry] + plane * z] : T(0);
         }
         if constexpr (CONV) {
 #pragma unroll
@@ -285,21 +293,28 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs<T> &a, int lin, d
             }
             if constexpr (MODE == kApply) {
                 a.out[id] = ax;
-            } else {
+            } else if constexpr (MODE == kResid) {
                 const T res = bcur[ry] - ax;
-                if constexpr (MODE == kResid) {
-                    a.out[id] = res;
-                    acc += (double)res * (double)res;
+                a.out[id] = res;
+                acc += (double)res * (double)res;
+            } else {
+                T f, res;
+                if (recur) {
+                    // f_k = f_{k-1} - omega D^-1 A f_{k-1}; b - A x_k = D f_k
+                    f = c - a.omega * (CONV ? ax / dg : ax * st.inv_diag);
+                    res = dg * f;
                 } else {
-                    const T f = CONV ? res / dg : res * st.inv_diag;
-                    Hist<H>::store(fout, id, f);
-                    if constexpr (MODE == kSweep) {
+                    res = bcur[ry] - ax;
+                    f = CONV ? res / dg : res * st.inv_diag;
+                }
+                Hist<H>::store(fout, id, f);
+                if constexpr (MODE == kSweep) {
+                    if (a.out)
                         a.out[id] = c + a.omega * f;
-                    } else {
-                        if (a.fcur)
-                            a.fcur[id] = f;
-                        acc += (double)res * (double)res;
-                    }
+                } else {
+                    if (a.fcur)
+                        a.fcur[id] = f;
+                    acc += (double)res * (double)res;
                 }
             }
         }
@@ -791,6 +806,7 @@ __global__ __launch_bounds__(kThreads) void k_stencil_batched(const BatchStencil
         a.order = 0;
         a.omega = ba.omega;
         a.gram_partial = nullptr;
+        a.recur = 0;
         if constexpr (MODE == kResid) {
             if (!ba.mask || ba.mask[it.x] == 0)
                 continue;

@@ -154,9 +154,13 @@ def test_batched_engine_equals_single_solves():
     xs, res, _ = _run_batch(probs, bs, prm)
     for i, (p, bi) in enumerate(zip(probs, bs)):
         x1, r1, _ = gpu_solve(p, prm, bi)
-        # same arithmetic per point; reductions are summed in a different
-        # order, so answers agree within the conditioning bound kappa * tol
-        assert res[i]["iterations"] == r1["iterations"]
+        # a single FP64 solve forms the residuals of a cycle's later Richardson
+        # steps by the recursion f_{j+1} = f_j - omega D^-1 A f_j, the batched
+        # engine from x and b: the same iteration in exact arithmetic, with
+        # reductions also summed in a different order, so the convergence
+        # decision may fall one cycle apart and the answers agree within the
+        # conditioning bound kappa * tol
+        assert abs(res[i]["iterations"] - r1["iterations"]) <= prm.p
         assert rel_err(xs[i], x1) < 1e-7
 
 
