@@ -188,6 +188,7 @@ template <typename T> struct BatchStencilArgs {
     int64_t slot_stride;
     int32_t j, p, nslots;
     T omega;
+    int32_t recur;           // kSweep / kFk: the residual recursion (see StencilArgs)
 };
 
 // ---- batched driver ----
@@ -259,11 +260,13 @@ template <typename T> struct BatchUpdateArgs {
     void *dxring;           // DxOf<T, H> elements
     int64_t slot_stride;
     int64_t dx_stride;
+    T omega_rich = 0;       // residual recursion: as in UpdateArgs
+    int32_t p_rich = 0;
 };
 
 enum : int32_t {
     kOpGather = 0, kOpScatter = 1, kOpNorm = 2, kOpSum = 3, kOpCorrect = 4, kOpDeflate = 5, kOpPrepare = 6,
-    kOpZero64 = 7, kOpScatterSel = 8,
+    kOpZero64 = 7, kOpScatterSel = 8, kOpScatterRecur = 9,
 };
 
 struct BatchStreamArgs {
@@ -284,6 +287,13 @@ struct BatchStreamArgs {
     float *rhs32;
     const double *inv_shift;
     double *partial;         // per item, or null
+    // kOpScatterRecur: the answer of a run that used the residual recursion,
+    // x64 plus omega times the Richardson f of the system's unfinished cycle
+    const InstState *state;
+    const double *fring;
+    int64_t slot_stride;
+    int32_t p, nslots;
+    double omega;
 };
 
 enum : int32_t { kCtlSelect = 0, kCtlNormB = 1, kCtlMean = 2, kCtlDecide = 3, kCtlStart = 4 };

@@ -276,6 +276,9 @@ __global__ __launch_bounds__(kThreads) void k_update_batched(const BatchUpdateAr
         }
         __syncthreads();
         const int nf = nf_s, nd = nd_s;
+        // residual recursion: positions tr0 .. nf - 2 are the cycle's Richardson steps
+        const int tr0 = a.p_rich > 0 ? nf - a.p_rich : nf;
+        const int t1 = tr0 < nf - 1 ? tr0 : nf - 1;
         D *dxw = ws_s >= 0 ? reinterpret_cast<D *>(a.dxring) + off + (int64_t)ws_s * a.dx_stride : nullptr;
         const T *xin = a.xin + off;
         T *xout = a.xout + off;
@@ -285,15 +288,26 @@ __global__ __launch_bounds__(kThreads) void k_update_batched(const BatchUpdateAr
         const int64_t hi = lo + kChunk < N ? lo + kChunk : N;
         const int64_t vhi = lo + (hi - lo) / V * V;
         for (int64_t i = lo + (int64_t)threadIdx.x * V; i < vhi; i += (int64_t)blockDim.x * V) {
-            T d[V];
+            T d[V], dr[V];
 #pragma unroll
-            for (int u = 0; u < V; ++u)
+            for (int u = 0; u < V; ++u) {
                 d[u] = T(0);
-            for (int t = 0; t < nf - 1; ++t) {
+                dr[u] = T(0);
+            }
+            for (int t = 0; t < t1; ++t) {
                 const Pack<H, V> h = *reinterpret_cast<const Pack<H, V> *>(fs[t] + i);
 #pragma unroll
                 for (int u = 0; u < V; ++u)
                     d[u] += al[t] * (T)Hist<H>::load(h.v, u);
+            }
+            for (int t = t1; t < nf - 1; ++t) {
+                const Pack<H, V> h = *reinterpret_cast<const Pack<H, V> *>(fs[t] + i);
+#pragma unroll
+                for (int u = 0; u < V; ++u) {
+                    const T fv = (T)Hist<H>::load(h.v, u);
+                    d[u] += al[t] * fv;
+                    dr[u] += fv;
+                }
             }
             T fk[V];
             if (fk_ptr) {
@@ -316,27 +330,32 @@ __global__ __launch_bounds__(kThreads) void k_update_batched(const BatchUpdateAr
                 for (int u = 0; u < V; ++u)
                     d[u] += de[t] * (T)h.v[u];
             }
-            const Pack<T, V> xk = *reinterpret_cast<const Pack<T, V> *>(xin + i);
+            const Pack<T, V> xc = *reinterpret_cast<const Pack<T, V> *>(xin + i);
             Pack<T, V> xn;
             Pack<D, V> dx;
 #pragma unroll
             for (int u = 0; u < V; ++u) {
-                xn.v[u] = xk.v[u] + d[u];
-                dx.v[u] = (D)(xn.v[u] - xk.v[u]);
+                const T xk = xc.v[u] + a.omega_rich * dr[u];
+                xn.v[u] = xk + d[u];
+                dx.v[u] = (D)(xn.v[u] - xk);
             }
             *reinterpret_cast<Pack<T, V> *>(xout + i) = xn;
             if (dxw)
                 *reinterpret_cast<Pack<D, V> *>(dxw + i) = dx;
         }
         for (int64_t i = vhi + threadIdx.x; i < hi; i += blockDim.x) {
-            T d = 0;
-            for (int t = 0; t < nf - 1; ++t)
-                d += al[t] * (T)Hist<H>::load(fs[t], i);
+            T d = 0, dr = 0;
+            for (int t = 0; t < nf - 1; ++t) {
+                const T fv = (T)Hist<H>::load(fs[t], i);
+                d += al[t] * fv;
+                if (t >= t1)
+                    dr += fv;
+            }
             const T fk = fk_ptr ? fk_ptr[i] : (T)Hist<H>::load(fs[nf - 1], i);
             d += al[nf - 1] * fk;
             for (int t = 0; t < nd; ++t)
                 d += de[t] * (T)ds[t][i];
-            const T xk = xin[i];
+            const T xk = xin[i] + a.omega_rich * dr;
             const T xn = xk + d;
             xout[i] = xn;
             if (dxw)
@@ -428,6 +447,21 @@ __global__ __launch_bounds__(kThreads) void k_stream_batched(const BatchStreamAr
             case kOpScatterSel:
                 a.user[a.uoffs[sys] + i] = c.zero ? 0.0 : (c.dsel ? a.x64 : a.v64)[off + i];
                 break;
+            case kOpScatterRecur: {
+                // x at the end of the run: the cycle-start iterate plus omega
+                // times the f's of the Richardson steps taken in the last cycle
+                const InstState &st = a.state[sys];
+                double v = a.v64[off + i];
+                if (st.status != kRunning) {
+                    const int64_t base = st.cycle * a.p;
+                    int64_t n = (st.status == kMaxIter ? st.iters : st.iters - 1) - base;
+                    n = n < a.p - 1 ? n : a.p - 1;
+                    for (int64_t k = 0; k < n; ++k)
+                        v += a.omega * a.fring[((base + k) % a.nslots) * a.slot_stride + off + i];
+                }
+                a.user[a.uoffs[sys] + i] = c.zero ? 0.0 : v;
+                break;
+            }
             case kOpNorm: {
                 const double v = a.v64[off + i];
                 acc += v * v;

@@ -254,6 +254,7 @@ struct aar_solver_t {
         double *log = nullptr;
         hipGraphExec_t graph = nullptr;
         int *h_remaining = nullptr;
+        bool recur = false;     // FP64 cycles use the residual recursion
     } B;
 
     template <typename T> T *alloc(size_t count, aar_status *st)
@@ -1218,6 +1219,8 @@ aar_status batch_setup(aar_solver_t *S)
     if (st != AAR_OK)
         return st;
     if (!S->mixed) {
+        // as for one system: the recursion needs the FP64 ring to hold a cycle's p f's
+        B.recur = S->hist == Prec::F64 && S->params.p >= 2 && S->params.m + 1 >= S->params.p;
         B.xa64 = S->alloc<double>(total, &st);
         B.xb64 = S->alloc<double>(total, &st);
         B.b64 = S->alloc<double>(total, &st);
@@ -1370,10 +1373,20 @@ template <typename T> hipError_t batch_enqueue_cycle(aar_solver_t *S, hipStream_
     a.omega = (T)pa.omega;
     hipError_t e;
     const Prec hist = S->hist;   // history storage of this path (F64 for the plain FP64 solve)
+    // residual recursion (FP64): the first sweep forms f from x and b and
+    // leaves x alone; later sweeps and the Anderson-step residual follow
+    // f_{j+1} = f_j - omega D^-1 A f_j from the ring; x stays in xa and the
+    // update adds the cycle's Richardson steps
+    const bool recur = f64 && B.recur;
     for (int j = 0; j < pa.p - 1; ++j) {
         a.j = j;
         a.x = (j & 1) ? xb : xa;
         a.out = (j & 1) ? xa : xb;
+        if (recur) {
+            a.x = xa;
+            a.out = nullptr;
+            a.recur = j > 0;
+        }
         if constexpr (std::is_same<T, double>::value)
             e = launch_stencil_batched_f64(kSweep, hist, B.radius, B.conv, B.ry, a, B.grid_s, s);
         else
@@ -1382,7 +1395,8 @@ template <typename T> hipError_t batch_enqueue_cycle(aar_solver_t *S, hipStream_
             return e;
     }
     const int jk = pa.p - 1;
-    T *xk = (jk & 1) ? xb : xa;
+    T *xk = recur ? xa : (jk & 1) ? xb : xa;
+    a.recur = recur && jk > 0;
     a.j = jk;
     a.x = xk;
     a.out = nullptr;
@@ -1448,6 +1462,8 @@ template <typename T> hipError_t batch_enqueue_cycle(aar_solver_t *S, hipStream_
     u.dxring = dx;
     u.slot_stride = B.stride;
     u.dx_stride = B.stride;
+    u.omega_rich = recur ? (T)pa.omega : T(0);
+    u.p_rich = recur ? pa.p : 0;
     if constexpr (std::is_same<T, double>::value)
         return launch_update_batched(hist, &u, nullptr, B.grid_c, s);
     else
@@ -1617,10 +1633,17 @@ aar_status batch_solve(aar_solver_t *S, const double *b, double *x, const int64_
     }
     // write the answers back in the caller's layout
     AAR_HIPE(launch_compact(batch_compact_args(S, 2, false), s));
-    BatchStreamArgs sc = batch_stream(S, S->mixed ? kOpScatter : kOpScatterSel, nullptr, 0);
+    BatchStreamArgs sc = batch_stream(S, S->mixed ? kOpScatter : B.recur ? kOpScatterRecur : kOpScatterSel,
+                                      nullptr, 0);
     sc.user = x;
     sc.v64 = x64;
     sc.x64 = B.xb64;
+    sc.state = B.state;
+    sc.fring = static_cast<const double *>(B.fring);
+    sc.slot_stride = B.stride;
+    sc.p = pa.p;
+    sc.nslots = pa.m + 1;
+    sc.omega = pa.omega;
     AAR_HIPE(launch_stream_batched(sc, B.grid_c, s));
     std::vector<BatchCtl> ctl(count);
     std::vector<InstState> sts(count);

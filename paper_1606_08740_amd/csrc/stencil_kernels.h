@@ -806,7 +806,7 @@ __global__ __launch_bounds__(kThreads) void k_stencil_batched(const BatchStencil
         a.order = 0;
         a.omega = ba.omega;
         a.gram_partial = nullptr;
-        a.recur = 0;
+        a.recur = ba.recur;
         if constexpr (MODE == kResid) {
             if (!ba.mask || ba.mask[it.x] == 0)
                 continue;

@@ -154,14 +154,33 @@ def test_batched_engine_equals_single_solves():
     xs, res, _ = _run_batch(probs, bs, prm)
     for i, (p, bi) in enumerate(zip(probs, bs)):
         x1, r1, _ = gpu_solve(p, prm, bi)
-        # a single FP64 solve forms the residuals of a cycle's later Richardson
-        # steps by the recursion f_{j+1} = f_j - omega D^-1 A f_j, the batched
-        # engine from x and b: the same iteration in exact arithmetic, with
-        # reductions also summed in a different order, so the convergence
+        # both follow the same iteration (with the residual recursion inside
+        # each cycle), but the batched engine lays the tiles and reductions
+        # out differently, so sums round in another order: the convergence
         # decision may fall one cycle apart and the answers agree within the
         # conditioning bound kappa * tol
         assert abs(res[i]["iterations"] - r1["iterations"]) <= prm.p
         assert rel_err(xs[i], x1) < 1e-7
+
+
+def test_batched_engine_iterates_match_oracle():
+    """Iteration caps inside and at the end of a cycle: every system of the
+    batch stops at iterate x_K, the one the oracle reaches after K steps
+    (Sec. 2, Eqs. 2-3); the caps inside a cycle check that the answer adds the
+    cycle's Richardson steps taken so far."""
+    sizes = [17, 24, 16, 31]
+    shifts = [1.5, 0.4, 6.0, 2.5]
+    probs, bs = _helmholtz_batch(sizes, shifts, seed=110)
+    m, p = 7, 6
+    for K in (1, p - 1, p, p + 1, 3 * p + 2):
+        prm = inputs.Params(tol=1e-30, max_iter=K, m=m, p=p, precision=0)
+        say(f"batched iterates K={K}")
+        xs, res, _ = _run_batch(probs, bs, prm)
+        for i, (pr, bi) in enumerate(zip(probs, bs)):
+            assert res[i]["status"] == aar.AAR_NOT_CONVERGED and res[i]["iterations"] == K, (K, i, res[i])
+            ref = oracle.aar_solve(pr, bi, m=m, p=p, tol=1e-30, max_iter=K)["x"]
+            np.testing.assert_allclose(xs[i], ref, rtol=0, atol=1e-10 * np.abs(ref).max(),
+                                       err_msg=f"K={K} system {i}")
 
 
 def test_batched_engine_edge_systems():
