@@ -817,4 +817,12 @@ hipError_t launch_finalize_f64(double *x, const void *fring, const InstState *st
     return hipGetLastError();
 }
 
+hipError_t launch_finalize_f32(float *x, const void *fring, const InstState *state, int p, int nslots,
+                               int64_t slot_stride, float omega, int64_t N, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_finalize<float, float>), dim3(stream_blocks(N)), dim3(kThreads), 0, s, x, fring, state,
+                       p, nslots, slot_stride, omega, N);
+    return hipGetLastError();
+}
+
 }  // namespace aar

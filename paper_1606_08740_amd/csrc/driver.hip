@@ -685,10 +685,12 @@ template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool 
     stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], P.ts, &tx, &ty, &tz, &blocks, paired_fk);
     P.rho_blocks = blocks;
     P.gram_fused = gram_fusable(P.ts, paired_fk, S->params.m, f64, P.hist);
-    // Residual recursion (FP64 iterate and ring): within a cycle,
+    // Residual recursion (iterate and ring of one type: FP64, or FP32 in the
+    // inner solves of the mixed mode): within a cycle,
     // f_{j+1} = f_j - omega D^-1 A f_j from the ring, no x or b traffic; the
     // ring must hold the cycle's p f's, so m + 1 >= p
-    P.recur = f64 && !S->mixed && P.hist == Prec::F64 && S->params.p >= 2 && S->params.m + 1 >= S->params.p;
+    P.recur = (f64 ? !S->mixed && P.hist == Prec::F64 : S->mixed && P.hist == Prec::F32) && S->params.p >= 2 &&
+              S->params.m + 1 >= S->params.p;
     P.gram_blocks = gram_blocks(op.N, S->params.m);
     P.upd_blocks = stream_blocks(op.N);
     P.slot_stride = S->slot_stride[f64 ? 0 : 1];
@@ -1044,7 +1046,12 @@ aar_status solve_one(aar_solver_t *S, int idx, const double *b, double *x, aar_r
         const int64_t j = (done - 1) % pa.p;
         const bool anderson_last = (st.status == kMaxIter || st.status == kRunning) && j == pa.p - 1;
         const float *df;
-        if (st.status == kConverged || st.status == kStagnated)
+        if (P.recur) {
+            // the sweeps wrote no x: add the unfinished cycle's Richardson steps
+            AAR_HIP(launch_finalize_f32(P.xa, P.fring, S->state, pa.p, pa.m + 1, P.slot_stride, (float)pa.omega, N,
+                                        s));
+            df = P.xa;
+        } else if (st.status == kConverged || st.status == kStagnated)
             df = ((pa.p - 1) & 1) ? P.xb : P.xa;
         else if (anderson_last)
             df = P.xa;
