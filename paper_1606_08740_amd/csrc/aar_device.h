@@ -287,13 +287,16 @@ struct BatchStreamArgs {
     float *rhs32;
     const double *inv_shift;
     double *partial;         // per item, or null
-    // kOpScatterRecur: the answer of a run that used the residual recursion,
-    // x64 plus omega times the Richardson f of the system's unfinished cycle
+    // runs that used the residual recursion: their answer is the cycle-start
+    // iterate plus omega times the Richardson f of the unfinished cycle
+    // (kOpScatterRecur: FP64 v64 and ring; kOpCorrect with recur set: FP32
+    // xa32 and ring)
     const InstState *state;
-    const double *fring;
+    const void *fring;
     int64_t slot_stride;
     int32_t p, nslots;
     double omega;
+    int32_t recur;
 };
 
 enum : int32_t { kCtlSelect = 0, kCtlNormB = 1, kCtlMean = 2, kCtlDecide = 3, kCtlStart = 4 };

@@ -415,10 +415,23 @@ __device__ inline int final_buffer(const InstState &st, int p)
 //   kOpScatter  dst_user[uoff + i] = x_packed[i]            (FP64 out)
 //   kOpNorm     partial = sum v^2                            (v FP64)
 //   kOpSum      partial = sum v                              (v FP64)
-//   kOpCorrect  x64 += rnorm * d32 (d from xa32/xb32 by dsel)
+//   kOpCorrect  x64 += rnorm * d32 (d from xa32/xb32 by dsel; with the
+//               residual recursion xa32 + omega * the unfinished cycle's f)
+//   kOpScatterSel / kOpScatterRecur   as kOpScatter from the run's final
+//               buffer / plus omega * the unfinished cycle's f (FP64)
 //   kOpDeflate  x64 += mean / sigma; r64 -= mean; partial = ||r64||^2
 //   kOpPrepare  rhs32 = r64 / rnorm; xa32 = 0; partial = ||rhs32||^2
 //   kOpZero64   v = 0
+// Residual recursion: number of Richardson steps of the run's last cycle
+// that the cycle-start iterate does not include yet (0 while running).
+__device__ inline int64_t pending_steps(const InstState &st, int p)
+{
+    if (st.status == kRunning)
+        return 0;
+    const int64_t n = (st.status == kMaxIter ? st.iters : st.iters - 1) - st.cycle * p;
+    return n < p - 1 ? n : p - 1;
+}
+
 __global__ __launch_bounds__(kThreads) void k_stream_batched(const BatchStreamArgs a)
 {
     __shared__ double red[kThreads / 64];
@@ -451,14 +464,11 @@ __global__ __launch_bounds__(kThreads) void k_stream_batched(const BatchStreamAr
                 // x at the end of the run: the cycle-start iterate plus omega
                 // times the f's of the Richardson steps taken in the last cycle
                 const InstState &st = a.state[sys];
+                const double *ring = static_cast<const double *>(a.fring);
+                const int64_t base = st.cycle * a.p, n = pending_steps(st, a.p);
                 double v = a.v64[off + i];
-                if (st.status != kRunning) {
-                    const int64_t base = st.cycle * a.p;
-                    int64_t n = (st.status == kMaxIter ? st.iters : st.iters - 1) - base;
-                    n = n < a.p - 1 ? n : a.p - 1;
-                    for (int64_t k = 0; k < n; ++k)
-                        v += a.omega * a.fring[((base + k) % a.nslots) * a.slot_stride + off + i];
-                }
+                for (int64_t k = 0; k < n; ++k)
+                    v += a.omega * ring[((base + k) % a.nslots) * a.slot_stride + off + i];
                 a.user[a.uoffs[sys] + i] = c.zero ? 0.0 : v;
                 break;
             }
@@ -471,8 +481,19 @@ __global__ __launch_bounds__(kThreads) void k_stream_batched(const BatchStreamAr
                 acc += a.v64[off + i];
                 break;
             case kOpCorrect: {
-                const float *d = c.dsel ? a.xb32 : a.xa32;
-                a.v64[off + i] += c.rnorm * (double)d[off + i];
+                float d;
+                if (a.recur) {
+                    const InstState &st = a.state[sys];
+                    const float *ring = static_cast<const float *>(a.fring);
+                    const float om = (float)a.omega;
+                    const int64_t base = st.cycle * a.p, n = pending_steps(st, a.p);
+                    d = a.xa32[off + i];
+                    for (int64_t k = 0; k < n; ++k)
+                        d += om * ring[((base + k) % a.nslots) * a.slot_stride + off + i];
+                } else {
+                    d = (c.dsel ? a.xb32 : a.xa32)[off + i];
+                }
+                a.v64[off + i] += c.rnorm * (double)d;
                 break;
             }
             case kOpDeflate: {

@@ -1225,9 +1225,11 @@ aar_status batch_setup(aar_solver_t *S)
     B.p_c = S->alloc<double>(B.sum_chunks, &st);
     if (st != AAR_OK)
         return st;
+    // as for one system: the recursion needs a ring of the iterate's type
+    // (FP64, or FP32 for mixed inner solves) that holds a cycle's p f's
+    B.recur = (S->mixed ? S->hist == Prec::F32 : S->hist == Prec::F64) && S->params.p >= 2 &&
+              S->params.m + 1 >= S->params.p;
     if (!S->mixed) {
-        // as for one system: the recursion needs the FP64 ring to hold a cycle's p f's
-        B.recur = S->hist == Prec::F64 && S->params.p >= 2 && S->params.m + 1 >= S->params.p;
         B.xa64 = S->alloc<double>(total, &st);
         B.xb64 = S->alloc<double>(total, &st);
         B.b64 = S->alloc<double>(total, &st);
@@ -1380,11 +1382,11 @@ template <typename T> hipError_t batch_enqueue_cycle(aar_solver_t *S, hipStream_
     a.omega = (T)pa.omega;
     hipError_t e;
     const Prec hist = S->hist;   // history storage of this path (F64 for the plain FP64 solve)
-    // residual recursion (FP64): the first sweep forms f from x and b and
-    // leaves x alone; later sweeps and the Anderson-step residual follow
+    // residual recursion: the first sweep forms f from x and b and leaves x
+    // alone; later sweeps and the Anderson-step residual follow
     // f_{j+1} = f_j - omega D^-1 A f_j from the ring; x stays in xa and the
     // update adds the cycle's Richardson steps
-    const bool recur = f64 && B.recur;
+    const bool recur = B.recur;
     for (int j = 0; j < pa.p - 1; ++j) {
         a.j = j;
         a.x = (j & 1) ? xb : xa;
@@ -1548,6 +1550,13 @@ aar_status batch_solve(aar_solver_t *S, const double *b, double *x, const int64_
                 c.v64 = x64;
                 c.xa32 = B.xa32;
                 c.xb32 = B.xb32;
+                c.recur = B.recur ? 1 : 0;
+                c.state = B.state;
+                c.fring = B.fring;
+                c.slot_stride = B.stride;
+                c.p = pa.p;
+                c.nslots = pa.m + 1;
+                c.omega = pa.omega;
                 AAR_HIPE(launch_stream_batched(c, B.grid_c, s));
             }
             if ((e = batch_residual(S, x64, B.b64, B.r64)) != AAR_OK)
@@ -1646,7 +1655,7 @@ aar_status batch_solve(aar_solver_t *S, const double *b, double *x, const int64_
     sc.v64 = x64;
     sc.x64 = B.xb64;
     sc.state = B.state;
-    sc.fring = static_cast<const double *>(B.fring);
+    sc.fring = B.fring;
     sc.slot_stride = B.stride;
     sc.p = pa.p;
     sc.nslots = pa.m + 1;

@@ -44,6 +44,32 @@ def test_mixed_reaches_fp64_tolerance(name, make, cmp):
     assert rel_err(a, r) < 1e-6
 
 
+MIXED_CAP_CASES = [
+    ("dirichlet_r1_32", lambda: inputs.dirichlet_poisson_problem(32)),
+    ("dirichlet_r1_27_odd", lambda: inputs.dirichlet_poisson_problem(27)),
+    ("periodic_r6_30", lambda: inputs.periodic_problem(30, 6, shift=0.5)),
+]
+
+
+@pytest.mark.parametrize("name,make", MIXED_CAP_CASES, ids=[c[0] for c in MIXED_CAP_CASES])
+def test_mixed_inner_iterates_match_oracle(name, make):
+    """An iteration cap inside and at the end of a cycle stops the first inner
+    FP32 solve at its iterate d_K.  From x_0 = 0 the answer is then ||b|| d_K
+    of the normalized system, which is the oracle's FP64 x_K: the AAR iterates
+    scale with b, since the extrapolation coefficients of Eqs. 4-5 do not
+    depend on the scale of F.  The difference is FP32 rounding."""
+    prob = make()
+    b = inputs.normal(21, 0, prob.size)
+    m, p = 7, 6
+    for K in (1, p - 1, p, p + 1, 2 * p + 1):
+        prm = inputs.Params(tol=1e-30, max_iter=K, m=m, p=p, precision=aar.AAR_MIXED_FP32)
+        say(f"mixed iterates {name} K={K}")
+        x, res, _ = gpu_solve(prob, prm, b)
+        assert res["status"] == aar.AAR_NOT_CONVERGED and res["iterations"] == K, (K, res)
+        ref = oracle.aar_solve(prob, b, m=m, p=p, tol=1e-30, max_iter=K)["x"]
+        np.testing.assert_allclose(x, ref, rtol=0, atol=1e-4 * np.abs(ref).max(), err_msg=f"K={K}")
+
+
 def test_fp64_deflation_same_answer():
     """The exact constant-mode step changes the path, not the answer."""
     prob = inputs.periodic_problem(24, 4, shift=0.3)
