@@ -473,9 +473,9 @@ hipError_t launch_gram_finish(const double *partial, int blocks, double *out, in
 hipError_t launch_update(Prec prec, const UpdateArgs<double> *a64, const UpdateArgs<float> *a32, int blocks,
                          hipStream_t s);
 // Residual recursion: x += omega * (the Richardson f_j of the unfinished cycle)
-// once a run has stopped (iterate and ring of one type: FP64, or FP32 for the
-// inner solves of the mixed mode).
-hipError_t launch_finalize_f64(double *x, const void *fring, const InstState *state, int p, int nslots,
+// once a run has stopped (FP64 iterate with an FP64 or FP32 ring; FP32
+// iterate and ring for the inner solves of the mixed mode).
+hipError_t launch_finalize_f64(Prec hist, double *x, const void *fring, const InstState *state, int p, int nslots,
                                int64_t slot_stride, double omega, int64_t N, hipStream_t s);
 hipError_t launch_finalize_f32(float *x, const void *fring, const InstState *state, int p, int nslots,
                                int64_t slot_stride, float omega, int64_t N, hipStream_t s);

@@ -809,11 +809,17 @@ __global__ __launch_bounds__(kThreads) void k_finalize(T *x, const void *fring, 
     }
 }
 
-hipError_t launch_finalize_f64(double *x, const void *fring, const InstState *state, int p, int nslots,
+hipError_t launch_finalize_f64(Prec hist, double *x, const void *fring, const InstState *state, int p, int nslots,
                                int64_t slot_stride, double omega, int64_t N, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_finalize<double, double>), dim3(stream_blocks(N)), dim3(kThreads), 0, s, x, fring, state,
-                       p, nslots, slot_stride, omega, N);
+    if (hist == Prec::F64)
+        hipLaunchKernelGGL((k_finalize<double, double>), dim3(stream_blocks(N)), dim3(kThreads), 0, s, x, fring,
+                           state, p, nslots, slot_stride, omega, N);
+    else if (hist == Prec::F32)
+        hipLaunchKernelGGL((k_finalize<double, float>), dim3(stream_blocks(N)), dim3(kThreads), 0, s, x, fring,
+                           state, p, nslots, slot_stride, omega, N);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -137,6 +137,13 @@ template <typename T> struct Path {
     int64_t dx_stride = 0;     // elements between dx slots
     bool gram_fused = false;   // the Anderson-residual pass forms the Gram products
     bool recur = false;        // sweeps after a cycle's first use the residual recursion
+    // FP64 iterate with an FP32 ring: the recursion sweeps and the Anderson-
+    // step residual run the FP32 stencil on the ring (tile ts32, FP32
+    // coefficients st32, rho_blocks32 workgroups)
+    bool recur32 = false;
+    TileShape ts32{};
+    StencilDev<float> st32{};
+    int rho_blocks32 = 0;
 };
 
 size_t hist_bytes(Prec p)
@@ -452,6 +459,29 @@ template <> struct Launch<float> {
     }
 };
 
+// Arguments of an FP32 recursion pass over an FP32 ring (Path::recur32).
+// The recursion reads neither x nor b; both point at the ring so that every
+// pointer the kernel holds is a valid FP32 vector.
+template <typename T> StencilArgs<float> ring_args32(aar_solver_t *S, const Path<T> &P, int j)
+{
+    const aar_params &pa = S->params;
+    StencilArgs<float> a;
+    std::memset(&a, 0, sizeof(a));
+    a.st = P.st32;
+    a.x = static_cast<const float *>(P.fring);
+    a.b = static_cast<const float *>(P.fring);
+    a.out = nullptr;
+    a.fring = P.fring;
+    a.state = S->state;
+    a.slot_stride = P.slot_stride;
+    a.j = j;
+    a.p = pa.p;
+    a.nslots = pa.m + 1;
+    a.omega = (float)pa.omega;
+    a.recur = 1;
+    return a;
+}
+
 template <typename T>
 hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStream_t s, int64_t cycle_tag)
 {
@@ -467,9 +497,10 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
     a.nslots = pa.m + 1;
     a.omega = (T)pa.omega;
     hipError_t e;
+    const bool rec = P.recur || P.recur32;
     for (int j = 0; j < pa.p - 1; ++j) {
         a.j = j;
-        if (P.recur) {
+        if (rec) {
             // x stays the cycle's first iterate; the first sweep reads it and
             // b, the others continue from the previous f
             a.recur = j > 0 ? 1 : 0;
@@ -492,7 +523,11 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
             if ((e = hipEventRecord(S->tev[S->tused], s)) != hipSuccess)
                 return e;
         }
-        if ((e = Launch<T>::stencil(kSweep, P, a, s)) != hipSuccess)
+        if (P.recur32 && j > 0)
+            e = launch_stencil_f32(kSweep, Prec::F32, P.radius, false, P.ts32, ring_args32(S, P, j), nullptr, s);
+        else
+            e = Launch<T>::stencil(kSweep, P, a, s);
+        if (e != hipSuccess)
             return e;
         if (S->timing && j == pa.p - 2) {
             if ((e = hipEventRecord(S->tev[S->tused + 1], s)) != hipSuccess)
@@ -502,7 +537,7 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
         }
     }
     const int jk = pa.p - 1;
-    T *xk = P.recur ? P.xa : (jk & 1) ? P.xb : P.xa;
+    T *xk = rec ? P.xa : (jk & 1) ? P.xb : P.xa;
     a.j = jk;
     a.x = xk;
     a.recur = P.recur && jk > 0 ? 1 : 0;
@@ -510,7 +545,14 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
     a.fcur = P.fcur;
     a.partial = S->part_rho;
     a.gram_partial = P.gram_fused ? S->part_gram : nullptr;
-    if ((e = Launch<T>::stencil(kFk, P, a, s)) != hipSuccess)
+    if (P.recur32) {   // jk >= 1: p >= 2
+        StencilArgs<float> a32 = ring_args32(S, P, jk);
+        a32.partial = S->part_rho;
+        e = launch_stencil_f32(kFk, Prec::F32, P.radius, false, P.ts32, a32, nullptr, s);
+    } else {
+        e = Launch<T>::stencil(kFk, P, a, s);
+    }
+    if (e != hipSuccess)
         return e;
 
     GramArgs g;
@@ -532,7 +574,7 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
     LsqArgs l;
     l.state = S->state;
     l.rho_partial = S->part_rho;
-    l.rho_blocks = P.rho_blocks;
+    l.rho_blocks = P.recur32 ? P.rho_blocks32 : P.rho_blocks;
     l.gram_final = S->gram_final;
     l.ne = S->ne;
     // the fused pass leaves one partial per workgroup and entry; the solve
@@ -564,7 +606,7 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
     u.slot_stride = P.slot_stride;
     u.dx_stride = P.dx_stride;
     u.status_out = S->status_dev;
-    if (P.recur) {
+    if (rec) {
         // xk is the cycle's first iterate: the update applies the cycle's
         // Richardson steps before the extrapolation
         u.omega_rich = (T)pa.omega;
@@ -691,6 +733,21 @@ template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool 
     // ring must hold the cycle's p f's, so m + 1 >= p
     P.recur = (f64 ? !S->mixed && P.hist == Prec::F64 : S->mixed && P.hist == Prec::F32) && S->params.p >= 2 &&
               S->params.m + 1 >= S->params.p;
+    // FP64 iterate, FP32 ring, no convection: the same recursion, computed in
+    // FP32 on the ring.  Its rounding (u32 |f| per step) restarts from the
+    // FP64 residual of x and b at every cycle, so the convergence test on
+    // |D f_k| keeps its FP64 meaning to ~1e-6 relative
+    P.recur32 = f64 && !S->mixed && P.hist == Prec::F32 && !P.conv && S->params.p >= 2 &&
+                S->params.m + 1 >= S->params.p;
+    if (P.recur32) {
+        P.ts32 = op.ts[1];
+        P.st32 = make_stencil<float>(op, nullptr);
+        int tx2, ty2, tz2, blocks2;
+        stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], P.ts32, &tx2, &ty2, &tz2, &blocks2,
+                     paired_layout(P.ts32, op.prob.n[0], false, kFk));
+        P.rho_blocks32 = blocks2;
+        P.gram_fused = false;   // the FP32 pass forms no Gram products
+    }
     P.gram_blocks = gram_blocks(op.N, S->params.m);
     P.upd_blocks = stream_blocks(op.N);
     P.slot_stride = S->slot_stride[f64 ? 0 : 1];
@@ -764,6 +821,21 @@ void append_tune_file(const std::tuple<int, int, int, int, int, int> &key, const
     f << std::get<0>(key) << ' ' << std::get<1>(key) << ' ' << std::get<2>(key) << ' ' << std::get<3>(key) << ' '
       << std::get<4>(key) << ' ' << std::get<5>(key) << ' ' << ts.ry << ' ' << ts.cz << ' ' << ts.order << ' '
       << ts.pair << '\n';
+}
+
+// Tile of the FP32 passes from the tile file, without timing candidates
+// (the FP32 recursion passes of an FP64 iteration over an FP32 ring, whose
+// solver holds no FP32 vectors to time them on); keeps the default shape
+// when the grid is not listed.
+void cached_tile32(Operator &op)
+{
+    const auto key = std::make_tuple(1, op.prob.radius, op.prob.velocity != nullptr ? 1 : 0, op.prob.n[0],
+                                     op.prob.n[1], op.prob.n[2]);
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    load_tune_file();
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end())
+        op.ts[1] = it->second;
 }
 
 template <typename T> aar_status autotune(aar_solver_t *S, int idx)
@@ -894,7 +966,7 @@ aar_status solve_one(aar_solver_t *S, int idx, const double *b, double *x, aar_r
     if (!S->mixed) {
         Path<double> &P = S->p64;
         bind_path(S, P, idx, true);
-        if (P.rho_blocks > S->part_rho_cap)
+        if (P.rho_blocks > S->part_rho_cap || P.rho_blocks32 > S->part_rho_cap)
             return fail(AAR_ERR_DEVICE, "stencil grid exceeds the partial-sum workspace");
         AAR_HIP(hipMemcpyAsync(P.b, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
         AAR_HIP(hipMemcpyAsync(P.xa, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
@@ -928,9 +1000,10 @@ aar_status solve_one(aar_solver_t *S, int idx, const double *b, double *x, aar_r
         aar_status e = run_cycles<double>(S, P, pa.max_iter, false, use_graph, &st);
         if (e != AAR_OK)
             return e;
-        if (P.recur) {
+        if (P.recur || P.recur32) {
             // the sweeps wrote no x: add the unfinished cycle's Richardson steps
-            AAR_HIP(launch_finalize_f64(P.xa, P.fring, S->state, pa.p, pa.m + 1, P.slot_stride, pa.omega, N, s));
+            AAR_HIP(launch_finalize_f64(P.hist, P.xa, P.fring, S->state, pa.p, pa.m + 1, P.slot_stride, pa.omega, N,
+                                        s));
             AAR_HIP(hipMemcpyAsync(x, P.xa, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
             AAR_HIP(hipStreamSynchronize(s));
             r.status = status_of(st);
@@ -1855,6 +1928,8 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
         st = S->mixed ? autotune<float>(S.get(), 0) : autotune<double>(S.get(), 0);
         if (st != AAR_OK)
             return st;
+        if (!S->mixed && S->hist == Prec::F32)
+            cached_tile32(S->ops[0]);
         AAR_HIP(hipStreamSynchronize(S->stream));
     }
     *out = S.release();
