@@ -60,16 +60,21 @@ enum { AAR_BC_ZERO_DIRICHLET = 0, AAR_BC_PERIODIC = 1 };
 
 /* Arithmetic of the iteration.
  *   AAR_FP64: every step in FP64.
- *   AAR_FP64_FP32HIST / AAR_FP64_BF16HIST: x, b and every residual in FP64,
- *     the history ring (the f_j of Eqs. 4-5) stored in FP32 / bfloat16; Gram
- *     products accumulated in FP64.  No refinement is needed: the iterate
- *     and the convergence test are FP64; only the extrapolation directions
- *     are rounded.  With an FP32 ring the Anderson update also takes f_k
- *     from the ring and the increments of Anderson steps (the X_k columns
- *     of Eq. 4) are stored in FP32: perturbations of the step relative to
- *     the current residual, which leave the fixed point and the FP64 test
- *     exact.  With a bfloat16 ring f_k comes from an FP64 copy and the
- *     increments stay FP64.
+ *   AAR_FP64_FP32HIST / AAR_FP64_BF16HIST: x and b in FP64, the history
+ *     ring (the f_j of Eqs. 4-5) stored in FP32 / bfloat16; Gram products
+ *     accumulated in FP64.  No refinement is needed: the iterate and the
+ *     residual of each cycle's first step are FP64; the extrapolation
+ *     directions are rounded.  With an FP32 ring the Anderson update also
+ *     takes f_k from the ring and the increments of Anderson steps (the X_k
+ *     columns of Eq. 4) are stored in FP32: perturbations of the step
+ *     relative to the current residual, which leave the fixed point exact.
+ *     Without convection the FP32-ring mode also forms the residuals of a
+ *     cycle's later steps (the Anderson step's included) in FP32 from the
+ *     previous one, f_{j+1} = f_j - omega D^-1 A f_j (Eq. 6 after a
+ *     Richardson step of Eq. 3); this restarts from the FP64 residual every
+ *     cycle, so the convergence test holds to ~1e-6 relative.  With a
+ *     bfloat16 ring every residual is FP64, f_k comes from an FP64 copy and
+ *     the increments stay FP64.
  *   AAR_MIXED_FP32: FP32 sweeps, history and Gram products (accumulated in
  *     FP64), FP64 m x m solve, and an outer FP64 iterative refinement:
  *     r = b - A x (FP64), inner FP32 AAR on A d = r/||r|| to inner_tol,

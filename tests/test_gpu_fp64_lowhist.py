@@ -1,9 +1,13 @@
 """GPU parity of the FP64 iteration with a reduced-precision history ring
 (FP32 or bfloat16 columns of F_k, Eqs. 4-5), against the FP64 CPU oracle.
 
-The iterate, the residual f_k and the convergence test stay in FP64; only
-the stored residual history is rounded, which perturbs the Anderson
-extrapolation direction but not the fixed point.  Parity is therefore on the
+The iterate and the residual of each cycle's first step stay in FP64; the
+stored residual history is rounded, which perturbs the Anderson
+extrapolation direction but not the fixed point.  With an FP32 ring (and no
+convection) the residuals of the cycle's later steps, the Anderson step's
+included, follow the residual recursion in FP32 on the ring, which restarts
+from the FP64 residual every cycle, so the reported residual matches the
+returned x's FP64 residual to ~1e-6 relative.  Parity is therefore on the
 answer and on the decision: the oracle's own operator must confirm
 ||b - A x|| / ||b|| < tol for the returned x, the residual the solver
 reported must be that x's residual, and x must match the oracle's solution
@@ -68,6 +72,31 @@ def test_lowhist_first_cycle_close_to_fp64():
         logs[prec] = log
     assert logs[aar.AAR_FP64][0] == pytest.approx(logs[aar.AAR_FP64_FP32HIST][0], rel=1e-4)
     assert logs[aar.AAR_FP64][0] == pytest.approx(logs[aar.AAR_FP64_BF16HIST][0], rel=5e-2)
+
+
+CAP_CASES = [
+    ("dirichlet_r1_32", lambda: inputs.dirichlet_poisson_problem(32)),
+    ("dirichlet_r1_27_odd", lambda: inputs.dirichlet_poisson_problem(27)),
+    ("periodic_r6_30", lambda: inputs.periodic_problem(30, 6, shift=0.5)),
+]
+
+
+@pytest.mark.parametrize("name,make", CAP_CASES, ids=[c[0] for c in CAP_CASES])
+def test_fp32hist_iterates_match_oracle(name, make):
+    """Iteration caps inside and at the end of a cycle: x_K of the FP64
+    iteration over an FP32 ring (the recursion in FP32 on the ring, the
+    unfinished cycle's steps added when the run stops) against the oracle's
+    FP64 x_K; the difference is the FP32 rounding of the history."""
+    prob = make()
+    b = inputs.normal(23, 0, prob.size)
+    m, p = 7, 6
+    for K in (1, p - 1, p, p + 1, 2 * p + 1):
+        prm = params(tol=1e-30, max_iter=K, m=m, p=p, precision=aar.AAR_FP64_FP32HIST)
+        say(f"fp32hist iterates {name} K={K}")
+        x, res, _ = gpu_solve(prob, prm, b)
+        assert res["status"] == aar.AAR_NOT_CONVERGED and res["iterations"] == K, (K, res)
+        ref = oracle.aar_solve(prob, b, m=m, p=p, tol=1e-30, max_iter=K)["x"]
+        np.testing.assert_allclose(x, ref, rtol=0, atol=1e-5 * np.abs(ref).max(), err_msg=f"K={K}")
 
 
 @pytest.mark.parametrize("precision", [aar.AAR_FP64_FP32HIST, aar.AAR_FP64_BF16HIST], ids=["fp32hist", "bf16hist"])
