@@ -68,7 +68,7 @@ enum { AAR_BC_ZERO_DIRICHLET = 0, AAR_BC_PERIODIC = 1 };
  *     takes f_k from the ring and the increments of Anderson steps (the X_k
  *     columns of Eq. 4) are stored in FP32: perturbations of the step
  *     relative to the current residual, which leave the fixed point exact.
- *     Without convection the FP32-ring mode also forms the residuals of a
+ *     The FP32-ring mode also forms the residuals of a
  *     cycle's later steps (the Anderson step's included) in FP32 from the
  *     previous one, f_{j+1} = f_j - omega D^-1 A f_j (Eq. 6 after a
  *     Richardson step of Eq. 3); this restarts from the FP64 residual every

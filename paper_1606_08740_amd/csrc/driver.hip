@@ -417,7 +417,7 @@ Sizes compute_sizes(const aar_problem *probs, int count, const aar_params *pa)
     if (!mixed) {
         b += vec_span(8) * 3 + vec_span(hist == Prec::F32 ? 4 : 8) * z.q + vec_span(hist_bytes(hist)) * slots +
              (hist == Prec::F32_BF16 ? vec_span(8) : 0);
-        b += sizeof(double) * (size_t)vel_total;
+        b += (sizeof(double) + (hist == Prec::F32 ? sizeof(float) : 0)) * (size_t)vel_total;
     } else {
         b += vec_span(4) * (3 + z.q) + vec_span(hist_bytes(hist)) * slots + vec_span(8) * 3;
         if (hist == Prec::F32_BF16)
@@ -524,7 +524,7 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
                 return e;
         }
         if (P.recur32 && j > 0)
-            e = launch_stencil_f32(kSweep, Prec::F32, P.radius, false, P.ts32, ring_args32(S, P, j), nullptr, s);
+            e = launch_stencil_f32(kSweep, Prec::F32, P.radius, P.conv, P.ts32, ring_args32(S, P, j), nullptr, s);
         else
             e = Launch<T>::stencil(kSweep, P, a, s);
         if (e != hipSuccess)
@@ -548,7 +548,7 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
     if (P.recur32) {   // jk >= 1: p >= 2
         StencilArgs<float> a32 = ring_args32(S, P, jk);
         a32.partial = S->part_rho;
-        e = launch_stencil_f32(kFk, Prec::F32, P.radius, false, P.ts32, a32, nullptr, s);
+        e = launch_stencil_f32(kFk, Prec::F32, P.radius, P.conv, P.ts32, a32, nullptr, s);
     } else {
         e = Launch<T>::stencil(kFk, P, a, s);
     }
@@ -733,18 +733,17 @@ template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool 
     // ring must hold the cycle's p f's, so m + 1 >= p
     P.recur = (f64 ? !S->mixed && P.hist == Prec::F64 : S->mixed && P.hist == Prec::F32) && S->params.p >= 2 &&
               S->params.m + 1 >= S->params.p;
-    // FP64 iterate, FP32 ring, no convection: the same recursion, computed in
-    // FP32 on the ring.  Its rounding (u32 |f| per step) restarts from the
-    // FP64 residual of x and b at every cycle, so the convergence test on
-    // |D f_k| keeps its FP64 meaning to ~1e-6 relative
-    P.recur32 = f64 && !S->mixed && P.hist == Prec::F32 && !P.conv && S->params.p >= 2 &&
-                S->params.m + 1 >= S->params.p;
+    // FP64 iterate, FP32 ring: the same recursion, computed in FP32 on the
+    // ring.  Its rounding (u32 |f| per step) restarts from the FP64 residual
+    // of x and b at every cycle, so the convergence test on |D f_k| keeps its
+    // FP64 meaning to ~1e-6 relative
+    P.recur32 = f64 && !S->mixed && P.hist == Prec::F32 && S->params.p >= 2 && S->params.m + 1 >= S->params.p;
     if (P.recur32) {
         P.ts32 = op.ts[1];
-        P.st32 = make_stencil<float>(op, nullptr);
+        P.st32 = make_stencil<float>(op, op.vel32);
         int tx2, ty2, tz2, blocks2;
         stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], P.ts32, &tx2, &ty2, &tz2, &blocks2,
-                     paired_layout(P.ts32, op.prob.n[0], false, kFk));
+                     paired_layout(P.ts32, op.prob.n[0], P.conv, kFk));
         P.rho_blocks32 = blocks2;
         P.gram_fused = false;   // the FP32 pass forms no Gram products
     }
@@ -1912,7 +1911,7 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
                 return st;
             AAR_HIP(hipMemcpyAsync(op.vel64, problems[i].velocity, sizeof(double) * 3 * op.N,
                                    hipMemcpyDeviceToDevice, S->stream));
-            if (S->mixed) {
+            if (S->mixed || S->hist == Prec::F32) {   // FP32 passes: mixed inner solves, FP32-ring recursion
                 op.vel32 = S->alloc<float>(3 * op.N, &st);
                 if (st != AAR_OK)
                     return st;

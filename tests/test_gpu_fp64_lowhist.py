@@ -3,8 +3,8 @@
 
 The iterate and the residual of each cycle's first step stay in FP64; the
 stored residual history is rounded, which perturbs the Anderson
-extrapolation direction but not the fixed point.  With an FP32 ring (and no
-convection) the residuals of the cycle's later steps, the Anderson step's
+extrapolation direction but not the fixed point.  With an FP32 ring the
+residuals of the cycle's later steps, the Anderson step's
 included, follow the residual recursion in FP32 on the ring, which restarts
 from the FP64 residual every cycle, so the reported residual matches the
 returned x's FP64 residual to ~1e-6 relative.  Parity is therefore on the
@@ -78,6 +78,7 @@ CAP_CASES = [
     ("dirichlet_r1_32", lambda: inputs.dirichlet_poisson_problem(32)),
     ("dirichlet_r1_27_odd", lambda: inputs.dirichlet_poisson_problem(27)),
     ("periodic_r6_30", lambda: inputs.periodic_problem(30, 6, shift=0.5)),
+    ("upwind_20", lambda: inputs.workload(4, n=20).problems[0]),
 ]
 
 
