@@ -289,14 +289,15 @@ struct BatchStreamArgs {
     double *partial;         // per item, or null
     // runs that used the residual recursion: their answer is the cycle-start
     // iterate plus omega times the Richardson f of the unfinished cycle
-    // (kOpScatterRecur: FP64 v64 and ring; kOpCorrect with recur set: FP32
-    // xa32 and ring)
+    // (kOpScatterRecur: FP64 v64, FP64 ring or FP32 ring when ring_f32 is
+    // set; kOpCorrect with recur set: FP32 xa32 and ring)
     const InstState *state;
     const void *fring;
     int64_t slot_stride;
     int32_t p, nslots;
     double omega;
     int32_t recur;
+    int32_t ring_f32;
 };
 
 enum : int32_t { kCtlSelect = 0, kCtlNormB = 1, kCtlMean = 2, kCtlDecide = 3, kCtlStart = 4 };

@@ -464,11 +464,13 @@ __global__ __launch_bounds__(kThreads) void k_stream_batched(const BatchStreamAr
                 // x at the end of the run: the cycle-start iterate plus omega
                 // times the f's of the Richardson steps taken in the last cycle
                 const InstState &st = a.state[sys];
-                const double *ring = static_cast<const double *>(a.fring);
                 const int64_t base = st.cycle * a.p, n = pending_steps(st, a.p);
                 double v = a.v64[off + i];
-                for (int64_t k = 0; k < n; ++k)
-                    v += a.omega * ring[((base + k) % a.nslots) * a.slot_stride + off + i];
+                for (int64_t k = 0; k < n; ++k) {
+                    const int64_t at = ((base + k) % a.nslots) * a.slot_stride + off + i;
+                    v += a.omega * (a.ring_f32 ? (double)static_cast<const float *>(a.fring)[at]
+                                               : static_cast<const double *>(a.fring)[at]);
+                }
                 a.user[a.uoffs[sys] + i] = c.zero ? 0.0 : v;
                 break;
             }

@@ -261,7 +261,8 @@ struct aar_solver_t {
         double *log = nullptr;
         hipGraphExec_t graph = nullptr;
         int *h_remaining = nullptr;
-        bool recur = false;     // FP64 cycles use the residual recursion
+        bool recur = false;     // cycles use the residual recursion (ring of the iterate's type)
+        bool recur32 = false;   // FP64 iterate, FP32 ring: the recursion passes run the FP32 stencil
     } B;
 
     template <typename T> T *alloc(size_t count, aar_status *st)
@@ -1301,6 +1302,7 @@ aar_status batch_setup(aar_solver_t *S)
     // (FP64, or FP32 for mixed inner solves) that holds a cycle's p f's
     B.recur = (S->mixed ? S->hist == Prec::F32 : S->hist == Prec::F64) && S->params.p >= 2 &&
               S->params.m + 1 >= S->params.p;
+    B.recur32 = !S->mixed && S->hist == Prec::F32 && S->params.p >= 2 && S->params.m + 1 >= S->params.p;
     if (!S->mixed) {
         B.xa64 = S->alloc<double>(total, &st);
         B.xb64 = S->alloc<double>(total, &st);
@@ -1458,7 +1460,25 @@ template <typename T> hipError_t batch_enqueue_cycle(aar_solver_t *S, hipStream_
     // alone; later sweeps and the Anderson-step residual follow
     // f_{j+1} = f_j - omega D^-1 A f_j from the ring; x stays in xa and the
     // update adds the cycle's Richardson steps
-    const bool recur = B.recur;
+    const bool recur32 = f64 && B.recur32;
+    const bool recur = B.recur || recur32;
+    // FP32 recursion passes over the FP32 ring of an FP64 iteration: the same
+    // (system, tile) items, FP32 coefficients; x and b are not read and point
+    // at the ring so that every pointer is a valid FP32 vector
+    BatchStencilArgs<float> a32;
+    std::memset(&a32, 0, sizeof(a32));
+    a32.desc = B.desc32;
+    a32.items = B.c_s;
+    a32.nitems = B.c_n;
+    a32.x = static_cast<const float *>(B.fring);
+    a32.b = static_cast<const float *>(B.fring);
+    a32.fring = B.fring;
+    a32.state = B.state;
+    a32.slot_stride = B.stride;
+    a32.p = pa.p;
+    a32.nslots = pa.m + 1;
+    a32.omega = (float)pa.omega;
+    a32.recur = 1;
     for (int j = 0; j < pa.p - 1; ++j) {
         a.j = j;
         a.x = (j & 1) ? xb : xa;
@@ -1468,10 +1488,14 @@ template <typename T> hipError_t batch_enqueue_cycle(aar_solver_t *S, hipStream_
             a.out = nullptr;
             a.recur = j > 0;
         }
-        if constexpr (std::is_same<T, double>::value)
+        if (recur32 && j > 0) {
+            a32.j = j;
+            e = launch_stencil_batched_f32(kSweep, Prec::F32, B.radius, B.conv, B.ry, a32, B.grid_s, s);
+        } else if constexpr (std::is_same<T, double>::value) {
             e = launch_stencil_batched_f64(kSweep, hist, B.radius, B.conv, B.ry, a, B.grid_s, s);
-        else
+        } else {
             e = launch_stencil_batched_f32(kSweep, hist, B.radius, B.conv, B.ry, a, B.grid_s, s);
+        }
         if (e != hipSuccess)
             return e;
     }
@@ -1483,10 +1507,15 @@ template <typename T> hipError_t batch_enqueue_cycle(aar_solver_t *S, hipStream_
     a.out = nullptr;
     a.fcur = fcur;
     a.partial = B.p_rho;
-    if constexpr (std::is_same<T, double>::value)
+    if (recur32) {   // jk >= 1: p >= 2
+        a32.j = jk;
+        a32.partial = B.p_rho;
+        e = launch_stencil_batched_f32(kFk, Prec::F32, B.radius, B.conv, B.ry, a32, B.grid_s, s);
+    } else if constexpr (std::is_same<T, double>::value) {
         e = launch_stencil_batched_f64(kFk, hist, B.radius, B.conv, B.ry, a, B.grid_s, s);
-    else
+    } else {
         e = launch_stencil_batched_f32(kFk, hist, B.radius, B.conv, B.ry, a, B.grid_s, s);
+    }
     if (e != hipSuccess)
         return e;
 
@@ -1721,8 +1750,9 @@ aar_status batch_solve(aar_solver_t *S, const double *b, double *x, const int64_
     }
     // write the answers back in the caller's layout
     AAR_HIPE(launch_compact(batch_compact_args(S, 2, false), s));
-    BatchStreamArgs sc = batch_stream(S, S->mixed ? kOpScatter : B.recur ? kOpScatterRecur : kOpScatterSel,
-                                      nullptr, 0);
+    BatchStreamArgs sc = batch_stream(
+        S, S->mixed ? kOpScatter : (B.recur || B.recur32) ? kOpScatterRecur : kOpScatterSel, nullptr, 0);
+    sc.ring_f32 = B.recur32 ? 1 : 0;
     sc.user = x;
     sc.v64 = x64;
     sc.x64 = B.xb64;
