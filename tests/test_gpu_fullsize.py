@@ -113,3 +113,58 @@ def test_large_grid_512():
     rr = oracle.relative_residual(prob, b, x)
     assert rr < prm.tol
     assert rr == pytest.approx(res["rel_residual"], rel=1e-6)
+
+
+CAP_CASES = [
+    ("periodic_poisson_r6_192", lambda: inputs.workload(2)),
+    ("convection_diffusion_upwind_128", lambda: inputs.workload(4)),
+]
+# answer tolerance relative to max |x_K| inside the first cycle (Richardson
+# steps only): FP64 rounding; the FP32 history ring (recursion in FP32 on the
+# ring); the FP32 inner iterates of the mixed mode
+CAP_TOL_FIRST_CYCLE = {aar.AAR_FP64: 1e-12, aar.AAR_FP64_FP32HIST: 1e-6, aar.AAR_MIXED_FP32: 1e-5}
+# after Anderson steps: the extrapolation coefficients of these smooth
+# problems are ill-conditioned (cond(F^T F) up to ~1e12 at this size), which
+# amplifies rounding-order differences of any two FP64 implementations to
+# ~1e-5 of x_K; a missing or doubled Richardson step would be an error of
+# order 1/K of x_K.  The reduced-precision modes round the history itself
+# (relative 6e-8), which the same conditioning turns into differences of a
+# few percent in the first extrapolation steps, so at full size they are
+# compared inside the first cycle only (the small-size tests follow them
+# through later cycles)
+CAP_TOL_LATER = 1e-3
+
+
+@pytest.mark.parametrize("name,make", CAP_CASES, ids=[c[0] for c in CAP_CASES])
+def test_full_size_iterates_at_caps(name, make):
+    """At full size and with the benchmark's tile shapes, an iteration cap
+    inside a cycle stops every mode at iterate x_K (Sec. 2, Eqs. 2-3): the
+    residual recursion's unfinished cycle must be added to the cycle-start
+    iterate.  Compared element by element with the oracle's x_K (the mixed
+    mode's first inner solve from x_0 = 0 scales with b, so it too is x_K)."""
+    import torch
+    w = make()
+    prob, b = w.problems[0], w.b[0]
+    bt = to_dev(b)
+    p = w.params.p
+    for K in (p - 1, p + 1, 2 * p + 3):
+        ref = oracle.aar_solve(prob, b, omega=w.params.omega, beta=w.params.beta, m=w.params.m, p=p, tol=1e-30,
+                               max_iter=K)["x"]
+        scale = np.abs(ref).max()
+        for prec, tol in CAP_TOL_FIRST_CYCLE.items():
+            if K >= p:
+                if prec != aar.AAR_FP64:
+                    continue
+                tol = CAP_TOL_LATER
+            prm = inputs.Params(**{**w.params.__dict__})
+            prm.precision = prec
+            prm.tol = 1e-30
+            prm.max_iter = K
+            say(f"full size caps {name} K={K} precision={prec}")
+            s = aar.Solver([prob], prm)
+            xt = torch.zeros_like(bt)
+            res = s.solve(bt, xt)
+            torch.cuda.synchronize()
+            s.close()
+            assert res["status"] == aar.AAR_NOT_CONVERGED and res["iterations"] == K, (prec, res)
+            np.testing.assert_allclose(xt.cpu().numpy(), ref, rtol=0, atol=tol * scale, err_msg=f"K={K} prec={prec}")
