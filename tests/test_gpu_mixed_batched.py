@@ -189,23 +189,27 @@ def test_batched_engine_equals_single_solves():
         assert rel_err(xs[i], x1) < 1e-7
 
 
-def test_batched_engine_iterates_match_oracle():
+@pytest.mark.parametrize("precision,tol", [(aar.AAR_FP64, 1e-10), (aar.AAR_FP64_FP32HIST, 1e-5),
+                                           (aar.AAR_MIXED_FP32, 1e-4)], ids=["fp64", "fp32hist", "mixed"])
+def test_batched_engine_iterates_match_oracle(precision, tol):
     """Iteration caps inside and at the end of a cycle: every system of the
     batch stops at iterate x_K, the one the oracle reaches after K steps
     (Sec. 2, Eqs. 2-3); the caps inside a cycle check that the answer adds the
-    cycle's Richardson steps taken so far."""
+    cycle's Richardson steps taken so far (from the FP64 ring, the FP32 ring,
+    or the mixed mode's FP32 inner iterate, whose first run from x_0 = 0
+    scales with b).  The tolerance is the rounding of the mode's history."""
     sizes = [17, 24, 16, 31]
     shifts = [1.5, 0.4, 6.0, 2.5]
     probs, bs = _helmholtz_batch(sizes, shifts, seed=110)
     m, p = 7, 6
     for K in (1, p - 1, p, p + 1, 3 * p + 2):
-        prm = inputs.Params(tol=1e-30, max_iter=K, m=m, p=p, precision=0)
-        say(f"batched iterates K={K}")
+        prm = inputs.Params(tol=1e-30, max_iter=K, m=m, p=p, precision=precision)
+        say(f"batched iterates precision={precision} K={K}")
         xs, res, _ = _run_batch(probs, bs, prm)
         for i, (pr, bi) in enumerate(zip(probs, bs)):
             assert res[i]["status"] == aar.AAR_NOT_CONVERGED and res[i]["iterations"] == K, (K, i, res[i])
             ref = oracle.aar_solve(pr, bi, m=m, p=p, tol=1e-30, max_iter=K)["x"]
-            np.testing.assert_allclose(xs[i], ref, rtol=0, atol=1e-10 * np.abs(ref).max(),
+            np.testing.assert_allclose(xs[i], ref, rtol=0, atol=tol * np.abs(ref).max(),
                                        err_msg=f"K={K} system {i}")
 
 
