@@ -1168,13 +1168,13 @@ bool batch_eligible(const aar_problem *probs, int count, const aar_params *pa)
 
 // Tile of the batched stencil passes (one-point layout): the tile file's
 // batch line (grid fields 0 0 0) for this precision, radius and convection,
-// else 4 rows per thread and z depth 16 (FP64 iterate) or 32 (FP32 iterate),
+// else z depth 32 with 2 rows per thread (FP64 iterate) or 4 (FP32 iterate),
 // the fastest of rows {1, 2, 4} x depth {4, 8, 16, 32} on the 512-system
 // Helmholtz batch.
 TileShape batch_tile(const aar_params *pa, int radius, bool conv)
 {
     const bool mixed = is_mixed(pa->precision);
-    TileShape ts{4, mixed ? 32 : 16, 0, 0};
+    TileShape ts{mixed ? 4 : 2, 32, 0, 0};
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     load_tune_file();
     const auto it = g_tune_cache.find(std::make_tuple(mixed ? 1 : 0, radius, conv ? 1 : 0, 0, 0, 0));
