@@ -6,14 +6,19 @@
  * large, sparse linear systems", arXiv:1606.08740.  The solver applies the
  * fixed-point iteration x_{k+1} = x_k + B_k f_k of Sec. 2, Eqs. 2-3, with the
  * left-preconditioned residual f_k = M^{-1}(b - A x_k) (Eq. 6) and the Jacobi
- * preconditioner M = diag(A) (Sec. 2, the AAJ special case; Secs. 3.2-3.3):
+ * preconditioner M = D = diag(A) (Sec. 2, the AAJ special case; Secs. 3.2-3.3):
  *   - Richardson, B_k = omega I, when (k+1)/p is not a natural number;
  *   - Anderson, B_k = beta I - (X_k + beta F_k)(F_k^T F_k)^+ F_k^T, when it is,
  *     with X_k, F_k the last m iterate and residual differences (Eqs. 4-5)
  *     and (.)^+ the Moore-Penrose pseudoinverse (Sec. 3.2).
- * Convergence, ||b - A x_k||_2 / ||b||_2 < tol, is tested at Anderson steps
- * only (Sec. 2, text after Eq. 6).  The iteration count reported is the
- * number of residual evaluations k+1, a multiple of p on convergence.
+ * Convergence, r_k = ||b - A x_k||_2 / ||b||_2 < tol (Sec. 2, text after
+ * Eq. 6), is tested at Anderson steps only.  The vector tested is D f_k for
+ * the f_k of that step.  For the first step of each cycle of p iterations f
+ * is formed from x and b; for the later steps of a cycle (the Anderson step
+ * included) the solver may form it from the previous one by the identity
+ * f_{j+1} = f_j - omega D^-1 A f_j, which a Richardson step x_{j+1} = x_j +
+ * omega f_j implies (see AAR_FP64 below).  The iteration count reported is
+ * the number of residual evaluations k+1, a multiple of p on convergence.
  *
  * The operator is a finite-difference stencil on a 3D grid (the paper's
  * Poisson and Helmholtz problems, Eqs. 7-8, use sixth-order central
@@ -21,6 +26,10 @@
  *   A u = -a Lap_h u + v . grad_h u + sigma u
  * with the order-2r central second difference along each axis (weights of
  * the standard central formula) and optional first-order upwind convection.
+ * Zero Dirichlet axes read zero outside the grid; periodic axes wrap indices
+ * modulo n, so on an axis shorter than the stencil (n < 2r+1) several taps
+ * land on one point and add up (a circulant), and D includes the taps that
+ * land on the point itself.
  *
  * Conventions for every entry point:
  *   - All functions are extern "C", never throw, and return aar_status.
@@ -30,6 +39,7 @@
  *     iterate, whose residual is reported.
  *   - Vector arguments b, x, y are caller-owned FP64 device pointers,
  *     contiguous, one value per grid point in the order i + n0*(j + n1*k).
+ *     The library never keeps them past the call.
  *   - Work runs on the HIP stream given at creation; the solve calls return
  *     after their results have reached the host.
  *   - A solver handle is not thread-safe; use one handle per stream.
@@ -59,7 +69,19 @@ typedef enum {
 enum { AAR_BC_ZERO_DIRICHLET = 0, AAR_BC_PERIODIC = 1 };
 
 /* Arithmetic of the iteration.
- *   AAR_FP64: every step in FP64.
+ *   AAR_FP64: every value and every operation in FP64.  When the history
+ *     ring holds a whole cycle (m + 1 >= p, p >= 2) the Richardson steps of
+ *     a cycle after its first do not read x and b: they form
+ *     f_{j+1} = f_j - omega D^-1 A f_j from the previous f (Eq. 6 after the
+ *     first case of Eq. 3), and the iterate x_j = x_c + omega sum f_i is
+ *     formed from the cycle's first iterate x_c where it is needed (the
+ *     Anderson update, the end of a run).  Each cycle's first f is formed
+ *     from x and b, so the recursion's rounding (about u ||f|| per step)
+ *     does not accumulate across cycles.  The convergence test and the
+ *     reported rel_residual are then ||D f_k|| / ||b|| for the recursed
+ *     f_k; they equal ||b - A x_k|| / ||b|| for the returned x_k to within
+ *     about p u kappa(D^-1 A) relative (1e-6 or better on the evaluation
+ *     grids).  With m + 1 < p every f is formed from x and b.
  *   AAR_FP64_FP32HIST / AAR_FP64_BF16HIST: x and b in FP64, the history
  *     ring (the f_j of Eqs. 4-5) stored in FP32 / bfloat16; Gram products
  *     accumulated in FP64.  No refinement is needed: the iterate and the
@@ -68,26 +90,26 @@ enum { AAR_BC_ZERO_DIRICHLET = 0, AAR_BC_PERIODIC = 1 };
  *     takes f_k from the ring and the increments of Anderson steps (the X_k
  *     columns of Eq. 4) are stored in FP32: perturbations of the step
  *     relative to the current residual, which leave the fixed point exact.
- *     The FP32-ring mode also forms the residuals of a
- *     cycle's later steps (the Anderson step's included) in FP32 from the
- *     previous one, f_{j+1} = f_j - omega D^-1 A f_j (Eq. 6 after a
- *     Richardson step of Eq. 3); this restarts from the FP64 residual every
- *     cycle, so the convergence test holds to ~1e-6 relative.  With a
- *     bfloat16 ring every residual is FP64, f_k comes from an FP64 copy and
- *     the increments stay FP64.
+ *     The FP32-ring mode runs the recursion described for AAR_FP64 in FP32
+ *     on the ring; it restarts from the FP64 residual every cycle, so the
+ *     convergence test holds to ~1e-6 relative.  With a bfloat16 ring every
+ *     residual is FP64, f_k comes from an FP64 copy and the increments stay
+ *     FP64.
  *   AAR_MIXED_FP32: FP32 sweeps, history and Gram products (accumulated in
  *     FP64), FP64 m x m solve, and an outer FP64 iterative refinement:
  *     r = b - A x (FP64), inner FP32 AAR on A d = r/||r|| to inner_tol,
- *     x += ||r|| d, until ||b - A x|| / ||b|| < tol.
+ *     x += ||r|| d, until ||b - A x|| / ||b|| < tol.  The outer test and the
+ *     reported rel_residual use r formed from x and b in FP64.
  *   AAR_MIXED_FP32_BF16HIST: as AAR_MIXED_FP32 with the history columns
  *     stored in bfloat16 (round to nearest even). */
 enum { AAR_FP64 = 0, AAR_MIXED_FP32 = 1, AAR_MIXED_FP32_BF16HIST = 2, AAR_FP64_FP32HIST = 3, AAR_FP64_BF16HIST = 4 };
 
 enum {
-    AAR_FLAG_RECORD_RESIDUALS = 1, /* keep r_k of every Anderson step (aar_residual_log)        */
+    AAR_FLAG_RECORD_RESIDUALS = 1, /* keep r_k and the kept rank of every Anderson step          */
     AAR_FLAG_DEFLATE_CONSTANT = 2, /* exact FP64 removal of the constant mode, see below        */
     AAR_FLAG_NO_GRAPH = 4,         /* launch kernels one by one instead of replaying HIP graphs */
-    AAR_FLAG_NO_AUTOTUNE = 8       /* use the default tile shape instead of timing candidates   */
+    AAR_FLAG_NO_AUTOTUNE = 8,      /* use the default tile shape instead of timing candidates   */
+    AAR_FLAG_FORCE_PINV = 16       /* every m x m solve by the eigendecomposition, see below    */
 };
 /* AAR_FLAG_DEFLATE_CONSTANT: when every axis is periodic and sigma > 0, the
  * constant vector is an exact eigenvector, A 1 = sigma 1 (upwind convection
@@ -98,26 +120,34 @@ enum {
  * which FP32 cannot resolve.  It is not part of the paper's method; the
  * answer is the same solution of A x = b.  aar_create returns
  * AAR_ERR_UNSUPPORTED for the flag on any system with a Dirichlet axis or
- * sigma == 0. */
+ * sigma == 0.
+ *
+ * AAR_FLAG_FORCE_PINV (a check of the solver, for tests): the m x m solve
+ * gamma = (F^T F)^+ F^T f_k normally takes a Cholesky solve when a bound
+ * proves every eigenvalue of F^T F above the pseudoinverse threshold (the
+ * pseudoinverse is then the inverse), and the Jacobi eigendecomposition
+ * otherwise.  With the flag every solve takes the eigendecomposition. */
 
-/* One linear system. */
+/* One linear system A x = b (Sec. 2, Eq. 1). */
 typedef struct {
     int32_t n[3];            /* grid points per axis (>= 1)                                  */
     double h[3];             /* grid spacing per axis (> 0)                                   */
-    int32_t bc[3];           /* AAR_BC_* per axis; periodic axes need n >= 2*radius + 1      */
+    int32_t bc[3];           /* AAR_BC_* per axis                                            */
     int32_t radius;          /* r in 1..6: order-2r central second difference, 6r+1 points   */
     double diffusion;        /* a (> 0)                                                      */
     double shift;            /* sigma (>= 0)                                                 */
     const double *velocity;  /* NULL, or device FP64 planar [vx | vy | vz] (3 N values);     */
-                             /* radius must be 1; copied at creation                         */
+                             /* radius must be 1 and periodic axes n >= 2; copied at creation */
 } aar_problem;
 
+/* Parameters of the iteration (Sec. 2, Eqs. 2-5; the paper's defaults are
+ * in Sec. 2, after the description of the method). */
 typedef struct {
     double omega;            /* Richardson relaxation (Eq. 3)                    paper: 0.6  */
     double beta;             /* Anderson relaxation (Eq. 3)                      paper: 0.6  */
     int32_t m;               /* history length, 1..32 (Eqs. 4-5)                 paper: 9    */
     int32_t p;               /* Anderson every p iterations, >= 1                paper: 8    */
-    double tol;              /* on ||b - A x|| / ||b||, > 0                                  */
+    double tol;              /* on r_k = ||b - A x|| / ||b||, > 0                            */
     int64_t max_iter;        /* cap on iterations (inner iterations in mixed mode), >= 1    */
     int32_t precision;       /* AAR_FP64, AAR_MIXED_FP32(_BF16HIST), AAR_FP64_*HIST           */
     double inner_tol;        /* mixed: inner FP32 tolerance (0 selects 1e-5)                 */
@@ -125,40 +155,58 @@ typedef struct {
     uint32_t flags;          /* AAR_FLAG_*                                                   */
 } aar_params;
 
+/* Outcome of one system. */
 typedef struct {
     int32_t status;          /* aar_status of this instance                                  */
+    int64_t iterations;      /* residual evaluations k+1 (all inner ones in mixed mode)      */
     int32_t outer_steps;     /* refinement steps (mixed), 0 in FP64 mode                     */
-    int64_t iterations;      /* residual evaluations (all inner ones in mixed mode)          */
-    double rel_residual;     /* last measured ||b - A x|| / ||b|| (FP64 in mixed mode)       */
+    double rel_residual;     /* last tested r_k (see above; FP64 from x and b in mixed mode) */
 } aar_result;
 
-/* Create a solver for `count` systems sharing `params`.  Validates the
- * descriptions, allocates the device workspace (history ring, partial sums,
- * descriptors), copies velocities, and picks tile shapes.  hip_stream is a
- * hipStream_t (NULL: the default stream).  *out receives the handle. */
+/* Create a solver for `count` systems A_i x_i = b_i (Eq. 1) sharing the
+ * iteration parameters of Eqs. 2-5.  Validates the descriptions (before any
+ * device work), allocates the device workspace (history ring of Eqs. 4-5,
+ * partial sums, descriptors; aar_workspace_bytes gives its size), copies
+ * velocities, and picks tile shapes (timing candidates unless
+ * AAR_FLAG_NO_AUTOTUNE or a tile file lists the grid).  hip_stream is a
+ * hipStream_t (NULL: the default stream).  *out receives the handle, which
+ * the caller releases with aar_destroy; on failure *out is NULL. */
 aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t count,
                       const aar_params *params, void *hip_stream);
 
-/* Solve system 0 (count must be 1).  x holds x_0 on entry and the answer on
- * return; b is read only.  r receives the outcome (may be NULL). */
+/* Solve system 0 (count must be 1) by AAR (Sec. 2, Eqs. 2-6).  x holds x_0
+ * on entry and the answer on return (the iterate x_k whose test passed, or
+ * the last iterate); b is read only.  r receives the outcome (may be NULL). */
 aar_status aar_solve(aar_solver s, const double *b, double *x, aar_result *r);
 
-/* Solve all `count` systems.  System i reads b + offsets[i] and updates
- * x + offsets[i] (offsets: count + 1 host int64 values, offsets[i+1] -
- * offsets[i] equal to that system's size).  results[i] (host, count entries)
- * receives each outcome; the return value is the worst status. */
+/* Solve all `count` systems by AAR (Sec. 2, Eqs. 2-6), advanced together,
+ * each stopping at its own test (Sec. 1: many independent solves).  System i
+ * reads b + offsets[i] and updates x + offsets[i] (offsets: count + 1 host
+ * int64 values, offsets[i+1] - offsets[i] equal to that system's size).
+ * results[i] (host, count entries) receives each outcome; the return value is
+ * the worst status. */
 aar_status aar_solve_batched(aar_solver s, const double *b, double *x, const int64_t *offsets,
                              aar_result *results);
 
-/* y = A x in FP64 for system `instance` (a check of the operator). */
+/* y = A x in FP64 for system `instance` (the operator of Eq. 1; a check of
+ * the stencil).  x and y are device vectors of that system's size and must
+ * not overlap. */
 aar_status aar_apply(aar_solver s, int32_t instance, const double *x, double *y);
 
-/* Copy up to `cap` recorded Anderson-step residuals r_k of system `instance`
- * from the last solve (needs AAR_FLAG_RECORD_RESIDUALS) into host `out`;
- * *count receives the number recorded.  In mixed mode these are the inner
- * residuals of the last refinement step. */
+/* Copy up to `cap` recorded Anderson-step residuals r_k (Sec. 2, text after
+ * Eq. 6) of system `instance` from the last solve (needs
+ * AAR_FLAG_RECORD_RESIDUALS) into host `out`; *count receives the number
+ * recorded.  In mixed mode these are the inner residuals of the last
+ * refinement step. */
 aar_status aar_residual_log(aar_solver s, int32_t instance, double *out, int64_t cap,
                             int64_t *count);
+
+/* Copy up to `cap` ranks kept by the pseudoinverse solve of each Anderson
+ * step (Sec. 3.2; the number of eigenvalues of F^T F above the threshold),
+ * index for index beside aar_residual_log, into host `out`: -1 for the step
+ * whose convergence test ended the run (no solve), l = min(k, m) whenever the
+ * Cholesky shortcut proved full rank.  Needs AAR_FLAG_RECORD_RESIDUALS. */
+aar_status aar_rank_log(aar_solver s, int32_t instance, int32_t *out, int64_t cap, int64_t *count);
 
 /* Device bytes aar_create would allocate for these arguments. */
 aar_status aar_workspace_bytes(const aar_problem *problems, int32_t count, const aar_params *params,

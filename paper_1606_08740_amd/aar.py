@@ -25,6 +25,7 @@ AAR_ERR_INVALID_ARG, AAR_ERR_UNSUPPORTED, AAR_ERR_DEVICE, AAR_ERR_OUT_OF_MEMORY 
 AAR_BC_ZERO_DIRICHLET, AAR_BC_PERIODIC = 0, 1
 AAR_FP64, AAR_MIXED_FP32, AAR_MIXED_FP32_BF16HIST, AAR_FP64_FP32HIST, AAR_FP64_BF16HIST = 0, 1, 2, 3, 4
 AAR_FLAG_RECORD_RESIDUALS, AAR_FLAG_DEFLATE_CONSTANT, AAR_FLAG_NO_GRAPH, AAR_FLAG_NO_AUTOTUNE = 1, 2, 4, 8
+AAR_FLAG_FORCE_PINV = 16
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "BREAKDOWN", -1: "INVALID_ARG", -2: "UNSUPPORTED",
                 -3: "DEVICE", -4: "OUT_OF_MEMORY"}
@@ -44,8 +45,8 @@ class aar_params(ctypes.Structure):
 
 
 class aar_result(ctypes.Structure):
-    _fields_ = [("status", ctypes.c_int32), ("outer_steps", ctypes.c_int32),
-                ("iterations", ctypes.c_int64), ("rel_residual", ctypes.c_double)]
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int64),
+                ("outer_steps", ctypes.c_int32), ("rel_residual", ctypes.c_double)]
 
 
 _lib = None
@@ -74,6 +75,7 @@ def load_library():
     lib.aar_solve_batched.argtypes = [vp, vp, vp, P(i64), P(aar_result)]
     lib.aar_apply.argtypes = [vp, i32, vp, vp]
     lib.aar_residual_log.argtypes = [vp, i32, P(ctypes.c_double), i64, P(i64)]
+    lib.aar_rank_log.argtypes = [vp, i32, P(i32), i64, P(i64)]
     lib.aar_workspace_bytes.argtypes = [P(aar_problem), i32, P(aar_params), P(ctypes.c_size_t)]
     lib.aar_destroy.argtypes = [vp]
     lib.aar_last_error.argtypes = []
@@ -81,7 +83,7 @@ def load_library():
     lib.aar_set_timing.argtypes = [vp, i32]
     lib.aar_sweep_time.argtypes = [vp, P(ctypes.c_double), P(i64)]
     for name in ["aar_create", "aar_solve", "aar_solve_batched", "aar_apply", "aar_residual_log",
-                 "aar_workspace_bytes", "aar_destroy", "aar_set_timing", "aar_sweep_time"]:
+                 "aar_rank_log", "aar_workspace_bytes", "aar_destroy", "aar_set_timing", "aar_sweep_time"]:
         getattr(lib, name).restype = st
     _lib = lib
     return lib
@@ -138,6 +140,15 @@ def aar_residual_log(handle, instance: int = 0, cap: int = 1 << 20) -> np.ndarra
     _check(load_library().aar_residual_log(handle, int(instance),
                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                            int(cap), ctypes.byref(cnt)), "aar_residual_log")
+    return out[: min(cnt.value, cap)].copy()
+
+
+def aar_rank_log(handle, instance: int = 0, cap: int = 1 << 20) -> np.ndarray:
+    out = np.zeros(max(cap, 1), dtype=np.int32)
+    cnt = ctypes.c_int64(0)
+    _check(load_library().aar_rank_log(handle, int(instance),
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       int(cap), ctypes.byref(cnt)), "aar_rank_log")
     return out[: min(cnt.value, cap)].copy()
 
 
@@ -256,6 +267,9 @@ class Solver:
 
     def residual_log(self, instance: int = 0) -> np.ndarray:
         return aar_residual_log(self.handle, instance)
+
+    def rank_log(self, instance: int = 0) -> np.ndarray:
+        return aar_rank_log(self.handle, instance)
 
     def set_timing(self, enable: bool) -> None:
         aar_set_timing(self.handle, enable)

@@ -116,8 +116,12 @@ template <typename T> struct StencilDev {
     T c1[kMaxRadius + 1];
     T c2[kMaxRadius + 1];
     T sigma;
-    T diag;                     // diag(A) without convection: sigma - 2 sum_axes sum_s c[s]
-    T inv_diag;
+    T diag;                     // centre weight of the stencil: sigma - 2 sum_axes sum_s c[s]
+    // Jacobi preconditioner D = diag(A) without convection: the centre weight
+    // plus the taps that a periodic axis shorter than the stencil wraps back
+    // onto the point itself (equal to diag when every periodic n >= 2r + 1)
+    T jdiag;
+    T inv_diag;                 // 1 / jdiag
     T ih0, ih1, ih2;            // 1/h per axis (upwind convection)
     const T *vel;               // planar [vx|vy|vz] or nullptr
     int64_t N;
@@ -358,6 +362,12 @@ struct LsqArgs {
     double stagnation_factor;    // best_r must fall below factor * best_r within the window
     double *log;                 // residual log or nullptr
     int64_t log_cap;
+    // beside the residual log (same index): the rank kept by that Anderson
+    // step's pseudoinverse solve, -1 for the step whose test stopped the run
+    int32_t *rank_log = nullptr;
+    // nonzero: skip the Cholesky shortcut, so every solve takes the
+    // eigendecomposition (a check of that branch on well-posed data)
+    int32_t force_pinv = 0;
 };
 
 // Element type of the ring of Anderson increments x_{k+1} - x_k (the X_k

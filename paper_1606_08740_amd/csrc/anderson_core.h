@@ -188,6 +188,8 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
         st->last_r = rel;
         if (a.log && log_count0 < a.log_cap)
             a.log[log_count0] = rel;
+        if (a.rank_log && log_count0 < a.log_cap)
+            a.rank_log[log_count0] = -1;   // overwritten below when the step extrapolates
         st->log_count = log_count0 + 1;
     }
     // breakdown: a NaN or Inf in the residual or in the l x l Gram system
@@ -309,7 +311,7 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
                 Lr[i][c] = acc * id[i];
                 fro += i < l ? Lr[i][c] * Lr[i][c] : 0.0;
             }
-        fast = l > 0 && ok && (1.0 / fro > a.rcond * (double)l * tr) && fro == fro;
+        fast = l > 0 && ok && (1.0 / fro > a.rcond * (double)l * tr) && fro == fro && !a.force_pinv;
         if (fast) {
             double y[kRegM];   // y = L^-1 c, gamma = L^-T y
 #pragma unroll
@@ -338,7 +340,7 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
                 cvec[i] = gram_vals[np + i];
             __syncthreads();
         }
-    } else if (l > 0) {
+    } else if (l > 0 && !a.force_pinv) {
         for (int i = tid; i < l * l; i += kLsqThreads)
             V[i / l][i % l] = S[i / l][i % l];
         if (tid == 0)
@@ -570,6 +572,8 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
                 rank += S[e][e] > sh_off;
         }
         st->rank = rank;
+        if (a.rank_log && log_count0 < a.log_cap)
+            a.rank_log[log_count0] = rank;
         st->nf = l + 1;
         st->nd = __popcll(amask);
         st->wslot = a.q > 0 ? cyc0 : -1;

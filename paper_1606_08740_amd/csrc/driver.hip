@@ -74,7 +74,8 @@ struct Operator {
     aar_problem prob;
     int64_t N = 0;
     double c[3][kMaxRadius + 1] = {};
-    double diag = 0.0;    // without convection
+    double diag = 0.0;    // centre weight of the stencil, without convection
+    double jdiag = 0.0;   // diag(A) without convection (the Jacobi preconditioner)
     double *vel64 = nullptr;
     float *vel32 = nullptr;
     TileShape ts[2];      // stencil tile for FP64 [0] and FP32 [1] passes
@@ -97,7 +98,8 @@ template <typename T> StencilDev<T> make_stencil(const Operator &op, const T *ve
     }
     st.sigma = (T)op.prob.shift;
     st.diag = (T)op.diag;
-    st.inv_diag = (T)(1.0 / op.diag);
+    st.jdiag = (T)op.jdiag;
+    st.inv_diag = (T)(1.0 / op.jdiag);
     st.ih0 = (T)(1.0 / op.prob.h[0]);
     st.ih1 = (T)(1.0 / op.prob.h[1]);
     st.ih2 = (T)(1.0 / op.prob.h[2]);
@@ -202,6 +204,7 @@ struct aar_solver_t {
     int part_rho_cap = 0;      // entries of part_rho (stencil workgroups of one pass)
     double *scal = nullptr;       // [0] ||r|| of the refinement, [1] ||b|| (FP64)
     double *log = nullptr;
+    int32_t *rank_log = nullptr;   // beside log: rank kept by each Anderson step's solve
     int64_t log_cap = 0;
     Path<double> p64;
     Path<float> p32;
@@ -259,6 +262,7 @@ struct aar_solver_t {
         float *xa32 = nullptr, *xb32 = nullptr, *rhs32 = nullptr, *fcur32 = nullptr, *dx32 = nullptr;
         void *fring = nullptr;
         double *log = nullptr;
+        int32_t *rank_log = nullptr;
         hipGraphExec_t graph = nullptr;
         int *h_remaining = nullptr;
         bool recur = false;     // cycles use the residual recursion (ring of the iterate's type)
@@ -344,9 +348,13 @@ aar_status validate_problem(const aar_problem &pr, int idx)
         return fail(AAR_ERR_INVALID_ARG, "shift must be non-negative and finite" + at);
     if (pr.velocity && pr.radius != 1)
         return fail(AAR_ERR_UNSUPPORTED, "convection needs radius 1" + at);
+    // a periodic axis shorter than the stencil wraps its taps modulo n and
+    // they add up (a circulant); with convection a one-point periodic axis
+    // would make the upwind difference vanish, which the kernels' Jacobi
+    // diagonal does not model
     for (int a = 0; a < 3; ++a)
-        if (pr.bc[a] == AAR_BC_PERIODIC && pr.n[a] < 2 * pr.radius + 1)
-            return fail(AAR_ERR_UNSUPPORTED, "periodic axis shorter than the stencil (n < 2r+1)" + at);
+        if (pr.velocity && pr.bc[a] == AAR_BC_PERIODIC && pr.n[a] < 2)
+            return fail(AAR_ERR_UNSUPPORTED, "convection on a periodic axis of one point" + at);
     const int64_t N = (int64_t)pr.n[0] * pr.n[1] * pr.n[2];
     if (N > ((int64_t)1 << 40) || (int64_t)pr.n[0] * pr.n[1] >= ((int64_t)1 << 31))
         return fail(AAR_ERR_UNSUPPORTED, "grid too large" + at);
@@ -368,6 +376,13 @@ Operator build_operator(const aar_problem &pr)
         }
     }
     op.diag = pr.shift - 2.0 * sum;
+    // taps +-s of a periodic axis land on the point itself when n divides s
+    op.jdiag = op.diag;
+    for (int a = 0; a < 3; ++a)
+        if (pr.bc[a] == AAR_BC_PERIODIC)
+            for (int s = 1; s <= pr.radius; ++s)
+                if (s % pr.n[a] == 0)
+                    op.jdiag += 2.0 * op.c[a][s];
     op.ts[0] = default_tile(pr.radius, true);
     op.ts[1] = default_tile(pr.radius, false);
     return op;
@@ -427,7 +442,7 @@ Sizes compute_sizes(const aar_problem *probs, int count, const aar_params *pa)
     }
     if (pa->flags & AAR_FLAG_RECORD_RESIDUALS) {
         z.log_cap = std::min<int64_t>(pa->max_iter / pa->p + 2, (int64_t)1 << 22);
-        b += sizeof(double) * (size_t)z.log_cap;
+        b += (sizeof(double) + sizeof(int32_t)) * (size_t)z.log_cap;
     }
     z.bytes = b;
     return z;
@@ -592,7 +607,9 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
     l.stagnation_window = inner ? 8 : 0;
     l.stagnation_factor = 0.9;
     l.log = S->log;
+    l.rank_log = S->rank_log;
     l.log_cap = S->log_cap;
+    l.force_pinv = (pa.flags & AAR_FLAG_FORCE_PINV) ? 1 : 0;
     if ((e = launch_lsq(l, s)) != hipSuccess)
         return e;
 
@@ -1228,6 +1245,9 @@ size_t batch_bytes(const aar_problem *probs, int count, const aar_params *pa)
     b += sizeof(double) * (size_t)(2 * tiles + chunks * (ne + 1));
     b += (sizeof(int2) * 2 + sizeof(int) * 4) * (size_t)(tiles + chunks + count);
     b += (sizeof(InstState) + sizeof(BatchCtl) + sizeof(BatchDesc<double>) + sizeof(BatchDesc<float>) + 64) * count;
+    if (pa->flags & AAR_FLAG_RECORD_RESIDUALS)
+        b += (sizeof(double) + sizeof(int32_t)) * (size_t)std::min<int64_t>(pa->max_iter / pa->p + 2, (int64_t)1 << 16) *
+             count;
     return b;
 }
 
@@ -1336,6 +1356,7 @@ aar_status batch_setup(aar_solver_t *S)
     if (pa.flags & AAR_FLAG_RECORD_RESIDUALS) {
         S->log_cap = std::min<int64_t>(pa.max_iter / pa.p + 2, (int64_t)1 << 16);
         B.log = S->alloc<double>((size_t)S->log_cap * count, &st);
+        B.rank_log = S->alloc<int32_t>((size_t)S->log_cap * count, &st);
     }
     if (st != AAR_OK)
         return st;
@@ -1547,7 +1568,9 @@ template <typename T> hipError_t batch_enqueue_cycle(aar_solver_t *S, hipStream_
     l.stagnation_window = S->mixed ? 8 : 0;
     l.stagnation_factor = 0.9;
     l.log = B.log;
+    l.rank_log = B.rank_log;
     l.log_cap = S->log_cap;
+    l.force_pinv = (pa.flags & AAR_FLAG_FORCE_PINV) ? 1 : 0;
     BatchLsqArgs bl;
     bl.state = B.state;
     bl.sbase = B.c_sb;
@@ -1875,6 +1898,7 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
     if (z.log_cap > 0) {
         S->log_cap = z.log_cap;
         S->log = S->alloc<double>(z.log_cap, &st);
+        S->rank_log = S->alloc<int32_t>(z.log_cap, &st);
     }
     if (!batched) {
         // Bulk vectors and ring slots come from one arena, each starting on a
@@ -2045,6 +2069,27 @@ aar_status aar_residual_log(aar_solver s, int32_t instance, double *out, int64_t
     const int64_t n = std::min(have, cap);
     if (n > 0)
         AAR_HIP(hipMemcpy(out, log + (s->B.on ? (int64_t)instance * s->log_cap : 0), sizeof(double) * n,
+                          hipMemcpyDeviceToHost));
+    return AAR_OK;
+}
+
+aar_status aar_rank_log(aar_solver s, int32_t instance, int32_t *out, int64_t cap, int64_t *count)
+{
+    g_error.clear();
+    if (!s || !count || (cap > 0 && !out))
+        return fail(AAR_ERR_INVALID_ARG, "solver, out or count invalid");
+    if (instance < 0 || instance >= (int)s->ops.size())
+        return fail(AAR_ERR_INVALID_ARG, "instance out of range");
+    const int32_t *log = s->B.on ? s->B.rank_log : s->rank_log;
+    if (!log)
+        return fail(AAR_ERR_INVALID_ARG, "solver created without AAR_FLAG_RECORD_RESIDUALS");
+    if (!s->B.on && instance != s->last_instance && s->ops.size() > 1)
+        return fail(AAR_ERR_UNSUPPORTED, "only the last solved system's log is kept");
+    const int64_t have = std::min<int64_t>(s->last_log_count[instance], s->log_cap);
+    *count = have;
+    const int64_t n = std::min(have, cap);
+    if (n > 0)
+        AAR_HIP(hipMemcpy(out, log + (s->B.on ? (int64_t)instance * s->log_cap : 0), sizeof(int32_t) * n,
                           hipMemcpyDeviceToHost));
     return AAR_OK;
 }

@@ -281,7 +281,7 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs<T> &a, int lin, d
             if (!own[ry])
                 continue;
             const int64_t id = coff[ry] + plane * z;
-            T dg = st.diag;
+            T dg = st.jdiag;
             if constexpr (CONV) {
                 const T v0 = vcur[3 * ry], v1 = vcur[3 * ry + 1], v2 = vcur[3 * ry + 2];
                 ax += v0 > T(0) ? -v0 * st.ih0 * (sh[ly][lx - 1] - c) : v0 * st.ih0 * (sh[ly][lx + 1] - c);
@@ -679,8 +679,8 @@ __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, 
                 // f_k = f_{k-1} - omega D^-1 A f_{k-1}; b - A x_k = D f_k
                 f0 = q[r][0][R] - a.omega * (st.inv_diag * ax[r][0]);
                 f1 = q[r][1][R] - a.omega * (st.inv_diag * ax[r][1]);
-                r0 = st.diag * f0;
-                r1 = st.diag * f1;
+                r0 = st.jdiag * f0;
+                r1 = st.jdiag * f1;
             } else {
                 r0 = bcur[r].x - ax[r][0];
                 r1 = bcur[r].y - ax[r][1];

@@ -1,7 +1,9 @@
 """The C-ABI library loads and exports every function include/aar.h declares,
 and rejects bad arguments before any device work (no GPU needed)."""
+import os
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_1606_08740_amd import aar, inputs
@@ -60,13 +62,56 @@ def test_bad_params_rejected(field, value, status):
     (dict(radius=7), aar.AAR_ERR_INVALID_ARG), (dict(radius=0), aar.AAR_ERR_INVALID_ARG),
     (dict(bc=(0, 2, 0)), aar.AAR_ERR_INVALID_ARG), (dict(diffusion=0.0), aar.AAR_ERR_INVALID_ARG),
     (dict(shift=-1.0), aar.AAR_ERR_INVALID_ARG),
-    (dict(bc=(1, 1, 1), radius=6, n=(12, 13, 13)), aar.AAR_ERR_UNSUPPORTED),
+    (dict(radius=2, velocity=np.zeros(3 * 512)), aar.AAR_ERR_UNSUPPORTED),
+    (dict(bc=(1, 0, 0), n=(1, 8, 8), velocity=np.zeros(3 * 64)), aar.AAR_ERR_UNSUPPORTED),
 ])
 def test_bad_problem_rejected(change, status):
     prob = inputs.dirichlet_poisson_problem(8)
     for k, v in change.items():
         setattr(prob, k, v)
+    # the checks run before anything is read from the velocity pointer, so a
+    # non-null placeholder address stands for a device array here
+    vptr = 1 if prob.velocity is not None else 0
     with pytest.raises(aar.AarError) as ei:
-        _ws(prob, inputs.Params())
+        aar.aar_workspace_bytes([aar.make_problem(prob, vptr)], aar.make_params(inputs.Params()))
     assert ei.value.status == status
     assert aar.aar_last_error() != ""
+
+
+def test_periodic_axis_shorter_than_stencil_accepted():
+    """A periodic axis with n < 2r + 1 wraps its taps (they add up)."""
+    prob = inputs.Problem(n=(4, 6, 5), h=(0.25, 1 / 6, 0.2), bc=(1, 1, 1), radius=6)
+    assert _ws(prob, inputs.Params()) > 0
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The C compiler's layout of the header's structs equals the binding's:
+    aar_result is {status, iterations, outer_steps, rel_residual}."""
+    import ctypes
+    src = tmp_path / "layout.c"
+    src.write_text("""#include <stdio.h>
+#include <stddef.h>
+#include "aar.h"
+#define F(s, m) printf(#s "." #m " %zu\\n", offsetof(s, m))
+int main(void) {
+  F(aar_result, status); F(aar_result, iterations); F(aar_result, outer_steps); F(aar_result, rel_residual);
+  printf("aar_result.size %zu\\n", sizeof(aar_result));
+  F(aar_problem, n); F(aar_problem, h); F(aar_problem, bc); F(aar_problem, radius);
+  F(aar_problem, diffusion); F(aar_problem, shift); F(aar_problem, velocity);
+  printf("aar_problem.size %zu\\n", sizeof(aar_problem));
+  F(aar_params, omega); F(aar_params, beta); F(aar_params, m); F(aar_params, p); F(aar_params, tol);
+  F(aar_params, max_iter); F(aar_params, precision); F(aar_params, inner_tol); F(aar_params, max_outer);
+  F(aar_params, flags);
+  printf("aar_params.size %zu\\n", sizeof(aar_params));
+  return 0; }
+""")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(aar.ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(line.rsplit(" ", 1) for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, cls in [("aar_result", aar.aar_result), ("aar_problem", aar.aar_problem),
+                       ("aar_params", aar.aar_params)]:
+        assert int(got[f"{cname}.size"]) == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(cls, fname).offset, (cname, fname)
+    order = [f for f, _ in aar.aar_result._fields_]
+    assert order == ["status", "iterations", "outer_steps", "rel_residual"]
