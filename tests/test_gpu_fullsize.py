@@ -123,29 +123,25 @@ CAP_CASES = [
 # steps only): FP64 rounding; the FP32 history ring (recursion in FP32 on the
 # ring); the FP32 inner iterates of the mixed mode
 CAP_TOL_FIRST_CYCLE = {aar.AAR_FP64: 1e-12, aar.AAR_FP64_FP32HIST: 1e-6, aar.AAR_MIXED_FP32: 1e-5}
-# unit roundoff of the values the Gram products are formed from, per mode
+# unit roundoff of the arithmetic each mode rounds its history in
 UNIT = {aar.AAR_FP64: 2.0 ** -53, aar.AAR_FP64_FP32HIST: 2.0 ** -24, aar.AAR_MIXED_FP32: 2.0 ** -24}
+# margin over the measured sensitivity (below)
+SENS_FACTOR = 50.0
 
 
-def later_cycle_tol(trace, N, threads, unit, first_cycle_tol):
-    """Bound on |x_K - x_K(oracle)| / max |x_K| after Anderson steps.
-
-    After a step, x_{k+1} = x* - ((D^-1 A)^-1 - beta) r_hat with r_hat the
-    least-squares residual f_k - F_k gamma (this uses F = -D^-1 A X, Eqs.
-    4-6), so a perturbation of the computed products moves the iterate by the
-    change it makes to F_k gamma, which is at most |delta c| / sigma_min(F_k)
-    = (relative error of the products) * sqrt(cond(F_k^T F_k)) * |f_k|.  The
-    two sides sum each product over N points in different orders; the
-    longest run the oracle sums in sequence is N / threads points, whose
-    rounding grows like sqrt(run) * u for these data (random-sign terms).
-    With the rounding of the values themselves (unit u of the mode's history)
-    and a factor 10 of margin, each extrapolation step t before K adds
-    10 sqrt(N / threads) u sqrt(cond_t); the first-cycle tolerance is the
-    floor.  A bound at or above 1e-2 says nothing and is returned as None."""
-    run = max(N / max(threads, 1), 1.0)
-    sens = sum(np.sqrt(max(c, 1.0)) for c in trace[:, 5])
-    tol = max(first_cycle_tol, 10.0 * np.sqrt(run) * unit * sens)
-    return None if tol >= 1e-2 else tol
+def rounding_sensitivity(prob, b, prm, K, unit, ref):
+    """How far the oracle's own x_K moves, relative to max |x_K|, when b is
+    perturbed by a few roundings of relative size `unit` (seeded N(0,1)
+    factors times 4 unit).  After Anderson steps this is large: the
+    extrapolation of Eq. 3 solves with F_k^T F_k, whose condition number
+    reaches 1e12 on these smooth problems, so two implementations that differ
+    only in rounding order separate by about this much.  It is measured on the
+    oracle, not assumed."""
+    xi = inputs.normal(4242, 0, b.size)
+    bp = b * (1.0 + 4.0 * unit * xi)
+    xp = oracle.aar_solve(prob, bp, omega=prm.omega, beta=prm.beta, m=prm.m, p=prm.p, tol=1e-30,
+                          max_iter=K)["x"]
+    return float(np.abs(xp - ref).max() / np.abs(ref).max())
 
 
 @pytest.mark.parametrize("name,make", CAP_CASES, ids=[c[0] for c in CAP_CASES])
@@ -162,14 +158,23 @@ def test_full_size_iterates_at_caps(name, make):
     p = w.params.p
     for K in (p - 1, p + 1, 2 * p + 3):
         out = oracle.aar_solve(prob, b, omega=w.params.omega, beta=w.params.beta, m=w.params.m, p=p, tol=1e-30,
-                               max_iter=K, trace_cap=100)
+                               max_iter=K)
         ref = out["x"]
         scale = np.abs(ref).max()
+        sens = {}
         for prec, tol in CAP_TOL_FIRST_CYCLE.items():
             if K >= p:
-                tol = later_cycle_tol(out["trace"], prob.size, oracle.threads(), UNIT[prec], tol)
-                if tol is None:
-                    say(f"full size caps {name} K={K} precision={prec}: bound vacuous, not compared")
+                # after Anderson steps: SENS_FACTOR times the oracle's own
+                # movement under rounding-size perturbations of its input, in
+                # the mode's unit roundoff; a bound of 1e-2 or more says
+                # nothing and that mode is not compared at this K (the
+                # small-size tests follow it through later cycles)
+                key = UNIT[prec]
+                if key not in sens:
+                    sens[key] = rounding_sensitivity(prob, b, w.params, K, key, ref)
+                tol = max(tol, SENS_FACTOR * sens[key])
+                say(f"full size caps {name} K={K} precision={prec}: sensitivity {sens[key]:.2e}, tol {tol:.2e}")
+                if tol >= 1e-2:
                     continue
             prm = inputs.Params(**{**w.params.__dict__})
             prm.precision = prec
