@@ -208,6 +208,24 @@ aar_status aar_residual_log(aar_solver s, int32_t instance, double *out, int64_t
  * Cholesky shortcut proved full rank.  Needs AAR_FLAG_RECORD_RESIDUALS. */
 aar_status aar_rank_log(aar_solver s, int32_t instance, int32_t *out, int64_t cap, int64_t *count);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * FP64 solve as aar_solve (precision AAR_FP64, default tile shapes, as with
+ * AAR_FLAG_NO_AUTOTUNE) of one system, with no handle.  The workspace (run
+ * state, partial sums, two copies of x, b, the m + 1 history slots and the
+ * floor(m/p) increment slots) lives in a fixed device array of 32 MiB that
+ * the library holds on every GPU it runs on until the process ends; no device
+ * memory is allocated or freed.  Systems whose workspace exceeds that limit
+ * (about 8 (m + 4 + floor(m/p)) N bytes: a 70^3 grid fits at m = 7, p = 6)
+ * return AAR_ERR_UNSUPPORTED before any device work, as do other precisions
+ * and AAR_FLAG_RECORD_RESIDUALS.  The velocity array, if any, is read in place
+ * and must stay valid for the call.  Work runs on hip_stream (NULL: the
+ * default stream) and the call returns after r has reached the host.  Every
+ * call on one GPU uses that GPU's array: calls that overlap on one GPU (from
+ * several threads or streams) race and must be serialized by the caller. */
+aar_status aar_solve_noalloc(const aar_problem *problem, const aar_params *params, const double *b, double *x,
+                             aar_result *r, void *hip_stream);
+
 /* Device bytes aar_create would allocate for these arguments. */
 aar_status aar_workspace_bytes(const aar_problem *problems, int32_t count, const aar_params *params,
                                size_t *bytes);

@@ -76,6 +76,7 @@ def load_library():
     lib.aar_apply.argtypes = [vp, i32, vp, vp]
     lib.aar_residual_log.argtypes = [vp, i32, P(ctypes.c_double), i64, P(i64)]
     lib.aar_rank_log.argtypes = [vp, i32, P(i32), i64, P(i64)]
+    lib.aar_solve_noalloc.argtypes = [P(aar_problem), P(aar_params), vp, vp, P(aar_result), vp]
     lib.aar_workspace_bytes.argtypes = [P(aar_problem), i32, P(aar_params), P(ctypes.c_size_t)]
     lib.aar_destroy.argtypes = [vp]
     lib.aar_last_error.argtypes = []
@@ -83,7 +84,8 @@ def load_library():
     lib.aar_set_timing.argtypes = [vp, i32]
     lib.aar_sweep_time.argtypes = [vp, P(ctypes.c_double), P(i64)]
     for name in ["aar_create", "aar_solve", "aar_solve_batched", "aar_apply", "aar_residual_log",
-                 "aar_rank_log", "aar_workspace_bytes", "aar_destroy", "aar_set_timing", "aar_sweep_time"]:
+                 "aar_rank_log", "aar_solve_noalloc", "aar_workspace_bytes", "aar_destroy", "aar_set_timing",
+                 "aar_sweep_time"]:
         getattr(lib, name).restype = st
     _lib = lib
     return lib
@@ -127,6 +129,15 @@ def aar_solve_batched(handle, b_ptr: int, x_ptr: int, offsets, count: int) -> li
     _check(load_library().aar_solve_batched(handle, ctypes.c_void_p(b_ptr), ctypes.c_void_p(x_ptr),
                                             offs, res), "aar_solve_batched")
     return list(res)
+
+
+def aar_solve_noalloc(problem: aar_problem, params: aar_params, b_ptr: int, x_ptr: int,
+                      hip_stream: int = 0) -> aar_result:
+    r = aar_result()
+    _check(load_library().aar_solve_noalloc(ctypes.byref(problem), ctypes.byref(params), ctypes.c_void_p(b_ptr),
+                                            ctypes.c_void_p(x_ptr), ctypes.byref(r), ctypes.c_void_p(hip_stream)),
+           "aar_solve_noalloc")
+    return r
 
 
 def aar_apply(handle, instance: int, x_ptr: int, y_ptr: int) -> None:

@@ -667,6 +667,24 @@ aar_status run_cycles(aar_solver_t *S, const Path<T> &P, int64_t max_iter, bool 
     }
     int64_t issued = 0;
     int inflight = 0, slot = 0;
+    if (S->host_status == nullptr) {
+        // no pinned status word (the allocation-free entry point): read the
+        // run state after every group of cycles
+        while (issued < needed) {
+            for (int c = 0; c < kGraphCycles && issued < needed; ++c, ++issued) {
+                hipError_t e = enqueue_cycle<T>(S, P, inner, s, issued);
+                if (e != hipSuccess)
+                    return fail(AAR_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+            }
+            AAR_HIP(hipMemcpyAsync(out, S->state, sizeof(InstState), hipMemcpyDeviceToHost, s));
+            AAR_HIP(hipStreamSynchronize(s));
+            if (out->status != kRunning)
+                break;
+        }
+        AAR_HIP(hipMemcpyAsync(out, S->state, sizeof(InstState), hipMemcpyDeviceToHost, s));
+        AAR_HIP(hipStreamSynchronize(s));
+        return AAR_OK;
+    }
     while (issued < needed) {
         if (use_graph) {
             AAR_HIP(hipGraphLaunch(S->graph, s));
@@ -733,9 +751,8 @@ bool gram_fusable(const TileShape &ts, bool paired_fk, int m, bool f64, Prec his
 }
 
 // Point Path<T> at the workspace for system `idx`.
-template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool f64)
+template <typename T> void bind_path_op(aar_solver_t *S, Path<T> &P, const Operator &op, bool f64)
 {
-    const Operator &op = S->ops[idx];
     P.N = op.N;
     P.radius = op.prob.radius;
     P.conv = op.prob.velocity != nullptr;
@@ -773,6 +790,11 @@ template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool 
         P.st = make_stencil<double>(op, op.vel64);
     else
         P.st = make_stencil<float>(op, op.vel32);
+}
+
+template <typename T> void bind_path(aar_solver_t *S, Path<T> &P, int idx, bool f64)
+{
+    bind_path_op(S, P, S->ops[idx], f64);
 }
 
 // Tile autotuner: time the Richardson sweep for each candidate tile height
@@ -963,6 +985,90 @@ template <typename T> aar_status autotune(aar_solver_t *S, int idx)
     return AAR_OK;
 }
 
+// The FP64 iteration (also with an FP32 or bfloat16 history ring) of one
+// system: x (FP64 device) holds x0 on entry and the answer on exit.
+aar_status solve_fp64(aar_solver_t *S, const Operator &op, const double *b, double *x, aar_result *res,
+                      bool use_graph, int32_t *log_count)
+{
+    const aar_params &pa = S->params;
+    const int64_t N = op.N;
+    hipStream_t s = S->stream;
+    aar_result r{};
+    InstState st{};
+    Path<double> &P = S->p64;
+    bind_path_op(S, P, op, true);
+    if (P.rho_blocks > S->part_rho_cap || P.rho_blocks32 > S->part_rho_cap)
+        return fail(AAR_ERR_DEVICE, "stencil grid exceeds the partial-sum workspace");
+    AAR_HIP(hipMemcpyAsync(P.b, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    AAR_HIP(hipMemcpyAsync(P.xa, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    const int nb_blocks = stream_blocks(N);
+    if (pa.flags & AAR_FLAG_DEFLATE_CONSTANT) {
+        // x_0 += mean(b - A x_0) / sigma; the first history slot is scratch here
+        double *r = static_cast<double *>(P.fring);
+        StencilArgs<double> ra;
+        std::memset(&ra, 0, sizeof(ra));
+        ra.st = P.st;
+        ra.x = P.xa;
+        ra.b = P.b;
+        ra.out = r;
+        ra.partial = S->part_rho;
+        AAR_HIP(launch_stencil_f64(kResid, Prec::F64, P.radius, P.conv, P.ts, ra, nullptr, s));
+        AAR_HIP(launch_deflate(P.xa, r, N, 1.0 / op.prob.shift, S->part_norm, nb_blocks, S->scal, s));
+    }
+    AAR_HIP(launch_norm_partial(true, P.b, N, S->part_norm, nb_blocks, s));
+    AAR_HIP(launch_init_state(S->state, S->part_norm, nb_blocks, pa.max_iter, pa.tol, s));
+    AAR_HIP(hipMemcpyAsync(&st, S->state, sizeof(InstState), hipMemcpyDeviceToHost, s));
+    AAR_HIP(hipStreamSynchronize(s));
+    if (st.nb == 0.0) {
+        AAR_HIP(launch_zero_f64(x, N, s));
+        AAR_HIP(hipStreamSynchronize(s));
+        r.status = AAR_OK;
+        if (res)
+            *res = r;
+        *log_count = 0;
+        return AAR_OK;
+    }
+    aar_status e = run_cycles<double>(S, P, pa.max_iter, false, use_graph, &st);
+    if (e != AAR_OK)
+        return e;
+    if (P.recur || P.recur32) {
+        // the sweeps wrote no x: add the unfinished cycle's Richardson steps
+        AAR_HIP(launch_finalize_f64(P.hist, P.xa, P.fring, S->state, pa.p, pa.m + 1, P.slot_stride, pa.omega, N,
+                                    s));
+        AAR_HIP(hipMemcpyAsync(x, P.xa, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        AAR_HIP(hipStreamSynchronize(s));
+        r.status = status_of(st);
+        r.iterations = (st.status == kMaxIter || st.status == kRunning) ? pa.max_iter : st.iters;
+        r.rel_residual = st.last_r;
+        r.outer_steps = 0;
+        *log_count = st.log_count;
+        if (res)
+            *res = r;
+        return (aar_status)r.status;
+    }
+    // where x ended: after j sweeps of a cycle it is in xb when j is odd
+    const int64_t done = (st.status == kMaxIter || st.status == kRunning) ? pa.max_iter : st.iters;
+    const int64_t j = (done - 1) % pa.p;     // last iteration's position in its cycle
+    const bool anderson_last = (st.status == kMaxIter || st.status == kRunning) && j == pa.p - 1;
+    const double *xf;
+    if (st.status == kConverged || st.status == kBreakdown)
+        xf = ((pa.p - 1) & 1) ? P.xb : P.xa;     // x_k of the Anderson step
+    else if (anderson_last)
+        xf = P.xa;                              // the last iteration was an update
+    else
+        xf = ((j + 1) & 1) ? P.xb : P.xa;       // after j+1 sweeps of the cycle
+    AAR_HIP(hipMemcpyAsync(x, xf, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    AAR_HIP(hipStreamSynchronize(s));
+    r.status = status_of(st);
+    r.iterations = (st.status == kMaxIter || st.status == kRunning) ? pa.max_iter : st.iters;
+    r.rel_residual = st.last_r;
+    r.outer_steps = 0;
+    *log_count = st.log_count;
+    if (res)
+        *res = r;
+    return (aar_status)r.status;
+}
+
 // x (length N, FP64 device) on entry x0, on exit the answer of system idx.
 aar_status solve_one(aar_solver_t *S, int idx, const double *b, double *x, aar_result *res)
 {
@@ -981,78 +1087,10 @@ aar_status solve_one(aar_solver_t *S, int idx, const double *b, double *x, aar_r
     InstState st{};
 
     if (!S->mixed) {
-        Path<double> &P = S->p64;
-        bind_path(S, P, idx, true);
-        if (P.rho_blocks > S->part_rho_cap || P.rho_blocks32 > S->part_rho_cap)
-            return fail(AAR_ERR_DEVICE, "stencil grid exceeds the partial-sum workspace");
-        AAR_HIP(hipMemcpyAsync(P.b, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-        AAR_HIP(hipMemcpyAsync(P.xa, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-        const int nb_blocks = stream_blocks(N);
-        if (pa.flags & AAR_FLAG_DEFLATE_CONSTANT) {
-            // x_0 += mean(b - A x_0) / sigma; the first history slot is scratch here
-            double *r = static_cast<double *>(P.fring);
-            StencilArgs<double> ra;
-            std::memset(&ra, 0, sizeof(ra));
-            ra.st = P.st;
-            ra.x = P.xa;
-            ra.b = P.b;
-            ra.out = r;
-            ra.partial = S->part_rho;
-            AAR_HIP(launch_stencil_f64(kResid, Prec::F64, P.radius, P.conv, P.ts, ra, nullptr, s));
-            AAR_HIP(launch_deflate(P.xa, r, N, 1.0 / op.prob.shift, S->part_norm, nb_blocks, S->scal, s));
-        }
-        AAR_HIP(launch_norm_partial(true, P.b, N, S->part_norm, nb_blocks, s));
-        AAR_HIP(launch_init_state(S->state, S->part_norm, nb_blocks, pa.max_iter, pa.tol, s));
-        AAR_HIP(hipMemcpyAsync(&st, S->state, sizeof(InstState), hipMemcpyDeviceToHost, s));
-        AAR_HIP(hipStreamSynchronize(s));
-        if (st.nb == 0.0) {
-            AAR_HIP(launch_zero_f64(x, N, s));
-            AAR_HIP(hipStreamSynchronize(s));
-            r.status = AAR_OK;
-            if (res)
-                *res = r;
-            S->last_log_count[idx] = 0;
-            return AAR_OK;
-        }
-        aar_status e = run_cycles<double>(S, P, pa.max_iter, false, use_graph, &st);
-        if (e != AAR_OK)
-            return e;
-        if (P.recur || P.recur32) {
-            // the sweeps wrote no x: add the unfinished cycle's Richardson steps
-            AAR_HIP(launch_finalize_f64(P.hist, P.xa, P.fring, S->state, pa.p, pa.m + 1, P.slot_stride, pa.omega, N,
-                                        s));
-            AAR_HIP(hipMemcpyAsync(x, P.xa, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-            AAR_HIP(hipStreamSynchronize(s));
-            r.status = status_of(st);
-            r.iterations = (st.status == kMaxIter || st.status == kRunning) ? pa.max_iter : st.iters;
-            r.rel_residual = st.last_r;
-            r.outer_steps = 0;
-            S->last_log_count[idx] = st.log_count;
-            if (res)
-                *res = r;
-            return (aar_status)r.status;
-        }
-        // where x ended: after j sweeps of a cycle it is in xb when j is odd
-        const int64_t done = (st.status == kMaxIter || st.status == kRunning) ? pa.max_iter : st.iters;
-        const int64_t j = (done - 1) % pa.p;     // last iteration's position in its cycle
-        const bool anderson_last = (st.status == kMaxIter || st.status == kRunning) && j == pa.p - 1;
-        const double *xf;
-        if (st.status == kConverged || st.status == kBreakdown)
-            xf = ((pa.p - 1) & 1) ? P.xb : P.xa;     // x_k of the Anderson step
-        else if (anderson_last)
-            xf = P.xa;                              // the last iteration was an update
-        else
-            xf = ((j + 1) & 1) ? P.xb : P.xa;       // after j+1 sweeps of the cycle
-        AAR_HIP(hipMemcpyAsync(x, xf, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-        AAR_HIP(hipStreamSynchronize(s));
-        r.status = status_of(st);
-        r.iterations = (st.status == kMaxIter || st.status == kRunning) ? pa.max_iter : st.iters;
-        r.rel_residual = st.last_r;
-        r.outer_steps = 0;
-        S->last_log_count[idx] = st.log_count;
-        if (res)
-            *res = r;
-        return (aar_status)r.status;
+        int32_t lc = 0;
+        const aar_status e = solve_fp64(S, op, b, x, res, use_graph, &lc);
+        S->last_log_count[idx] = lc;
+        return e;
     }
 
     // ---- mixed precision: FP64 refinement around FP32 AAR ----
@@ -1805,6 +1843,143 @@ aar_status batch_solve(aar_solver_t *S, const double *b, double *x, const int64_
     }
     return worst;
 }
+// ---------------------------------------------------------------------------
+// Allocation-free solve (aar_solve_noalloc): the workspace of one FP64 solve
+// is carved from a fixed device array instead of device allocations.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+
+// Each GPU the library runs on holds its own copy of this array until the
+// process ends.  In host code `scratch` names a host-side stand-in; the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device, with it current).
+aar_status scratch_address(int device, unsigned char **out)
+{
+    if (device < 0 || device >= kMaxScratchDevices)
+        return fail(AAR_ERR_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(AAR_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = static_cast<unsigned char *>(g_scratch_ptr[device]);
+    return AAR_OK;
+}
+
+// Byte layout of the scratch workspace of one FP64 solve: run state, the
+// partial sums of the stencil, Gram and norm passes, then x (two copies), b,
+// the m + 1 history slots and the floor(m/p) increment slots, each vector on a
+// 4 KiB boundary (slots stay 8-element aligned).
+struct NoAllocLayout {
+    size_t state, rho, gram, norm, gfinal, scal, xa, xb, b, ring, dx, total;
+    int64_t slot_stride;       // elements between ring slots (and between dx slots)
+    int rho_cap;
+};
+
+NoAllocLayout noalloc_layout(const aar_problem &pr, const aar_params &pa)
+{
+    const Sizes z = compute_sizes(&pr, 1, &pa);
+    NoAllocLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    const int64_t Np = (z.maxN + 7) / 8 * 8;
+    const size_t span = ((size_t)Np * sizeof(double) + 4095) / 4096 * 4096;
+    L.state = take(sizeof(InstState));
+    L.rho = take(sizeof(double) * (size_t)z.max_stencil_blocks);
+    L.gram = take(sizeof(double) * (size_t)std::max(z.gram_blocks, z.max_stencil_blocks) * z.ne);
+    L.norm = take(sizeof(double) * (size_t)z.gram_blocks);
+    L.gfinal = take(sizeof(double) * (size_t)z.ne);
+    L.scal = take(sizeof(double) * 8);
+    off = (off + 4095) / 4096 * 4096;
+    L.xa = take(span);
+    L.xb = take(span);
+    L.b = take(span);
+    L.ring = take(span * (size_t)(pa.m + 1));
+    L.dx = take(span * (size_t)z.q);
+    L.total = off;
+    L.slot_stride = (int64_t)(span / sizeof(double));
+    L.rho_cap = z.max_stencil_blocks;
+    return L;
+}
+
+aar_status solve_noalloc(const aar_problem *problem, const aar_params *params, const double *b, double *x,
+                         aar_result *res, void *hip_stream)
+{
+    if (!problem || !params || !b || !x)
+        return fail(AAR_ERR_INVALID_ARG, "problem, params, b or x is NULL");
+    aar_status st = validate_params(params);
+    if (st != AAR_OK)
+        return st;
+    if ((st = validate_problem(*problem, 0)) != AAR_OK)
+        return st;
+    if (params->precision != AAR_FP64)
+        return fail(AAR_ERR_UNSUPPORTED, "aar_solve_noalloc runs the FP64 iteration only");
+    if (params->flags & AAR_FLAG_RECORD_RESIDUALS)
+        return fail(AAR_ERR_UNSUPPORTED, "aar_solve_noalloc keeps no residual log");
+    if (params->flags & AAR_FLAG_DEFLATE_CONSTANT) {
+        const aar_problem &pr = *problem;
+        if (!(pr.bc[0] == AAR_BC_PERIODIC && pr.bc[1] == AAR_BC_PERIODIC && pr.bc[2] == AAR_BC_PERIODIC &&
+              pr.shift > 0.0))
+            return fail(AAR_ERR_UNSUPPORTED, "AAR_FLAG_DEFLATE_CONSTANT needs periodic axes and shift > 0");
+    }
+    const NoAllocLayout L = noalloc_layout(*problem, *params);
+    if (L.total > kScratchBytes)
+        return fail(AAR_ERR_UNSUPPORTED, "system needs " + std::to_string(L.total) +
+                                             " bytes of scratch; aar_solve_noalloc holds " +
+                                             std::to_string(kScratchBytes));
+    int device = 0;
+    AAR_HIP(hipGetDevice(&device));
+    unsigned char *base = nullptr;
+    if ((st = scratch_address(device, &base)) != AAR_OK)
+        return st;
+
+    // the operator: tile shapes are the defaults (no timing, no tile file);
+    // the caller's velocity array is read in place
+    Operator op = build_operator(*problem);
+    op.vel64 = const_cast<double *>(problem->velocity);
+    aar_solver_t S;
+    S.params = *params;
+    S.stream = (hipStream_t)hip_stream;
+    S.device = device;
+    S.mixed = false;
+    S.hist = Prec::F64;
+    S.maxN = op.N;
+    S.q = params->m / params->p;
+    S.ne = params->m * (params->m + 1) / 2 + params->m;
+    S.state = reinterpret_cast<InstState *>(base + L.state);
+    S.part_rho = reinterpret_cast<double *>(base + L.rho);
+    S.part_rho_cap = L.rho_cap;
+    S.part_gram = reinterpret_cast<double *>(base + L.gram);
+    S.part_norm = reinterpret_cast<double *>(base + L.norm);
+    S.gram_final = reinterpret_cast<double *>(base + L.gfinal);
+    S.scal = reinterpret_cast<double *>(base + L.scal);
+    Path<double> &P = S.p64;
+    P.hist = Prec::F64;
+    P.xa = reinterpret_cast<double *>(base + L.xa);
+    P.xb = reinterpret_cast<double *>(base + L.xb);
+    P.b = reinterpret_cast<double *>(base + L.b);
+    P.fring = base + L.ring;
+    P.dx = S.q > 0 ? (void *)(base + L.dx) : nullptr;
+    S.slot_stride[0] = L.slot_stride;
+    S.dx_stride64 = L.slot_stride;
+    int32_t lc = 0;
+    return solve_fp64(&S, op, b, x, res, false, &lc);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1987,6 +2162,13 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
     }
     *out = S.release();
     return AAR_OK;
+}
+
+aar_status aar_solve_noalloc(const aar_problem *problem, const aar_params *params, const double *b, double *x,
+                             aar_result *r, void *hip_stream)
+{
+    g_error.clear();
+    return solve_noalloc(problem, params, b, x, r, hip_stream);
 }
 
 aar_status aar_destroy(aar_solver s)
