@@ -23,14 +23,30 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 OK, NOT_CONVERGED, BREAKDOWN, BAD_ARG = 0, 1, 2, -1
 
 
+# gcc flags of the oracle: optimized, ISO C (no floating-point contraction or
+# reassociation, so every build computes the same bits), OpenMP static loops
+CFLAGS = ["-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11"]
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP) into oracle/liboracle.so."""
+    """Compile the oracle with gcc (CFLAGS) into oracle/liboracle.so (portable:
+    no -march, so the library runs on any x86-64 host it is copied to)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                               "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def load_native(dirpath: str):
+    """Build the oracle with CFLAGS plus -march=native for the host that runs
+    this (the CPU baseline's build) into `dirpath`, load it, and make it the
+    library every function here calls.  Returns the flags used."""
+    flags = CFLAGS + ["-march=native"]
+    path = os.path.join(dirpath, "liboracle_native.so")
+    subprocess.check_call(["gcc", *flags, "-o", path, _SRC, "-lm"])
+    _load_from(path)
+    return flags
 
 
 class _Problem(ctypes.Structure):
@@ -43,29 +59,35 @@ _lib = None
 
 
 def _load():
-    global _lib
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
-        lib = ctypes.CDLL(_LIB)
-        dp = ctypes.POINTER(ctypes.c_double)
-        pp = ctypes.POINTER(_Problem)
-        lib.oracle_fd_weights.argtypes = [ctypes.c_int, dp]
-        lib.oracle_apply.argtypes = [pp, dp, dp]
-        lib.oracle_diagonal.argtypes = [pp, dp]
-        lib.oracle_jacobi_eigen.argtypes = [ctypes.c_int, dp, dp]
-        lib.oracle_pinv_solve.argtypes = [ctypes.c_int, dp, dp, dp]
-        lib.oracle_pinv_solve.restype = ctypes.c_int
-        lib.oracle_aar_solve.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                                         ctypes.c_int, ctypes.c_double, ctypes.c_int64,
-                                         ctypes.POINTER(ctypes.c_int64), dp, dp, ctypes.c_int64,
-                                         ctypes.POINTER(ctypes.c_int64)]
-        lib.oracle_aar_solve.restype = ctypes.c_int
-        lib.oracle_relative_residual.argtypes = [pp, dp, dp]
-        lib.oracle_relative_residual.restype = ctypes.c_double
-        lib.oracle_threads.restype = ctypes.c_int
-        _lib = lib
+        _load_from(_LIB)
     return _lib
+
+
+def _load_from(path: str):
+    global _lib
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    pp = ctypes.POINTER(_Problem)
+    lib.oracle_fd_weights.argtypes = [ctypes.c_int, dp]
+    lib.oracle_apply.argtypes = [pp, dp, dp]
+    lib.oracle_diagonal.argtypes = [pp, dp]
+    lib.oracle_jacobi_eigen.argtypes = [ctypes.c_int, dp, dp]
+    lib.oracle_pinv_solve.argtypes = [ctypes.c_int, dp, dp, dp]
+    lib.oracle_pinv_solve.restype = ctypes.c_int
+    lib.oracle_aar_solve.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_double, ctypes.c_int64,
+                                     ctypes.POINTER(ctypes.c_int64), dp, dp, ctypes.c_int64,
+                                     ctypes.POINTER(ctypes.c_int64)]
+    lib.oracle_aar_solve.restype = ctypes.c_int
+    lib.oracle_relative_residual.argtypes = [pp, dp, dp]
+    lib.oracle_relative_residual.restype = ctypes.c_double
+    lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_deflate_constant.argtypes = [pp, dp, dp]
+    lib.oracle_deflate_constant.restype = ctypes.c_int
+    _lib = lib
 
 
 def _ptr(a: np.ndarray):
@@ -166,6 +188,17 @@ def aar_solve(prob, b, x0=None, omega=0.6, beta=0.6, m=7, p=6, tol=1e-10, max_it
     if trace_cap > 0:
         out["trace"] = tr[: tl.value].copy()
     return out
+
+
+def deflate_constant(prob, b, x0=None) -> np.ndarray:
+    """The solver's optional constant-mode step (not in the paper): for an
+    all-periodic system with sigma > 0, x0 + (mean(b - A x0) / sigma) 1, whose
+    residual has zero mean (A 1 = sigma 1).  Raises ValueError otherwise."""
+    bd = _Bound(prob)
+    x = np.zeros(bd.size) if x0 is None else _f64(x0).copy()
+    if _load().oracle_deflate_constant(bd.ref, _ptr(_f64(b)), _ptr(x)) != OK:
+        raise ValueError("the constant-mode step needs every axis periodic and shift > 0")
+    return x
 
 
 def relative_residual(prob, b, x) -> float:

@@ -526,6 +526,35 @@ double oracle_relative_residual(const oracle_problem *P, const double *b, const 
     return den > 0.0 ? sqrt(num) / sqrt(den) : sqrt(num);
 }
 
+/*
+ * The constant-mode step of the solver's optional deflation (not part of the
+ * paper's method).  When every axis is periodic the constant vector 1 is an
+ * eigenvector of A with eigenvalue sigma: each row of the central second
+ * difference sums to zero (w_0 = -2 sum w_s) and the upwind differences of a
+ * constant vanish, so A 1 = sigma 1.  For sigma > 0, with r = b - A x, the
+ * step x <- x + (mean r / sigma) 1 changes the residual to r - (mean r) 1,
+ * whose mean is zero; the solution of A x = b is unchanged.  Written out from
+ * that definition: one application of A, the mean as a plain sum over the
+ * grid, and the shift of every value.  Returns ORACLE_BAD_ARG unless every
+ * axis is periodic and sigma > 0.
+ */
+int oracle_deflate_constant(const oracle_problem *P, const double *b, double *x)
+{
+    if (P->bc[0] != 1 || P->bc[1] != 1 || P->bc[2] != 1 || !(P->shift > 0.0))
+        return ORACLE_BAD_ARG;
+    const int64_t N = problem_size(P);
+    double *ax = malloc(sizeof(double) * N);
+    oracle_apply(P, x, ax);
+    double sum = 0.0;
+    for (int64_t i = 0; i < N; ++i)
+        sum += b[i] - ax[i];
+    const double shift = (sum / (double)N) / P->shift;
+    for (int64_t i = 0; i < N; ++i)
+        x[i] += shift;
+    free(ax);
+    return ORACLE_OK;
+}
+
 int oracle_threads(void)
 {
 #ifdef _OPENMP
