@@ -4,21 +4,32 @@ A step is one complete AAR solve (every stage of the iteration: fused
 Richardson sweeps, Anderson residual and Gram reduction, pseudoinverse
 solve, update; plus FP64 refinement in mixed mode) of one seeded synthetic
 system whose right-hand side and solver workspace are already resident in
-HBM.  Default workload: periodic Poisson, 192^3 grid, 12th-order central
-differences (37-point stencil), 64 Gaussian charges minus their mean,
-Jacobi preconditioner, omega = beta = 0.6, m = 7, p = 6, tol 1e-10, FP64.
-The same grid is also solved in mixed precision (FP32 iteration inside FP64
-refinement) and as FP64 with an FP32 history ring, each reported beside it
-with the speedup over FP64, and the batched workload (512 shifted Helmholtz
-systems in one call) runs in FP64 and mixed precision.
+HBM.  The headline (`value`) is the largest single-grid workload at the
+paper's arithmetic: periodic Poisson 256^3, 12th-order central differences
+(37-point stencil), 64 Gaussian charges minus their mean, Jacobi
+preconditioner, omega = beta = 0.6, m = 7, p = 6, tol 1e-10, FP64.
 
-Prints one JSON line.  `roofline` covers the dominant kernel (the fused
-Richardson sweep): algorithmic bytes per launch (read x and b, write x and
-f: 4 values per grid point) over the mean launch time measured with HIP
-events on the solver's stream, against the 8 TB/s HBM peak and against a
-measured 1 GiB device copy.  `cpu_baseline` times the CPU oracle on a
-bounded number of iterations of the same system and scales to solves/s with
-the oracle's own iteration count.
+Beside it, in the same JSON line, every other evaluation workload and mode,
+each with solves/s, iterations, the speedup over FP64 on the same system and
+the error against the oracle's stored FP64 solution:
+  c3_256   the headline grid in mixed precision (FP32 inner AAR + FP64
+           refinement; FP32 or bfloat16 history) and FP64 with an FP32 ring;
+  c2_192   the same problem at 192^3 (FP64, mixed, FP64 + FP32 ring);
+  c4_128   nonsymmetric convection-diffusion 128^3, m = 10, p = 4;
+  c1_32    Dirichlet Poisson 32^3 at 1e-8 (FP64) and 1e-10 (FP64, mixed),
+           reported as microseconds per iteration (launch-bound size);
+  batched  512 periodic shifted Helmholtz systems of uneven sizes in one call:
+           the paper's method in FP64 and, with the exact constant-mode
+           deflation (not in the paper), FP64, mixed and FP64 + FP32 ring;
+           each with a whole-call bandwidth figure.
+`roofline` covers the dominant kernel of the headline, the Richardson sweep:
+algorithmic bytes per launch over the mean launch time measured with HIP
+events on the solver's stream, against the 8 TB/s HBM peak.  Each solve also
+gets an effective bandwidth: the method's algorithmic bytes per cycle (model
+in cycle_bytes) times its cycles, over the solve time.  `cpu_baseline` times
+the oracle (built -O3 -march=native on this host) on a bounded number of
+iterations of the headline system and scales to solves/s with the oracle's
+own iteration count.
 """
 from __future__ import annotations
 
@@ -26,6 +37,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -34,15 +46,23 @@ if ROOT not in sys.path:
 
 METRIC = "AAR solves/s and sweep HBM GB/s at 1e-10 rel-residual: mixed/batched vs FP64"
 HBM_PEAK_GBS = 8000.0
-# Oracle (FP64, CPU) iterations to 1e-10 on the default workload, written by
-# tests/golden/make_golden.py (oracle only).
+# Oracle (FP64, CPU) solutions at full size, written by tests/golden/make_golden.py (oracle only).
 GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_full_size.json")
-# HBM traffic of the sweep kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
-# scaled by a plain copy's counters; valid while the stencil sources and the
-# grid's tile shape are those it was measured with.
-SWEEP_PROFILE = os.path.join(ROOT, "profiles", "k_stencil2_sweep_fp64_r6_192.md")
+# HBM traffic of the headline sweep kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs, scaled by a plain copy's counters; valid while the stencil sources and
+# the grid's tile shape are those it was measured with.
+PROFILE_DIR = os.path.join(ROOT, "profiles")
 STENCIL_SRCS = [os.path.join(ROOT, "paper_1606_08740_amd", "csrc", f)
                 for f in ("stencil_kernels.h", "stencil.hip", "stencil_narrow.hip", "stencil_f32.hip")]
+
+FP64, MIXED, MIXED_BF16, FP64_FP32HIST, FP64_BF16HIST = 0, 1, 2, 3, 4
+MODE_NAMES = {FP64: "fp64", MIXED: "mixed_fp32", MIXED_BF16: "mixed_fp32_bf16hist",
+              FP64_FP32HIST: "fp64_fp32hist", FP64_BF16HIST: "fp64_bf16hist"}
+
+
+def log(msg):
+    """Progress on stderr (the JSON line is the only stdout output)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def stencil_sha():
@@ -74,18 +94,69 @@ def fp64_tile(n, radius=6):
     return tile
 
 
-def sweep_traffic(n):
-    """Counter-measured bytes per sweep launch, or None when absent or stale."""
+def sweep_profile(n):
+    """The machine-readable record of profiles/k_stencil*_sweep_fp64_r6_<n>.md, or None."""
+    import glob
     import re
-    if n != 192 or not os.path.exists(SWEEP_PROFILE):
-        return None
-    m = re.search(r"```json\n(.*?)\n```", open(SWEEP_PROFILE).read(), flags=re.S)
-    if not m:
-        return None
-    rec = json.loads(m.group(1))
-    if rec.get("stencil_source_sha256_16") != stencil_sha() or rec.get("tile") != fp64_tile(n):
+    for path in sorted(glob.glob(os.path.join(PROFILE_DIR, f"k_stencil*_sweep_fp64_r6_{n}.md"))):
+        m = re.search(r"```json\n(.*?)\n```", open(path).read(), flags=re.S)
+        if m:
+            return json.loads(m.group(1))
+    return None
+
+
+def sweep_traffic(n):
+    """Counter-measured bytes per sweep launch at n^3, or None when absent or
+    stale (other stencil sources or another tile shape)."""
+    rec = sweep_profile(n)
+    if rec is None or rec.get("stencil_source_sha256_16") != stencil_sha() or rec.get("tile") != fp64_tile(n):
         return None
     return rec.get("traffic_bytes_per_launch")
+
+
+def sweep_bytes_per_point(m, p):
+    """Algorithmic bytes per point of one FP64 Richardson sweep launch,
+    averaged over a cycle's p - 1 sweeps.  With the residual recursion
+    (m + 1 >= p >= 2) the first sweep reads x and b and writes f (24 B), the
+    others read f_j and write f_{j+1} (16 B); otherwise each reads x and b and
+    writes x and f (32 B)."""
+    if m + 1 >= p >= 2:
+        return (3 * 8 + (p - 2) * 2 * 8) / (p - 1)
+    return 32.0
+
+
+def cycle_bytes(precision, m, p, fused_gram=False):
+    """Algorithmic bytes per grid point of one AAR cycle (p iterations) of the
+    given mode: every vector a pass must read or write, counted once.
+      FP64: first sweep 2s + s_h, the others 2 s_h (recursion) or 3s + s_h;
+        Anderson residual 2 s_h (recursion) or 2s + s_h; Gram (m + 1) s_h
+        (fused into the residual pass: the slots it did not read); update x,
+        m + 1 slots, q increments, x and one increment written.
+      FP64 + FP32 ring: as FP64 with 4-byte slots and increments, the later
+        sweeps and the residual over the ring only.
+      Mixed: the inner FP32 cycles (FP32 iterate and ring, recursion); the
+        FP64 refinement passes (a few per solve) are left out.
+    Returns None for the bfloat16-history modes (not modelled)."""
+    q = m // p
+    rec = m + 1 >= p >= 2
+    if precision == FP64:
+        s = sh = sdx = 8
+    elif precision == FP64_FP32HIST:
+        s, sh, sdx = 8, 4, 4
+    elif precision == MIXED:
+        s = sh = sdx = 4
+    else:
+        return None
+    if rec:
+        sweeps = (2 * s + sh) + (p - 2) * 2 * sh
+        resid = 2 * sh
+        gram = (m - 1) * sh if fused_gram else (m + 1) * sh
+    else:
+        sweeps = (p - 1) * (3 * s + sh)
+        resid = 2 * s + sh
+        gram = m * sh if fused_gram else (m + 1) * sh
+    update = s + (m + 1) * sh + q * sdx + s + sdx
+    return sweeps + resid + gram + update
 
 
 def parse():
@@ -93,20 +164,19 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=192)
-    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--n", type=int, default=256, help="headline grid edge (periodic Poisson, radius 6)")
+    ap.add_argument("--side-steps", type=int, default=3, help="timed solves per side measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=180)
+    ap.add_argument("--cpu-sample-iters", type=int, default=120)
     ap.add_argument("--kernel-timing-solves", type=int, default=1)
-    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--only", choices=["headline", "c1", "c2", "c3", "c4", "c5"],
+                    help="run one part only and print its JSON object (for profiling)")
+    ap.add_argument("--precision", type=int, choices=[0, 1, 2, 3, 4],
+                    help="with --only: the one precision mode to time")
     ap.add_argument("--batched-count", type=int, default=512)
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--batched-only", action="store_true",
-                    help="only run the batched part (for profiling it); prints its JSON object")
-    ap.add_argument("--precision-only", choices=["mixed_fp32", "fp64_fp32hist"],
-                    help="only time this precision mode on the headline system (for profiling it)")
     return ap.parse_args()
 
 
@@ -140,16 +210,20 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8}))
 
 
-def oracle_sample_error(x, n):
+def golden(key):
+    if not os.path.exists(GOLDEN):
+        return None
+    return json.load(open(GOLDEN)).get(key)
+
+
+def oracle_sample_error(x, n, key=None):
     """Max |x - x_oracle| over the 64 seeded sample points stored in the golden
     file (the oracle's FP64 solution of the same system, mean-free when the
     system is singular periodic), divided by the RMS of the oracle's solution;
-    None when no stored solution exists for this size."""
+    None when no stored solution exists for this system."""
     import numpy as np
-    if not os.path.exists(GOLDEN):
-        return None
-    g = json.load(open(GOLDEN)).get(f"periodic_poisson_r6_{n}")
-    if g is None:
+    g = golden(key or f"periodic_poisson_r6_{n}")
+    if g is None or int(np.prod(g["n"])) != x.size:
         return None
     xs = x - x.mean() if g["mean_free"] else x
     rms = g["x_norm"] / np.sqrt(x.size)
@@ -172,24 +246,73 @@ def timed_solves(solver, bt, steps, warmup):
     return dt, res, xs[-1]
 
 
-def run_batched(args):
+def fused_gram_used(n, m, radius=6):
+    """Whether the FP64 Anderson-residual pass forms the Gram products itself
+    (paired tile, 8 or fewer waves, m = 7) for this grid."""
+    tile = fp64_tile(n, radius)
+    return tile is not None and 0 < tile["pair"] <= 2 and m == 7
+
+
+def run_modes(w, key, modes, steps, warmup, n=None):
+    """Solve the workload's system in each mode; returns {mode: record} plus
+    the FP64 solve's seconds per solve (when FP64 is among the modes)."""
+    import torch
+    from paper_1606_08740_amd import aar, inputs
+    prob, b = w.problems[0], w.b[0]
+    bt = torch.as_tensor(b, device="cuda:0")
+    out, t64 = {}, None
+    for prec in modes:
+        log(f"{w.name} {MODE_NAMES[prec]}")
+        pm = inputs.Params(**{**w.params.__dict__})
+        pm.precision = prec
+        s = aar.Solver([prob], pm)
+        dt, r, xt = timed_solves(s, bt, steps, warmup)
+        s.close()
+        x = xt.cpu().numpy()
+        per = dt / steps
+        rec = {"value": 1.0 / per, "unit": "solves/s", "ms_per_solve": per * 1e3, "iterations": r["iterations"],
+               "outer_steps": r["outer_steps"], "rel_residual": r["rel_residual"], "status": r["status"],
+               "error_vs_oracle": oracle_sample_error(x, n or 0, key)}
+        cb = cycle_bytes(prec, pm.m, pm.p, fused_gram=(prec == FP64 and n is not None and fused_gram_used(n, pm.m)))
+        if cb is not None and r["iterations"] > 0:
+            gbs = prob.size * cb * (r["iterations"] / pm.p) / per / 1e9
+            rec["effective_GBs"] = gbs
+            rec["effective_frac_of_peak"] = gbs / HBM_PEAK_GBS
+            rec["bytes_per_point_per_cycle"] = cb
+        if prec == FP64:
+            t64 = per
+        out[MODE_NAMES[prec]] = rec
+        del xt
+    if t64 is not None:
+        for name, rec in out.items():
+            rec["speedup_vs_fp64"] = t64 / (rec["ms_per_solve"] * 1e-3)
+    del bt
+    return out
+
+
+def run_batched(args, modes=None):
     """The batched workload: 512 shifted periodic Helmholtz systems of uneven
-    sizes solved by one aar_solve_batched call: FP64, mixed precision, and
-    FP64 with an FP32 history ring."""
+    sizes solved by one aar_solve_batched call, in the paper's plain method
+    (FP64) and with the exact constant-mode deflation (FP64, mixed, FP64 +
+    FP32 ring).  Whole-call bandwidth: sum over systems of points x cycles x
+    the mode's bytes per point and cycle, over the call time."""
     import numpy as np
     import torch
-
     from paper_1606_08740_amd import aar, inputs
     wb = inputs.workload(5, count=args.batched_count)
     bb = torch.as_tensor(np.concatenate(wb.b), device="cuda:0")
+    sizes = np.array([p.size for p in wb.problems], dtype=np.float64)
     res_out = {"workload": f"{args.batched_count} periodic shifted Helmholtz systems, 8th-order "
-                           "central FD (25-point), n ~ U{16..96}, sigma ~ U(0,10), b ~ N(0,1), "
-                           "exact constant-mode deflation, tol 1e-10",
-               "points": int(sum(p.size for p in wb.problems))}
-    for label, prec in [("fp64", aar.AAR_FP64), ("mixed_fp32", aar.AAR_MIXED_FP32),
-                        ("fp64_fp32hist", aar.AAR_FP64_FP32HIST)]:
+                           "central FD (25-point), n ~ U{16..96}, sigma ~ U(0,10), b ~ N(0,1), tol 1e-10",
+               "points": int(sizes.sum()), "min_shift": float(min(p.shift for p in wb.problems))}
+    runs = modes or [("fp64_plain", FP64, 0), ("fp64", FP64, aar.AAR_FLAG_DEFLATE_CONSTANT),
+                     ("mixed_fp32", MIXED, aar.AAR_FLAG_DEFLATE_CONSTANT),
+                     ("fp64_fp32hist", FP64_FP32HIST, aar.AAR_FLAG_DEFLATE_CONSTANT)]
+    for label, prec, flags in runs:
+        log(f"batched {label}")
         pb = inputs.Params(**{**wb.params.__dict__})
         pb.precision = prec
+        pb.flags = flags
         sb = aar.Solver(wb.problems, pb)
         res = None
         for _ in range(max(args.warmup, 1)):
@@ -203,16 +326,122 @@ def run_batched(args):
         torch.cuda.synchronize()
         dtb = (time.perf_counter() - t0) / args.batched_steps
         sb.close()
-        its = [r["iterations"] for r in res]
-        res_out[label] = {"value": args.batched_count / dtb, "unit": "solves/s",
-                          "ms_per_call": dtb * 1e3,
-                          "converged": int(sum(r["status"] == 0 for r in res)),
-                          "iterations_total": int(sum(its)), "iterations_max": int(max(its)),
-                          "max_rel_residual": float(max(r["rel_residual"] for r in res))}
-    res_out["mixed_speedup_vs_fp64"] = res_out["mixed_fp32"]["value"] / res_out["fp64"]["value"]
-    res_out["fp64_fp32hist_speedup_vs_fp64"] = res_out["fp64_fp32hist"]["value"] / res_out["fp64"]["value"]
+        its = np.array([r["iterations"] for r in res], dtype=np.float64)
+        rec = {"value": args.batched_count / dtb, "unit": "solves/s", "ms_per_call": dtb * 1e3,
+               "deflated": bool(flags & aar.AAR_FLAG_DEFLATE_CONSTANT),
+               "converged": int(sum(r["status"] == 0 for r in res)),
+               "iterations_total": int(its.sum()), "iterations_max": int(its.max()),
+               "max_rel_residual": float(max(r["rel_residual"] for r in res))}
+        cb = cycle_bytes(prec, pb.m, pb.p)
+        if cb is not None:
+            gbs = float((sizes * (its / pb.p)).sum()) * cb / dtb / 1e9
+            rec["effective_GBs"] = gbs
+            rec["effective_frac_of_peak"] = gbs / HBM_PEAK_GBS
+            rec["bytes_per_point_per_cycle"] = cb
+        res_out[label] = rec
+    if "fp64" in res_out:
+        for label, _, _ in runs:
+            res_out[label]["speedup_vs_fp64_deflated"] = res_out[label]["value"] / res_out["fp64"]["value"]
     del bb
     return res_out
+
+
+def headline(args):
+    """The headline FP64 solve, its sweep-kernel roofline and error."""
+    import numpy as np
+    import torch
+    from paper_1606_08740_amd import aar, inputs
+    w = inputs.workload(3, n=args.n, precision=FP64) if args.n != 192 else inputs.workload(2)
+    prob, b = w.problems[0], w.b[0]
+    N = prob.size
+    prm = w.params
+    prm.precision = FP64
+    bt = torch.as_tensor(b, device="cuda:0")
+    log(f"headline {w.name} fp64")
+    s64 = aar.Solver([prob], prm)
+    dt64, r64, x64 = timed_solves(s64, bt, args.steps, args.warmup)
+    # kernel timing: one HIP event pair around each cycle's p - 1 consecutive
+    # sweep launches, on the solver's stream (one extra solve)
+    s64.set_timing(True)
+    for _ in range(args.kernel_timing_solves):
+        xt = torch.zeros_like(bt)
+        s64.solve(bt, xt)
+    ms_tot, launches = s64.sweep_time()
+    s64.set_timing(False)
+    s64.close()
+    sweep_us = ms_tot / max(launches, 1) * 1e3
+    bpp = sweep_bytes_per_point(prm.m, prm.p)
+    sweep_bytes = bpp * N
+    achieved = sweep_bytes / (sweep_us * 1e-6) / 1e9
+    tile = fp64_tile(args.n)
+    per = dt64 / args.steps
+    cb = cycle_bytes(FP64, prm.m, prm.p, fused_gram=fused_gram_used(args.n, prm.m))
+    eff = N * cb * (r64["iterations"] / prm.p) / per / 1e9
+    key = f"periodic_poisson_r6_{args.n}"
+    x = x64.cpu().numpy()
+    out = {
+        "dt": dt64, "r": r64, "N": N,
+        "config": {"workload": f"periodic Poisson {args.n}^3, 12th-order central FD (37-point), "
+                               "64 Gaussian charges minus mean, Jacobi, omega=beta=0.6, m=7, p=6, "
+                               "tol 1e-10, FP64",
+                   "grid": [args.n] * 3, "radius": 6, "m": prm.m, "p": prm.p, "tol": prm.tol, "precision": "fp64",
+                   "tile": tile},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic(args.n),
+                     "kernel": "Richardson sweep (FP64, radius 6): a cycle's first from x and b, the others "
+                               "by the residual recursion f_{j+1} = f_j - omega D^-1 A f_j",
+                     "bytes_per_point": bpp, "bytes_per_launch": sweep_bytes, "mean_launch_us": sweep_us,
+                     "launches": launches},
+        "solve": {"effective_GBs": eff, "effective_frac_of_peak": eff / HBM_PEAK_GBS,
+                  "bytes_per_point_per_cycle": cb,
+                  "error_vs_oracle": oracle_sample_error(x, args.n, key),
+                  "oracle_iterations": (golden(key) or {}).get("iterations")},
+    }
+    del bt, x64
+    return out, w
+
+
+def cpu_baseline(args, w):
+    """The oracle, built -O3 -march=native here, on a bounded sample of the
+    headline system (the first cpu_sample_iters iterations), scaled to
+    solves/s by the oracle's own iteration count."""
+    import oracle
+    prob, b, prm = w.problems[0], w.b[0], w.params
+    log("cpu baseline")
+    with tempfile.TemporaryDirectory() as d:
+        flags = oracle.load_native(d)
+        k = args.cpu_sample_iters
+        t0 = time.perf_counter()
+        oracle.aar_solve(prob, b, m=prm.m, p=prm.p, tol=1e-30, max_iter=k)
+        dtc = time.perf_counter() - t0
+        cores = oracle.threads()
+    g = golden(f"periodic_poisson_r6_{args.n}")
+    iters_full = g["iterations"] if g else None
+    basis = "the oracle's iterations to 1e-10 (tests/golden)" if iters_full else "no stored count: per iteration"
+    return {"value": 1.0 / (dtc / k * iters_full) if iters_full else k / dtc,
+            "unit": "solves/s" if iters_full else "iterations/s", "cores": cores, "kind": "oracle",
+            "build": "gcc " + " ".join(flags),
+            "sample": f"{k} AAR iterations of the {args.n}^3 headline system ({dtc:.1f} s on {cores} threads), "
+                      f"scaled by {iters_full} iterations per solve ({basis})"}
+
+
+def c1(args):
+    """32^3 Dirichlet Poisson: launch-bound; microseconds per iteration."""
+    from paper_1606_08740_amd import inputs
+    steps = max(args.side_steps * 10, 20)
+    out = {}
+    for label, tol, modes in [("tol_1e-8", 1e-8, [FP64]), ("tol_1e-10", 1e-10, [FP64, MIXED, FP64_FP32HIST])]:
+        w = inputs.workload(1, tol=tol)
+        key = f"dirichlet_poisson_7pt_32_tol{'1e-8' if tol == 1e-8 else '1e-10'}"
+        r = run_modes(w, key, modes, steps, 3)
+        for rec in r.values():
+            rec["us_per_iteration"] = rec["ms_per_solve"] * 1e3 / max(rec["iterations"], 1)
+            rec.pop("effective_GBs", None)
+            rec.pop("effective_frac_of_peak", None)
+        r["oracle_iterations"] = (golden(key) or {}).get("iterations")
+        out[label] = r
+    out["note"] = "working set in L2 / Infinity Cache: launch latency, not HBM, bounds it; reported per iteration"
+    return out
 
 
 def main():
@@ -223,134 +452,84 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
-    import numpy as np
     import torch
-
-    from paper_1606_08740_amd import aar, inputs
+    from paper_1606_08740_amd import inputs
 
     assert torch.cuda.is_available(), "bench needs a GPU"
-    if args.batched_only:
-        print(json.dumps(run_batched(args)))
+    steps, warm = args.side_steps, 1
+    if args.only in ("c2", "c3", "c4"):
+        w = {"c2": lambda: inputs.workload(2), "c3": lambda: inputs.workload(3, precision=FP64),
+             "c4": lambda: inputs.workload(4, precision=FP64)}[args.only]()
+        key = {"c2": "periodic_poisson_r6_192", "c3": "periodic_poisson_r6_256",
+               "c4": "convection_diffusion_upwind_128"}[args.only]
+        modes = [args.precision] if args.precision is not None else [FP64, MIXED, FP64_FP32HIST]
+        print(json.dumps(run_modes(w, key, modes, args.steps, args.warmup, n=w.problems[0].n[0])))
         return
-    w = inputs.workload(2, n=args.n)
-    prob, b = w.problems[0], w.b[0]
-    N = prob.size
-    bt = torch.as_tensor(b, device="cuda:0")
-    if args.precision_only:
-        pm = w.params
-        pm.precision = {"mixed_fp32": aar.AAR_MIXED_FP32, "fp64_fp32hist": aar.AAR_FP64_FP32HIST}[args.precision_only]
-        sm = aar.Solver([prob], pm)
-        dtm, rm, _ = timed_solves(sm, bt, args.steps, args.warmup)
-        sm.close()
-        print(json.dumps({"precision": args.precision_only, "value": args.steps / dtm, "unit": "solves/s",
-                          "ms_per_step": dtm / args.steps * 1e3, "iterations": rm["iterations"],
-                          "outer_steps": rm["outer_steps"], "rel_residual": rm["rel_residual"],
-                          "status": rm["status"]}))
+    if args.only == "c1":
+        print(json.dumps(c1(args)))
+        return
+    if args.only == "c5":
+        modes = None
+        if args.precision is not None:
+            from paper_1606_08740_amd import aar
+            modes = [(MODE_NAMES[args.precision], args.precision, aar.AAR_FLAG_DEFLATE_CONSTANT)]
+        print(json.dumps(run_batched(args, modes)))
         return
 
-    # ---- FP64 (headline) ----
-    prm = w.params
-    prm.precision = aar.AAR_FP64
-    s64 = aar.Solver([prob], prm)
-    dt64, r64, x64 = timed_solves(s64, bt, args.steps, args.warmup)
-    # kernel timing pass: one HIP event pair around each cycle's p - 1 consecutive
-    # sweep launches, on the solver's stream
-    s64.set_timing(True)
-    for _ in range(args.kernel_timing_solves):
-        xt = torch.zeros_like(bt)
-        s64.solve(bt, xt)
-    ms_tot, launches = s64.sweep_time()
-    s64.set_timing(False)
-    s64.close()
-    sweep_us = ms_tot / max(launches, 1) * 1e3
-    # algorithmic bytes of the p - 1 Richardson sweeps of a cycle, per launch.
-    # With the paired layout (and m + 1 >= p) the first sweep of a cycle reads
-    # x and b and writes f (24 B per point); the others follow the residual
-    # recursion f_{j+1} = f_j - omega D^-1 A f_j: read f_j, write f_{j+1}
-    # (16 B).  Otherwise every sweep reads x, b and writes x, f (32 B).
-    tile = fp64_tile(args.n)
-    recursion = tile is not None and tile["pair"] > 0 and prm.m + 1 >= prm.p >= 2
-    p = prm.p
-    sweep_bytes = (3 * 8 + (p - 2) * 2 * 8) * N / (p - 1) if recursion else 4 * 8 * N
-    achieved = sweep_bytes / (sweep_us * 1e-6) / 1e9
-
+    h, w = headline(args)
+    r64 = h["r"]
     out = {
         "metric": METRIC,
-        "value": args.steps / dt64,
+        "value": args.steps / h["dt"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt64 / args.steps * 1e3,
+        "ms_per_step": h["dt"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"periodic Poisson {args.n}^3, 12th-order central FD (37-point), "
-                               "64 Gaussian charges minus mean, Jacobi, omega=beta=0.6, m=7, p=6, "
-                               "tol 1e-10, FP64",
-                   "grid": [args.n] * 3, "radius": 6, "m": 7, "p": 6, "tol": 1e-10, "precision": "fp64"},
+        "config": h["config"],
         "iterations": r64["iterations"],
         "rel_residual": r64["rel_residual"],
         "status": r64["status"],
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic(args.n),
-                     "kernel": ("k_stencil2 Richardson sweeps, paired-point layout, FP64, radius 6: " +
-                                ("a cycle's first from x and b, the others by the residual recursion"
-                                 if recursion else "each from x and b")),
-                     "bytes_per_launch": sweep_bytes, "mean_launch_us": sweep_us, "launches": launches},
+        "roofline": h["roofline"],
+        "solve": h["solve"],
     }
-    xa = x64.cpu().numpy()
-    out["error_vs_oracle"] = {
-        "fp64": oracle_sample_error(xa, args.n),
-        "measure": "max abs error at 64 seeded sample points over the RMS of the oracle's FP64 solution "
-                   "(mean-free), stored in tests/golden/oracle_full_size.json by tests/golden/make_golden.py"}
-    copy_gbs = measured_copy_gbs()
-    out["roofline"]["measured_copy_GBs"] = copy_gbs
-    out["roofline"]["frac_of_measured_copy"] = achieved / copy_gbs
+    if args.only == "headline":
+        print(json.dumps(out))
+        return
+    out["roofline"]["measured_copy_GBs"] = copy_gbs = measured_copy_gbs()
+    out["roofline"]["frac_of_measured_copy"] = out["roofline"]["achieved"] / copy_gbs
 
-    # ---- other precisions on the same system ----
-    if not args.no_mixed:
-        xa -= xa.mean()
-        for label, prec in [("mixed_fp32", aar.AAR_MIXED_FP32), ("fp64_fp32hist", aar.AAR_FP64_FP32HIST)]:
-            pm = inputs.Params(**{**prm.__dict__})
-            pm.precision = prec
-            sm = aar.Solver([prob], pm)
-            dtm, rm, xm = timed_solves(sm, bt, args.steps, args.warmup)
-            sm.close()
-            xb = xm.cpu().numpy()
-            err = oracle_sample_error(xb, args.n)
-            xb -= xb.mean()
-            out[label] = {"value": args.steps / dtm, "unit": "solves/s", "ms_per_step": dtm / args.steps * 1e3,
-                          "iterations": rm["iterations"], "outer_steps": rm["outer_steps"],
-                          "rel_residual": rm["rel_residual"], "status": rm["status"],
-                          "speedup_vs_fp64": dt64 / dtm, "error_vs_oracle": err,
-                          "rel_diff_vs_fp64_gpu": float(np.linalg.norm(xa - xb) / np.linalg.norm(xa))}
-
-    # ---- batched: 512 shifted periodic Helmholtz systems, one call ----
-    if not args.no_batched:
-        out["batched"] = run_batched(args)
+    # ---- the headline grid in the other modes ----
+    c3 = run_modes(w, f"periodic_poisson_r6_{args.n}", [MIXED, MIXED_BF16, FP64_FP32HIST], steps, warm, n=args.n)
+    t64 = h["dt"] / args.steps
+    for rec in c3.values():
+        rec["speedup_vs_fp64"] = t64 / (rec["ms_per_solve"] * 1e-3)
+    c3["fp64"] = {"value": 1.0 / t64, "unit": "solves/s", "ms_per_solve": t64 * 1e3,
+                  "iterations": r64["iterations"], "error_vs_oracle": h["solve"]["error_vs_oracle"],
+                  "effective_GBs": h["solve"]["effective_GBs"], "speedup_vs_fp64": 1.0}
+    out[f"c3_{args.n}"] = c3
+    del w
+    # ---- the other evaluation workloads ----
+    if args.n != 192:
+        w2 = inputs.workload(2)
+        out["c2_192"] = run_modes(w2, "periodic_poisson_r6_192", [FP64, MIXED, FP64_FP32HIST], steps, warm, n=192)
+        del w2
+    w4 = inputs.workload(4, precision=FP64)
+    out["c4_128"] = run_modes(w4, "convection_diffusion_upwind_128", [FP64, MIXED, FP64_FP32HIST], steps, warm,
+                              n=128)
+    del w4
+    out["c1_32"] = c1(args)
+    out["batched"] = run_batched(args)
 
     # ---- CPU oracle baseline (bounded sample) ----
     if not args.no_cpu_baseline:
-        import oracle
-        k = args.cpu_sample_iters
-        t0 = time.perf_counter()
-        oracle.aar_solve(prob, b, m=prm.m, p=prm.p, tol=1e-30, max_iter=k)
-        dtc = time.perf_counter() - t0
-        iters_full = None
-        if os.path.exists(GOLDEN):
-            g = json.load(open(GOLDEN))
-            key = f"periodic_poisson_r6_{args.n}"
-            if key in g:
-                iters_full = g[key]["iterations"]
-        basis = "oracle iterations to 1e-10 (tests/golden)" if iters_full else "GPU iteration count"
-        iters_full = iters_full or r64["iterations"]
-        out["cpu_baseline"] = {"value": 1.0 / (dtc / k * iters_full), "unit": "solves/s",
-                               "cores": oracle.threads(), "kind": "oracle",
-                               "sample": f"{k} AAR iterations of the same {args.n}^3 system ({dtc:.1f} s), "
-                                         f"scaled by {iters_full} iterations per solve ({basis})"}
+        wc = inputs.workload(3, n=args.n, precision=FP64) if args.n != 192 else inputs.workload(2)
+        out["cpu_baseline"] = cpu_baseline(args, wc)
     print(json.dumps(out))
 
 

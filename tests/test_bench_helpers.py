@@ -48,3 +48,18 @@ def test_oracle_sample_error():
     x[idx[3]] += 1e-3 * rms
     assert bench.oracle_sample_error(x, 192) == pytest.approx(1e-3, rel=1e-2)
     assert bench.oracle_sample_error(x, 100) is None
+
+
+def test_byte_models():
+    """Per-point byte counts of the design's passes (m = 7, p = 6, FP64):
+    sweeps 24 + 4 x 16, residual + fused Gram 64, update 96 = 248 B per cycle;
+    with the separate Gram pass 16 + 64 for the residual and the products."""
+    assert bench.sweep_bytes_per_point(7, 6) == pytest.approx(17.6)
+    assert bench.sweep_bytes_per_point(3, 6) == 32.0        # ring shorter than a cycle: direct sweeps
+    assert bench.cycle_bytes(bench.FP64, 7, 6, fused_gram=True) == 248
+    assert bench.cycle_bytes(bench.FP64, 7, 6) == 264
+    # FP64 iterate with an FP32 ring: first sweep 8 + 8 + 4, then 4 x 8 over
+    # the ring and the residual 8, Gram 8 x 4, update 8 + 32 + 4 + 8 + 4
+    assert bench.cycle_bytes(bench.FP64_FP32HIST, 7, 6) == 20 + 4 * 8 + 8 + 32 + 56
+    assert bench.cycle_bytes(bench.MIXED, 7, 6) == 12 + 4 * 8 + 8 + 32 + 4 + 32 + 4 + 4 + 4
+    assert bench.cycle_bytes(bench.FP64_BF16HIST, 7, 6) is None
