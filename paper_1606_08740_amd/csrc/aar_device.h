@@ -423,11 +423,14 @@ __device__ inline int xcd_tile(int b, int nb)
 constexpr int kOrderAltZ = 1;
 constexpr int kOrderZFast = 2;
 
+constexpr int kTbMaxDepth = 5;   // deepest temporal block of recursion steps
+
 struct TileShape {
     int ry;      // y rows per thread (tile height = kWY * ry; 2 kWY * ry paired)
     int cz;      // z planes per workgroup
     int order = 0;   // kOrder* bits
     int pair = 0;    // paired layout for the sweep and residual passes: 1, 2, 3 = 4, 8, 16 waves
+    int tb = 0;      // temporal block depth of the recursion steps (0, 1: one pass per step)
 };
 
 // The paired layout (each thread owns two x-adjacent points, loaded and
@@ -474,6 +477,16 @@ hipError_t launch_stencil_batched_f64_narrow(int mode, Prec hist, int radius, bo
                                              const BatchStencilArgs<double> &a, int grid, hipStream_t s);
 hipError_t launch_stencil_batched_f32(int mode, Prec hist, int radius, bool conv, int ry,
                                       const BatchStencilArgs<float> &a, int grid, hipStream_t s);
+
+// Temporal block of nt recursion steps at cycle positions j0 .. j0+nt-1
+// (j0 >= 1; one-point tiles, radius <= 2, ring of the iterate's type); the
+// last stage is the Anderson-step residual with its norm partial when
+// last_fk.  tblock_fits: whether that block's LDS rings fit a workgroup.
+bool tblock_fits(int radius, bool conv, const TileShape &ts, int nt, bool f64);
+hipError_t launch_tblock_f64(int radius, bool conv, const TileShape &ts, StencilArgs<double> a, int j0, int nt,
+                             bool last_fk, hipStream_t s);
+hipError_t launch_tblock_f32(int radius, bool conv, const TileShape &ts, StencilArgs<float> a, int j0, int nt,
+                             bool last_fk, hipStream_t s);
 
 hipError_t launch_gram(Prec prec, const GramArgs &a, int blocks, hipStream_t s);
 hipError_t launch_lsq(const LsqArgs &a, hipStream_t s);

@@ -228,6 +228,7 @@ struct aar_solver_t {
     bool timing = false;
     std::vector<hipEvent_t> tev;
     std::vector<int64_t> tcycle;
+    std::vector<int> tcount;        // positions each timed group covers
     size_t tused = 0;
     double t_total_ms = 0.0;
     int64_t t_launches = 0;
@@ -475,6 +476,24 @@ template <> struct Launch<float> {
     }
 };
 
+template <typename T> hipError_t launch_tblock(const Path<T> &P, const StencilArgs<T> &a, int j0, int nt, bool last_fk,
+                                               hipStream_t s, const TileShape &ts)
+{
+    if constexpr (std::is_same<T, double>::value)
+        return launch_tblock_f64(P.radius, P.conv, ts, a, j0, nt, last_fk, s);
+    else
+        return launch_tblock_f32(P.radius, P.conv, ts, a, j0, nt, last_fk, s);
+}
+
+// Whether a cycle's positions 1 .. p-1 run as temporal blocks for this path:
+// the residual recursion with a ring of the iterate's type, a one-point tile
+// with a block depth of 2 or more, radius <= 2, and blocks whose LDS fits.
+template <typename T> bool tblock_active(const Path<T> &P, int p, const TileShape &ts)
+{
+    return P.recur && !P.recur32 && p >= 2 && ts.tb >= 2 && ts.pair == 0 &&
+           tblock_fits(P.radius, P.conv, ts, std::min(ts.tb, p - 1), std::is_same<T, double>::value);
+}
+
 // Arguments of an FP32 recursion pass over an FP32 ring (Path::recur32).
 // The recursion reads neither x nor b; both point at the ring so that every
 // pointer the kernel holds is a valid FP32 vector.
@@ -514,7 +533,11 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
     a.omega = (T)pa.omega;
     hipError_t e;
     const bool rec = P.recur || P.recur32;
-    for (int j = 0; j < pa.p - 1; ++j) {
+    // temporal blocks: the first sweep alone, then blocks over positions
+    // 1 .. p-1 (the last one ending with the Anderson-step residual)
+    const bool tb = tblock_active(P, pa.p, P.ts);
+    const int jend = tb ? 1 : pa.p - 1;
+    for (int j = 0; j < jend; ++j) {
         a.j = j;
         if (rec) {
             // x stays the cycle's first iterate; the first sweep reads it and
@@ -545,14 +568,37 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
             e = Launch<T>::stencil(kSweep, P, a, s);
         if (e != hipSuccess)
             return e;
-        if (S->timing && j == pa.p - 2) {
+        if (S->timing && !tb && j == pa.p - 2) {
             if ((e = hipEventRecord(S->tev[S->tused + 1], s)) != hipSuccess)
                 return e;
             S->tcycle.push_back(cycle_tag * pa.p + j);   // the group's last sweep
+            S->tcount.push_back(pa.p - 1);
             S->tused += 2;
         }
     }
     const int jk = pa.p - 1;
+    if (tb) {
+        a.recur = 1;
+        a.x = P.xa;
+        a.out = nullptr;
+        a.partial = S->part_rho;
+        a.gram_partial = nullptr;
+        for (int j = 1; j <= jk;) {
+            const int nt = std::min(P.ts.tb, pa.p - j);
+            if ((e = launch_tblock<T>(P, a, j, nt, j + nt - 1 == jk, s, P.ts)) != hipSuccess)
+                return e;
+            j += nt;
+        }
+        if (S->timing) {
+            // the timed group covers every position of the cycle (the blocks
+            // include the Anderson-step residual)
+            if ((e = hipEventRecord(S->tev[S->tused + 1], s)) != hipSuccess)
+                return e;
+            S->tcycle.push_back(cycle_tag * pa.p + jk);
+            S->tcount.push_back(pa.p);
+            S->tused += 2;
+        }
+    }
     T *xk = rec ? P.xa : (jk & 1) ? P.xb : P.xa;
     a.j = jk;
     a.x = xk;
@@ -561,7 +607,9 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
     a.fcur = P.fcur;
     a.partial = S->part_rho;
     a.gram_partial = P.gram_fused ? S->part_gram : nullptr;
-    if (P.recur32) {   // jk >= 1: p >= 2
+    if (tb) {
+        e = hipSuccess;   // the last block formed the Anderson-step residual
+    } else if (P.recur32) {   // jk >= 1: p >= 2
         StencilArgs<float> a32 = ring_args32(S, P, jk);
         a32.partial = S->part_rho;
         e = launch_stencil_f32(kFk, Prec::F32, P.radius, P.conv, P.ts32, a32, nullptr, s);
@@ -721,9 +769,10 @@ aar_status run_cycles(aar_solver_t *S, const Path<T> &P, int64_t max_iter, bool 
             float ms = 0.0f;
             AAR_HIP(hipEventElapsedTime(&ms, S->tev[2 * t], S->tev[2 * t + 1]));
             S->t_total_ms += ms;
-            S->t_launches += S->params.p - 1;
+            S->t_launches += S->tcount[t];
         }
         S->tcycle.clear();
+        S->tcount.clear();
         S->tused = 0;
     }
     return AAR_OK;
@@ -837,17 +886,19 @@ void load_tune_file()
         if (line.empty() || line[0] == '#')
             continue;
         std::istringstream in(line);
-        int prec, radius, conv, n0, n1, n2, ry, cz, order = 0, pair = 0;
+        int prec, radius, conv, n0, n1, n2, ry, cz, order = 0, pair = 0, tb = 0;
         if (!(in >> prec >> radius >> conv >> n0 >> n1 >> n2 >> ry >> cz))
             continue;
         if (!(in >> order))
             order = 0;
         if (!(in >> pair))
             pair = 0;
-        if ((ry != 1 && ry != 2 && ry != 4) || cz < 1 || order < 0 || order > 3 ||
-            !paired_shape_ok(TileShape{ry, cz, order, pair}, prec == 0))
+        if (!(in >> tb))
+            tb = 0;
+        if ((ry != 1 && ry != 2 && ry != 4) || cz < 1 || order < 0 || order > 3 || tb < 0 ||
+            tb > kTbMaxDepth || (tb >= 2 && pair != 0) || !paired_shape_ok(TileShape{ry, cz, order, pair}, prec == 0))
             continue;
-        g_tune_cache[std::make_tuple(prec, radius, conv, n0, n1, n2)] = TileShape{ry, cz, order, pair};
+        g_tune_cache[std::make_tuple(prec, radius, conv, n0, n1, n2)] = TileShape{ry, cz, order, pair, tb};
     }
 }
 
@@ -859,7 +910,7 @@ void append_tune_file(const std::tuple<int, int, int, int, int, int> &key, const
     std::ofstream f(path, std::ios::app);
     f << std::get<0>(key) << ' ' << std::get<1>(key) << ' ' << std::get<2>(key) << ' ' << std::get<3>(key) << ' '
       << std::get<4>(key) << ' ' << std::get<5>(key) << ' ' << ts.ry << ' ' << ts.cz << ' ' << ts.order << ' '
-      << ts.pair << '\n';
+      << ts.pair << ' ' << ts.tb << '\n';
 }
 
 // Tile of the FP32 passes from the tile file, without timing candidates
@@ -973,6 +1024,68 @@ template <typename T> aar_status autotune(aar_solver_t *S, int idx)
             best_ms = ms;
             best = ts;
         }
+    }
+    // Temporal block depth (one-point tiles of radius <= 2 with the residual
+    // recursion): time a cycle's positions 1 .. p-1 (its later Richardson
+    // steps and the Anderson-step residual) as one pass per step and as
+    // blocks of 2 .. kTbMaxDepth steps; keep the fastest.
+    P.ts = best;
+    if (result == AAR_OK && best.pair == 0 && P.recur && !P.recur32 && S->params.p >= 3 && op.prob.radius <= 2) {
+        const int p = S->params.p;
+        a.partial = S->part_rho;
+        a.j = 0;
+        a.recur = 0;
+        a.x = P.xa;
+        a.out = nullptr;
+        hipError_t e = Launch<T>::stencil(kSweep, P, a, s, best);   // ring slot 0 <- f_0
+        auto group = [&](int depth) -> hipError_t {
+            hipError_t ge = hipSuccess;
+            StencilArgs<T> g = a;
+            g.recur = 1;
+            if (depth < 2) {
+                for (int j = 1; j < p && ge == hipSuccess; ++j) {
+                    g.j = j;
+                    ge = Launch<T>::stencil(j < p - 1 ? kSweep : kFk, P, g, s, best);
+                }
+                return ge;
+            }
+            TileShape ts = best;
+            ts.tb = depth;
+            for (int j = 1; j < p && ge == hipSuccess;) {
+                const int nt = std::min(depth, p - j);
+                ge = launch_tblock<T>(P, g, j, nt, j + nt - 1 == p - 1, s, ts);
+                j += nt;
+            }
+            return ge;
+        };
+        float best_group = 1e30f;
+        for (int depth = 0; depth <= kTbMaxDepth && e == hipSuccess; ++depth) {
+            if (depth == 1)
+                continue;
+            TileShape ts = best;
+            ts.tb = depth;
+            if (depth >= 2 && !tblock_fits(op.prob.radius, op.prob.velocity != nullptr, ts, std::min(depth, p - 1), f64))
+                continue;
+            for (int w = 0; w < 2 && e == hipSuccess; ++w)
+                e = group(depth);
+            if (e == hipSuccess)
+                e = hipEventRecord(e0, s);
+            for (int w = 0; w < 5 && e == hipSuccess; ++w)
+                e = group(depth);
+            if (e == hipSuccess)
+                e = hipEventRecord(e1, s);
+            if (e == hipSuccess)
+                e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && ms < best_group) {
+                best_group = ms;
+                best.tb = depth;
+            }
+        }
+        if (e != hipSuccess)
+            result = fail(AAR_ERR_DEVICE, std::string("autotune (temporal blocks): ") + hipGetErrorString(e));
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -2284,6 +2397,7 @@ aar_status aar_set_timing(aar_solver s, int32_t enable)
     s->t_total_ms = 0.0;
     s->t_launches = 0;
     s->tcycle.clear();
+    s->tcount.clear();
     s->tused = 0;
     return AAR_OK;
 }

@@ -115,3 +115,15 @@ int main(void) {
             assert int(got[f"{cname}.{fname}"]) == getattr(cls, fname).offset, (cname, fname)
     order = [f for f, _ in aar.aar_result._fields_]
     assert order == ["status", "iterations", "outer_steps", "rel_residual"]
+
+
+def test_tile_file_block_depth_field(tmp_path, monkeypatch):
+    """A tile line with a temporal block depth (11th field) is accepted for
+    one-point tiles; depth with a paired tile or beyond 5 is ignored (the
+    library then falls back to its default shape without error)."""
+    prob = inputs.dirichlet_poisson_problem(12)
+    f = tmp_path / "t.txt"
+    f.write_text("0 1 0 12 12 12 2 4 0 0 3\n0 1 0 13 13 13 1 4 0 1 3\n0 1 0 14 14 14 2 4 0 0 9\n")
+    monkeypatch.setenv("AAR_TUNE_CACHE", str(f))
+    for n in (12, 13, 14):
+        assert _ws(inputs.dirichlet_poisson_problem(n), inputs.Params()) > 0
