@@ -176,11 +176,14 @@ __global__ __launch_bounds__(kThreads) void k_tblock(const StencilArgs<T> a, int
             // stage's plane zc is tau = t - s R (>= (s - 1) R + R here)
             const int tin = t - s * R;
             T *fout = reinterpret_cast<T *>(a.fring) + (int64_t)(ks % a.nslots) * a.slot_stride;
+            const int gs = (NT - s) * R;
+            // the whole region inside the grid: no boundary rule to apply
+            const bool inside = x0 - gs >= 0 && x0 + kTX + gs <= st.n0 && y0 - gs >= 0 && y0 + TY + gs <= st.n1;
             const int nout = W[s] * H[s];
             for (int c = tid; c < nout; c += kThreads) {
                 const int ex = c % W[s], ey = c / W[s];
-                const int gx = x0 - (NT - s) * R + ex, gy = y0 - (NT - s) * R + ey;
-                const int io = inplane(gx, gy);
+                const int gx = x0 - gs + ex, gy = y0 - gs + ey;
+                const int io = inside ? gx + st.n0 * gy : inplane(gx, gy);
                 T f = T(0);
                 if (io >= 0 && zg >= 0) {
                     const int lx = ex + R, ly = ey + R;      // position in region s - 1
