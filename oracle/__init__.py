@@ -87,6 +87,12 @@ def _load_from(path: str):
     lib.oracle_threads.restype = ctypes.c_int
     lib.oracle_deflate_constant.argtypes = [pp, dp, dp]
     lib.oracle_deflate_constant.restype = ctypes.c_int
+    lib.oracle_apply_complex.argtypes = [pp, ctypes.c_double, dp, dp]
+    lib.oracle_aar_solve_complex.argtypes = [pp, ctypes.c_double, dp, dp, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_double, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), dp,
+                                             dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.oracle_aar_solve_complex.restype = ctypes.c_int
     _lib = lib
 
 
@@ -199,6 +205,52 @@ def deflate_constant(prob, b, x0=None) -> np.ndarray:
     if _load().oracle_deflate_constant(bd.ref, _ptr(_f64(b)), _ptr(x)) != OK:
         raise ValueError("the constant-mode step needs every axis periodic and shift > 0")
     return x
+
+
+def _c128(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def apply_complex(prob, shift_im, x) -> np.ndarray:
+    """y = A x for the complex operator A = A_r + i shift_im I (A_r: the real
+    operator of `prob`, its real shift included): Eq. 1 over C, the form of
+    the periodic Helmholtz problem of Sec. 3.2 (Eq. 7)."""
+    bd = _Bound(prob)
+    xc = _c128(x)
+    y = np.empty(bd.size, dtype=np.complex128)
+    _load().oracle_apply_complex(bd.ref, float(shift_im), _ptr(xc.view(np.float64)), _ptr(y.view(np.float64)))
+    return y
+
+
+def aar_solve_complex(prob, b, shift_im, x0=None, omega=0.6, beta=0.6, m=7, p=6, tol=1e-10,
+                      max_iter=1_000_000, trace_cap: int = 0) -> dict:
+    """Complex AAR (Eqs. 2-6 over C, T the conjugate transpose) with the
+    complex Jacobi preconditioner D = diag(A); omega and beta may be complex.
+    Returns x (complex), status, iterations, relres and, with trace_cap > 0,
+    trace rows [k, r_k, ||f_k||, ||f_k - F_k gamma_k||, rank, cond]."""
+    bd = _Bound(prob)
+    bc = _c128(b)
+    x = np.zeros(bd.size, dtype=np.complex128) if x0 is None else _c128(x0).copy()
+    omega, beta = complex(omega), complex(beta)
+    it = ctypes.c_int64(0)
+    rr = ctypes.c_double(0.0)
+    tl = ctypes.c_int64(0)
+    tr = np.zeros((max(trace_cap, 1), 6))
+    st = _load().oracle_aar_solve_complex(bd.ref, float(shift_im), _ptr(bc.view(np.float64)),
+                                          _ptr(x.view(np.float64)), omega.real, omega.imag, beta.real, beta.imag,
+                                          int(m), int(p), float(tol), int(max_iter), ctypes.byref(it),
+                                          ctypes.byref(rr), _ptr(tr) if trace_cap > 0 else None, int(trace_cap),
+                                          ctypes.byref(tl))
+    out = {"x": x, "status": st, "iterations": it.value, "relres": rr.value}
+    if trace_cap > 0:
+        out["trace"] = tr[: tl.value].copy()
+    return out
+
+
+def relative_residual_complex(prob, shift_im, b, x) -> float:
+    """||b - A x|| / ||b|| for the complex operator, from apply_complex."""
+    r = _c128(b) - apply_complex(prob, shift_im, x)
+    return float(np.linalg.norm(r) / np.linalg.norm(_c128(b)))
 
 
 def relative_residual(prob, b, x) -> float:

@@ -564,3 +564,246 @@ int oracle_threads(void)
     return 1;
 #endif
 }
+
+/* ====================================================================== */
+/* Complex-valued systems                                                  */
+/* ====================================================================== */
+/*
+ * The method is stated for A, x, b complex (Sec. 2, Eq. 1), with complex
+ * relaxation parameters omega, beta and T the conjugate transpose (Eq. 3);
+ * the paper's periodic Helmholtz problem (Sec. 3.2, Eq. 7) has a complex
+ * shift Q and a complex right-hand side P rho^alpha.  Here A = A_r + i s I:
+ * the real finite-difference operator of P (with its real shift) plus an
+ * imaginary shift s.  Complex vectors are stored interleaved (re, im) per
+ * grid point.  Plain C99 complex arithmetic; the steps are those of
+ * oracle_aar_solve in the same order.
+ */
+#include <complex.h>
+
+typedef double complex cplx;
+
+/* y = A x = A_r x + i s x. */
+void oracle_apply_complex(const oracle_problem *P, double shift_im, const double *x, double *y)
+{
+    const int64_t N = problem_size(P);
+    double *xr = malloc(sizeof(double) * N), *xi = malloc(sizeof(double) * N);
+    double *yr = malloc(sizeof(double) * N), *yi = malloc(sizeof(double) * N);
+    for (int64_t i = 0; i < N; ++i) {
+        xr[i] = x[2 * i];
+        xi[i] = x[2 * i + 1];
+    }
+    oracle_apply(P, xr, yr);
+    oracle_apply(P, xi, yi);
+    for (int64_t i = 0; i < N; ++i) {
+        y[2 * i] = yr[i] - shift_im * xi[i];
+        y[2 * i + 1] = yi[i] + shift_im * xr[i];
+    }
+    free(xr);
+    free(xi);
+    free(yr);
+    free(yi);
+}
+
+/* sum_i conj(a_i) b_i */
+static cplx cdot(int64_t N, const cplx *a, const cplx *b)
+{
+    cplx s = 0.0;
+    for (int64_t i = 0; i < N; ++i)
+        s += conj(a[i]) * b[i];
+    return s;
+}
+
+/* gamma = pinv(G) c for a Hermitian positive semidefinite l x l matrix G,
+ * through its real form [[Re G, -Im G], [Im G, Re G]] (symmetric, the same
+ * eigenvalues each twice): eigenvalues <= l lambda_max 2^-52 are dropped,
+ * with l the complex order.  Returns the complex rank; *cond the condition
+ * number over the kept eigenvalues. */
+static int pinv_solve_hermitian(int l, const cplx *G, const cplx *c, cplx *gamma, double *cond)
+{
+    *cond = 1.0;
+    if (l <= 0)
+        return 0;
+    const int L = 2 * l;
+    double *S = malloc(sizeof(double) * L * L), *V = malloc(sizeof(double) * L * L), *cc = malloc(sizeof(double) * L);
+    for (int a = 0; a < l; ++a) {
+        for (int b = 0; b < l; ++b) {
+            const double gr = creal(G[a * l + b]), gi = cimag(G[a * l + b]);
+            S[a * L + b] = gr;
+            S[a * L + (b + l)] = -gi;
+            S[(a + l) * L + b] = gi;
+            S[(a + l) * L + (b + l)] = gr;
+        }
+        cc[a] = creal(c[a]);
+        cc[a + l] = cimag(c[a]);
+    }
+    oracle_jacobi_eigen(L, S, V);
+    double lmax = 0.0;
+    for (int i = 0; i < L; ++i)
+        if (S[i * L + i] > lmax)
+            lmax = S[i * L + i];
+    const double thresh = l * lmax * ldexp(1.0, -52);
+    double *g = calloc(L, sizeof(double));
+    int kept = 0;
+    double lmin = lmax;
+    for (int e = 0; e < L; ++e) {
+        const double lam = S[e * L + e];
+        if (!(lam > thresh))
+            continue;
+        ++kept;
+        if (lam < lmin)
+            lmin = lam;
+        double proj = 0.0;
+        for (int i = 0; i < L; ++i)
+            proj += V[i * L + e] * cc[i];
+        for (int i = 0; i < L; ++i)
+            g[i] += V[i * L + e] * proj / lam;
+    }
+    for (int a = 0; a < l; ++a)
+        gamma[a] = g[a] + I * g[a + l];
+    if (kept > 0)
+        *cond = lmax / lmin;
+    free(S);
+    free(V);
+    free(cc);
+    free(g);
+    return kept / 2;
+}
+
+/*
+ * Complex AAR with M = diag(A) (complex): the steps of oracle_aar_solve with
+ * complex values.  b, x interleaved complex (length 2N); omega, beta complex
+ * (re, im); trace rows as there (k, r_k, ||f_k||, 0, rank, cond).
+ */
+int oracle_aar_solve_complex(const oracle_problem *P, double shift_im, const double *b_in, double *x_io,
+                             double omega_re, double omega_im, double beta_re, double beta_im, int m, int p,
+                             double tol, int64_t max_iter, int64_t *iters_out, double *relres_out, double *trace,
+                             int64_t trace_cap, int64_t *trace_len)
+{
+    const int64_t N = problem_size(P);
+    if (N <= 0 || m < 1 || p < 1 || !(tol > 0.0) || max_iter < 1)
+        return ORACLE_BAD_ARG;
+    if (trace_len)
+        *trace_len = 0;
+    *iters_out = 0;
+    *relres_out = 0.0;
+    const cplx omega = omega_re + I * omega_im, beta = beta_re + I * beta_im;
+    const cplx *b = (const cplx *)b_in;
+    cplx *x = (cplx *)x_io;
+    const double nb = sqrt(creal(cdot(N, b, b)));
+    if (nb == 0.0) {
+        for (int64_t i = 0; i < N; ++i)
+            x[i] = 0.0;
+        return ORACLE_OK;
+    }
+    double *Dr = malloc(sizeof(double) * N);
+    oracle_diagonal(P, Dr);
+    cplx *D = malloc(sizeof(cplx) * N), *res = malloc(sizeof(cplx) * N), *f = malloc(sizeof(cplx) * N);
+    cplx *x_prev = malloc(sizeof(cplx) * N), *f_prev = malloc(sizeof(cplx) * N);
+    cplx *DX = malloc(sizeof(cplx) * N * m), *DF = malloc(sizeof(cplx) * N * m);
+    cplx *G = malloc(sizeof(cplx) * m * m), *c = malloc(sizeof(cplx) * m), *gamma = malloc(sizeof(cplx) * m);
+    int *order = malloc(sizeof(int) * m);
+    for (int64_t i = 0; i < N; ++i)
+        D[i] = Dr[i] + I * shift_im;
+    int cols = 0, status = ORACLE_NOT_CONVERGED;
+    double r = 0.0;
+    for (int64_t k = 0;; ++k) {
+        /* f_k = D^{-1}(b - A x_k)  (Eq. 6) */
+        oracle_apply_complex(P, shift_im, (const double *)x, (double *)res);
+        for (int64_t i = 0; i < N; ++i) {
+            res[i] = b[i] - res[i];
+            f[i] = res[i] / D[i];
+        }
+        /* history push (Eqs. 4-5) */
+        if (k >= 1) {
+            int slot;
+            if (cols < m) {
+                slot = cols;
+                order[cols++] = slot;
+            } else {
+                slot = order[0];
+                for (int t = 0; t < m - 1; ++t)
+                    order[t] = order[t + 1];
+                order[m - 1] = slot;
+            }
+            for (int64_t i = 0; i < N; ++i) {
+                DX[(int64_t)slot * N + i] = x[i] - x_prev[i];
+                DF[(int64_t)slot * N + i] = f[i] - f_prev[i];
+            }
+        }
+        memcpy(x_prev, x, sizeof(cplx) * N);
+        memcpy(f_prev, f, sizeof(cplx) * N);
+        if ((k + 1) % p == 0) {
+            r = sqrt(creal(cdot(N, res, res))) / nb;
+            int64_t row = -1;
+            if (trace && trace_len && *trace_len < trace_cap) {
+                row = (*trace_len)++;
+                trace[row * 6 + 0] = (double)k;
+                trace[row * 6 + 1] = r;
+                trace[row * 6 + 2] = sqrt(creal(cdot(N, f, f)));
+                trace[row * 6 + 3] = 0.0;
+                trace[row * 6 + 4] = 0.0;
+                trace[row * 6 + 5] = 1.0;
+            }
+            if (!isfinite(r)) {
+                status = ORACLE_BREAKDOWN;
+                *iters_out = k + 1;
+                break;
+            }
+            if (r < tol) {
+                status = ORACLE_OK;
+                *iters_out = k + 1;
+                break;
+            }
+            /* G = F^H F, c = F^H f_k (T is the conjugate transpose, Eq. 3) */
+            for (int a = 0; a < cols; ++a) {
+                const cplx *fa = DF + (int64_t)order[a] * N;
+                for (int bb = 0; bb < cols; ++bb)
+                    G[a * cols + bb] = cdot(N, fa, DF + (int64_t)order[bb] * N);
+                c[a] = cdot(N, fa, f);
+            }
+            double cond = 1.0;
+            const int rank = pinv_solve_hermitian(cols, G, c, gamma, &cond);
+            /* x_{k+1} = x_k + beta f_k - (X_k + beta F_k) gamma */
+            for (int64_t i = 0; i < N; ++i) {
+                cplx corr = 0.0;
+                for (int a = 0; a < cols; ++a)
+                    corr += (DX[(int64_t)order[a] * N + i] + beta * DF[(int64_t)order[a] * N + i]) * gamma[a];
+                x[i] = x[i] + beta * f[i] - corr;
+            }
+            if (row >= 0) {
+                /* ||f_k - F_k gamma||, the least-squares residual */
+                for (int64_t i = 0; i < N; ++i) {
+                    cplx e = f[i];
+                    for (int a = 0; a < cols; ++a)
+                        e -= DF[(int64_t)order[a] * N + i] * gamma[a];
+                    res[i] = e;
+                }
+                trace[row * 6 + 3] = sqrt(creal(cdot(N, res, res)));
+                trace[row * 6 + 4] = rank;
+                trace[row * 6 + 5] = cond;
+            }
+        } else {
+            /* Richardson step (Eq. 3, first case) */
+            for (int64_t i = 0; i < N; ++i)
+                x[i] = x[i] + omega * f[i];
+        }
+        if (k + 1 >= max_iter) {
+            *iters_out = max_iter;
+            break;
+        }
+    }
+    *relres_out = r;
+    free(Dr);
+    free(D);
+    free(res);
+    free(f);
+    free(x_prev);
+    free(f_prev);
+    free(DX);
+    free(DF);
+    free(G);
+    free(c);
+    free(gamma);
+    free(order);
+    return status;
+}

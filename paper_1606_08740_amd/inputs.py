@@ -256,6 +256,56 @@ def batched_helmholtz(count: int = 512, seed: int = 5, nmin: int = 16, nmax: int
                     Params(omega=0.6, beta=0.6, m=7, p=6, tol=tol, precision=precision, flags=flags))
 
 
+# The periodic Helmholtz problem of orbital-free DFT (Sec. 3.2, Eq. 7):
+# -(1/(4 pi)) Lap V + Q V = P rho^alpha with the paper's complex constants.
+OFDFT_P = complex(0.003277, -0.009081)
+OFDFT_Q = complex(-0.134992, -0.070225)
+OFDFT_ALPHA = 5.0 / 6.0 + 5.0 ** 0.5 / 6.0
+
+
+def ofdft_density(n: int, seed: int, lattice: float = 7.78, cells: int = 1, width: float = 0.9,
+                  displacement: float = 0.15) -> np.ndarray:
+    """Synthetic electron density on a periodic cube of `cells`^3 FCC cells of
+    the given lattice constant (Bohr): one Gaussian per atom (width in Bohr,
+    minimum-image distance), atoms displaced from the FCC sites by up to
+    `displacement` of the lattice constant (uniform, seeded), on a floor of
+    1e-3 so that rho^alpha is smooth; normalised to 3 electrons per atom.
+    Stands in for the aluminium densities of the paper's Helmholtz problem."""
+    basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
+    sites = np.array([(b + np.array([i, j, k])) / cells for i in range(cells) for j in range(cells)
+                      for k in range(cells) for b in basis])
+    u = uniform(seed, 2, sites.size).reshape(sites.shape)
+    sites = (sites + displacement / cells * (2.0 * u - 1.0)) % 1.0
+    L = lattice * cells
+    grid = np.arange(n) / n
+    rho = np.full((n, n, n), 1e-3)
+    for c in sites:
+        prof = []
+        for ax in range(3):
+            d = grid - c[ax]
+            d -= np.round(d)
+            prof.append(np.exp(-(d * L) ** 2 / (2.0 * width ** 2)))
+        rho += prof[2][:, None, None] * prof[1][None, :, None] * prof[0][None, None, :]
+    h = L / n
+    rho *= 3.0 * len(sites) / (rho.sum() * h ** 3)
+    return rho.reshape(-1)
+
+
+def ofdft_helmholtz(n: int = 72, seed: int = 6, cells: int = 1, tol: float = 1e-10):
+    """Complex periodic Helmholtz (Eq. 7): grid n^3 over `cells`^3 aluminium
+    FCC cells (lattice 7.78 Bohr; n = 36 and 72 give the paper's h = 0.216
+    and 0.108 Bohr for one cell), sixth-order central differences (r = 3),
+    diffusion 1/(4 pi), complex shift Q, rhs P rho^alpha.  Returns
+    (problem with the real part of Q as its shift, imaginary part of Q,
+    complex rhs, Params)."""
+    L = 7.78 * cells
+    h = L / n
+    prob = Problem(n=(n, n, n), h=(h, h, h), bc=(BC_PERIODIC,) * 3, radius=3, diffusion=1.0 / (4.0 * np.pi),
+                   shift=OFDFT_Q.real)
+    b = OFDFT_P * ofdft_density(n, seed, cells=cells) ** OFDFT_ALPHA
+    return prob, OFDFT_Q.imag, b.astype(np.complex128), Params(omega=0.6, beta=0.6, m=7, p=6, tol=tol)
+
+
 def workload(index: int, **kw) -> Workload:
     """The five evaluation workloads, 1-based, at full size unless overridden."""
     if index == 1:
