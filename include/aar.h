@@ -174,6 +174,22 @@ typedef struct {
 aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t count,
                       const aar_params *params, void *hip_stream);
 
+/* Create a solver for one complex-valued system A x = b (Sec. 2, Eq. 1 over C;
+ * the periodic Helmholtz problem of Sec. 3.2, Eq. 7, has a complex shift and
+ * right-hand side): A = A_r + i shift_imag I, with A_r the real operator of
+ * `problem` (its real shift included), and the complex relaxation parameters
+ * omega = params->omega + i omega_imag, beta = params->beta + i beta_imag of
+ * Eq. 3.  The Anderson step solves with F^H F (the paper's T is the conjugate
+ * transpose), its Moore-Penrose pseudoinverse computed on the real form
+ * [[Re, -Im], [Im, Re]] of the Hermitian matrix, eigenvalues <=
+ * l lambda_max 2^-52 dropped; D = diag(A) is complex.  Every Richardson step
+ * forms f from x and b.  The handle then takes complex vectors in aar_solve
+ * and aar_apply: b, x, y hold 2N doubles, (re, im) interleaved per grid point.
+ * Supported: precision AAR_FP64, m <= 8, no velocity, no deflation
+ * (AAR_ERR_UNSUPPORTED otherwise); aar_solve_batched is not. */
+aar_status aar_create_complex(aar_solver *out, const aar_problem *problem, const aar_params *params,
+                              double shift_imag, double omega_imag, double beta_imag, void *hip_stream);
+
 /* Solve system 0 (count must be 1) by AAR (Sec. 2, Eqs. 2-6).  x holds x_0
  * on entry and the answer on return (the iterate x_k whose test passed, or
  * the last iterate); b is read only.  r receives the outcome (may be NULL). */

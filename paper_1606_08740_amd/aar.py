@@ -77,6 +77,8 @@ def load_library():
     lib.aar_residual_log.argtypes = [vp, i32, P(ctypes.c_double), i64, P(i64)]
     lib.aar_rank_log.argtypes = [vp, i32, P(i32), i64, P(i64)]
     lib.aar_solve_noalloc.argtypes = [P(aar_problem), P(aar_params), vp, vp, P(aar_result), vp]
+    d = ctypes.c_double
+    lib.aar_create_complex.argtypes = [P(vp), P(aar_problem), P(aar_params), d, d, d, vp]
     lib.aar_workspace_bytes.argtypes = [P(aar_problem), i32, P(aar_params), P(ctypes.c_size_t)]
     lib.aar_destroy.argtypes = [vp]
     lib.aar_last_error.argtypes = []
@@ -84,7 +86,7 @@ def load_library():
     lib.aar_set_timing.argtypes = [vp, i32]
     lib.aar_sweep_time.argtypes = [vp, P(ctypes.c_double), P(i64)]
     for name in ["aar_create", "aar_solve", "aar_solve_batched", "aar_apply", "aar_residual_log",
-                 "aar_rank_log", "aar_solve_noalloc", "aar_workspace_bytes", "aar_destroy", "aar_set_timing",
+                 "aar_rank_log", "aar_solve_noalloc", "aar_create_complex", "aar_workspace_bytes", "aar_destroy", "aar_set_timing",
                  "aar_sweep_time"]:
         getattr(lib, name).restype = st
     _lib = lib
@@ -113,6 +115,15 @@ def aar_create(problems, params, hip_stream: int = 0):
     h = ctypes.c_void_p()
     _check(lib.aar_create(ctypes.byref(h), arr, len(problems), ctypes.byref(params),
                           ctypes.c_void_p(hip_stream)), "aar_create")
+    return h
+
+
+def aar_create_complex(problem, params, shift_imag: float, omega_imag: float = 0.0, beta_imag: float = 0.0,
+                       hip_stream: int = 0):
+    h = ctypes.c_void_p()
+    _check(load_library().aar_create_complex(ctypes.byref(h), ctypes.byref(problem), ctypes.byref(params),
+                                             float(shift_imag), float(omega_imag), float(beta_imag),
+                                             ctypes.c_void_p(hip_stream)), "aar_create_complex")
     return h
 
 
@@ -304,3 +315,61 @@ class Solver:
         if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
                 and t.numel() == n):
             raise ValueError(f"expected a contiguous float64 CUDA tensor of {n} elements")
+
+
+class ComplexSolver:
+    """A solver handle for one complex-valued system (aar_create_complex):
+    A = A_r + i shift_imag I with A_r the real operator of `problem`; omega and
+    beta may be complex.  Vectors are complex128 CUDA tensors (interleaved
+    re, im in memory)."""
+
+    def __init__(self, problem, params, shift_imag, omega=None, beta=None, device=None, stream=None):
+        import torch
+        load_library()
+        self.device = torch.device(device or "cuda:0")
+        self.problem = problem
+        self.params = params
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        omega = complex(params.omega if omega is None else omega)
+        beta = complex(params.beta if beta is None else beta)
+        pm = make_params(params)
+        pm.omega, pm.beta = omega.real, beta.real
+        with torch.cuda.device(self.device):
+            self.handle = aar_create_complex(make_problem(problem), pm, shift_imag, omega.imag, beta.imag,
+                                             self.stream.cuda_stream)
+        self.size = problem.size
+
+    def solve(self, b, x) -> dict:
+        self._check_vec(b)
+        self._check_vec(x)
+        return result_dict(aar_solve(self.handle, b.data_ptr(), x.data_ptr()))
+
+    def apply(self, x):
+        import torch
+        self._check_vec(x)
+        y = torch.empty_like(x)
+        aar_apply(self.handle, 0, x.data_ptr(), y.data_ptr())
+        return y
+
+    def residual_log(self) -> np.ndarray:
+        return aar_residual_log(self.handle, 0)
+
+    def rank_log(self) -> np.ndarray:
+        return aar_rank_log(self.handle, 0)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            aar_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_vec(self, t):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()
+                and t.numel() == self.size):
+            raise ValueError(f"expected a contiguous complex128 CUDA tensor of {self.size} elements")

@@ -57,12 +57,47 @@ struct alignas(64) InstState {
     int32_t dslot[kMaxM];
     double alpha[kMaxSlots];
     double delta[kMaxM];
+    // imaginary parts of the plan's coefficients (complex-valued systems)
+    double alpha_im[kMaxSlots];
+    double delta_im[kMaxM];
 };
 
 // bfloat16 storage: the upper half of an IEEE float, rounded to nearest even.
 struct bf16_t {
     uint16_t bits;
 };
+
+// Complex FP64 value (the complex-valued systems of Eq. 1; the periodic
+// Helmholtz problem of Eq. 7): stored interleaved (re, im), 16 bytes.
+struct zd {
+    double re, im;
+    zd() = default;   // trivial (LDS arrays); zd() value-initializes to 0
+    __host__ __device__ zd(double r) : re(r), im(0.0) {}
+    __host__ __device__ zd(double r, double i) : re(r), im(i) {}
+    __host__ __device__ zd &operator+=(const zd &o)
+    {
+        re += o.re;
+        im += o.im;
+        return *this;
+    }
+};
+__host__ __device__ inline zd operator+(const zd &a, const zd &b) { return zd(a.re + b.re, a.im + b.im); }
+__host__ __device__ inline zd operator-(const zd &a, const zd &b) { return zd(a.re - b.re, a.im - b.im); }
+__host__ __device__ inline zd operator*(const zd &a, const zd &b)
+{
+    return zd(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+__host__ __device__ inline zd operator/(const zd &a, const zd &b)
+{
+    const double d = b.re * b.re + b.im * b.im;
+    return zd((a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d);
+}
+__host__ __device__ inline zd conj(const zd &a) { return zd(a.re, -a.im); }
+
+// |v|^2 in FP64 (the residual norms of the convergence test)
+__host__ __device__ inline double sqnorm(double v) { return v * v; }
+__host__ __device__ inline double sqnorm(float v) { return (double)v * (double)v; }
+__host__ __device__ inline double sqnorm(const zd &v) { return v.re * v.re + v.im * v.im; }
 
 template <typename H> struct Hist;
 // store2: elements i and i + 1 (i even, p 16-byte aligned) in one store.
@@ -82,6 +117,10 @@ template <> struct Hist<float> {
     {
         *reinterpret_cast<float2 *>(p + i) = make_float2((float)v0, (float)v1);
     }
+};
+template <> struct Hist<zd> {
+    __device__ static inline zd load(const zd *p, int64_t i) { return p[i]; }
+    __device__ static inline void store(zd *p, int64_t i, const zd &v) { p[i] = v; }
 };
 template <> struct Hist<bf16_t> {
     __device__ static inline float load(const bf16_t *p, int64_t i)
@@ -519,6 +558,14 @@ hipError_t launch_fill_pattern_f32(float *v, int64_t N, hipStream_t s);
 // constant-mode deflation: mean of r -> scal[2]; x += mean * inv_sigma; r -= mean; partial ||r||^2
 hipError_t launch_deflate(double *x, double *r, int64_t N, double inv_sigma, double *partial, int blocks,
                           double *scal, hipStream_t s);
+
+// Complex-valued systems (complex.hip)
+hipError_t launch_stencil_complex(int mode, int radius, const TileShape &ts, StencilArgs<zd> a, int *blocks_out,
+                                  hipStream_t s);
+hipError_t launch_cgram(const GramArgs &a, int blocks, hipStream_t s);
+hipError_t launch_clsq(const LsqArgs &a, double omega_im, double beta_im, hipStream_t s);
+hipError_t launch_cupdate(const UpdateArgs<zd> &a, int blocks, hipStream_t s);
+hipError_t launch_cnorm_partial(const zd *v, int64_t N, double *partial, int blocks, hipStream_t s);
 
 int stream_blocks(int64_t N);
 int gram_blocks(int64_t N, int m);

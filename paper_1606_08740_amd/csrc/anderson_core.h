@@ -117,6 +117,135 @@ __device__ inline int tri_index(int i, int j, int m)
     return i * m - i * (i - 1) / 2 + (j - i);
 }
 
+// gamma = pinv(S) c for the symmetric l x l matrix held in S (LDS; rows and
+// columns from l on are scratch), run by one wave: parallel cyclic Jacobi
+// rotations with the round-robin ordering, then eigenvalues at or below
+// rcond * thresh_order * lambda_max are dropped (thresh_order is the order
+// the threshold counts: l for a real matrix, the complex order for the real
+// form of a Hermitian one).  Leaves the eigenvalues on the diagonal of S, the
+// eigenvectors in V and the threshold in sh_off; gamma goes to gam.
+__device__ inline void jacobi_pinv(int l, double rcond, double thresh_order, double (*S)[kMaxM + 1],
+                                   double (*V)[kMaxM + 1], const double *cvec, double *wvec, double *gam,
+                                   double *rot_c, double *rot_s, int *pair_p, int *pair_q, double &sh_off,
+                                   int &sh_stop)
+{
+    const int tid = threadIdx.x;
+    // ---- gamma = pinv(S) c by parallel cyclic Jacobi (round-robin pairs) ----
+    const int L = l + (l & 1);   // even order; index l is a dummy when l is odd
+    for (int i = tid; i < kMaxM * kMaxM; i += kLsqThreads) {
+        const int row = i / kMaxM, col = i % kMaxM;
+        if (row < L && col < L) {
+            V[row][col] = row == col ? 1.0 : 0.0;
+            if (row >= l || col >= l)
+                S[row][col] = 0.0;
+        }
+    }
+    __syncthreads();
+    const int half = L / 2;
+    const int M1 = L - 1;
+    // Sweeps stop when one applies no rotation: a pair is rotated only while
+    // |s_pq| > 1e-15 sqrt(|s_pp s_qq|) (negligible against both diagonals).
+    for (int sweep = 0; sweep < 40 && L >= 2; ++sweep) {
+        if (tid == 0)
+            sh_stop = 1;
+        __syncthreads();
+        for (int round = 0; round < M1; ++round) {
+            if (tid < half) {
+                // circle method: index L-1 meets `round`; the others pair
+                // (round + i) mod (L-1) with (round - i) mod (L-1)
+                int p, qq;
+                if (tid == 0) {
+                    p = round;
+                    qq = L - 1;
+                } else {
+                    p = (round + tid) % M1;
+                    qq = (round - tid + M1) % M1;
+                }
+                if (p > qq) {
+                    const int t = p;
+                    p = qq;
+                    qq = t;
+                }
+                double c = 1.0, sn = 0.0;
+                if (qq < l) {
+                    const double apq = S[p][qq];
+                    const double app = S[p][p], aqq = S[qq][qq];
+                    if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
+                        const double theta = (aqq - app) / (2.0 * apq);
+                        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                        c = 1.0 / sqrt(t * t + 1.0);
+                        sn = t * c;
+                        sh_stop = 0;
+                    }
+                }
+                pair_p[tid] = p;
+                pair_q[tid] = qq;
+                rot_c[tid] = c;
+                rot_s[tid] = sn;
+            }
+            __syncthreads();
+            // rows: S <- J^T S
+            for (int it = tid; it < half * L; it += kLsqThreads) {
+                const int pi = it / L, col = it % L;
+                const int p = pair_p[pi], qq = pair_q[pi];
+                const double c = rot_c[pi], sn = rot_s[pi];
+                const double sp = S[p][col], sq = S[qq][col];
+                S[p][col] = c * sp - sn * sq;
+                S[qq][col] = sn * sp + c * sq;
+            }
+            __syncthreads();
+            // columns: S <- S J, V <- V J
+            for (int it = tid; it < half * L; it += kLsqThreads) {
+                const int pi = it / L, row = it % L;
+                const int p = pair_p[pi], qq = pair_q[pi];
+                const double c = rot_c[pi], sn = rot_s[pi];
+                const double sp = S[row][p], sq = S[row][qq];
+                S[row][p] = c * sp - sn * sq;
+                S[row][qq] = sn * sp + c * sq;
+                const double vp = V[row][p], vq = V[row][qq];
+                V[row][p] = c * vp - sn * vq;
+                V[row][qq] = sn * vp + c * vq;
+            }
+            __syncthreads();
+            // the annihilated pairs are zero in exact arithmetic
+            if (tid < half) {
+                const int p = pair_p[tid], qq = pair_q[tid];
+                if (qq < l && rot_s[tid] != 0.0) {
+                    S[p][qq] = 0.0;
+                    S[qq][p] = 0.0;
+                }
+            }
+            __syncthreads();
+        }
+        if (sh_stop)
+            break;
+    }
+    // eigenvalues on the diagonal; drop those <= rcond * l * lambda_max
+    if (tid == 0) {
+        double lmax = 0.0;
+        for (int i = 0; i < l; ++i)
+            lmax = fmax(lmax, S[i][i]);
+        sh_off = rcond * thresh_order * lmax;
+    }
+    __syncthreads();
+    const double thresh = sh_off;
+    for (int e = tid; e < l; e += kLsqThreads) {
+        const double lam = S[e][e];
+        double proj = 0.0;
+        for (int i = 0; i < l; ++i)
+            proj += V[i][e] * cvec[i];
+        wvec[e] = lam > thresh ? proj / lam : 0.0;
+    }
+    __syncthreads();
+    for (int i = tid; i < l; i += kLsqThreads) {
+        double g = 0.0;
+        for (int e = 0; e < l; ++e)
+            g += V[i][e] * wvec[e];
+        gam[i] = g;
+    }
+    __syncthreads();
+}
+
 // The least-squares step of one system: convergence test, gamma and the
 // update plan.  rho2 = ||b - A x_k||^2 and gram_vals (the m(m+1)/2 entries of
 // the upper triangle of F^T F, then F^T f_k) are already summed.  Run by one
@@ -408,122 +537,8 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
         }
     }
 
-    if (!fast) {
-    // ---- gamma = pinv(S) c by parallel cyclic Jacobi (round-robin pairs) ----
-    const int L = l + (l & 1);   // even order; index l is a dummy when l is odd
-    for (int i = tid; i < kMaxM * kMaxM; i += kLsqThreads) {
-        const int row = i / kMaxM, col = i % kMaxM;
-        if (row < L && col < L) {
-            V[row][col] = row == col ? 1.0 : 0.0;
-            if (row >= l || col >= l)
-                S[row][col] = 0.0;
-        }
-    }
-    __syncthreads();
-    const int half = L / 2;
-    const int M1 = L - 1;
-    // Sweeps stop when one applies no rotation: a pair is rotated only while
-    // |s_pq| > 1e-15 sqrt(|s_pp s_qq|) (negligible against both diagonals).
-    for (int sweep = 0; sweep < 40 && L >= 2; ++sweep) {
-        if (tid == 0)
-            sh_stop = 1;
-        __syncthreads();
-        for (int round = 0; round < M1; ++round) {
-            if (tid < half) {
-                // circle method: index L-1 meets `round`; the others pair
-                // (round + i) mod (L-1) with (round - i) mod (L-1)
-                int p, qq;
-                if (tid == 0) {
-                    p = round;
-                    qq = L - 1;
-                } else {
-                    p = (round + tid) % M1;
-                    qq = (round - tid + M1) % M1;
-                }
-                if (p > qq) {
-                    const int t = p;
-                    p = qq;
-                    qq = t;
-                }
-                double c = 1.0, sn = 0.0;
-                if (qq < l) {
-                    const double apq = S[p][qq];
-                    const double app = S[p][p], aqq = S[qq][qq];
-                    if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
-                        const double theta = (aqq - app) / (2.0 * apq);
-                        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                        c = 1.0 / sqrt(t * t + 1.0);
-                        sn = t * c;
-                        sh_stop = 0;
-                    }
-                }
-                pair_p[tid] = p;
-                pair_q[tid] = qq;
-                rot_c[tid] = c;
-                rot_s[tid] = sn;
-            }
-            __syncthreads();
-            // rows: S <- J^T S
-            for (int it = tid; it < half * L; it += kLsqThreads) {
-                const int pi = it / L, col = it % L;
-                const int p = pair_p[pi], qq = pair_q[pi];
-                const double c = rot_c[pi], sn = rot_s[pi];
-                const double sp = S[p][col], sq = S[qq][col];
-                S[p][col] = c * sp - sn * sq;
-                S[qq][col] = sn * sp + c * sq;
-            }
-            __syncthreads();
-            // columns: S <- S J, V <- V J
-            for (int it = tid; it < half * L; it += kLsqThreads) {
-                const int pi = it / L, row = it % L;
-                const int p = pair_p[pi], qq = pair_q[pi];
-                const double c = rot_c[pi], sn = rot_s[pi];
-                const double sp = S[row][p], sq = S[row][qq];
-                S[row][p] = c * sp - sn * sq;
-                S[row][qq] = sn * sp + c * sq;
-                const double vp = V[row][p], vq = V[row][qq];
-                V[row][p] = c * vp - sn * vq;
-                V[row][qq] = sn * vp + c * vq;
-            }
-            __syncthreads();
-            // the annihilated pairs are zero in exact arithmetic
-            if (tid < half) {
-                const int p = pair_p[tid], qq = pair_q[tid];
-                if (qq < l && rot_s[tid] != 0.0) {
-                    S[p][qq] = 0.0;
-                    S[qq][p] = 0.0;
-                }
-            }
-            __syncthreads();
-        }
-        if (sh_stop)
-            break;
-    }
-    // eigenvalues on the diagonal; drop those <= rcond * l * lambda_max
-    if (tid == 0) {
-        double lmax = 0.0;
-        for (int i = 0; i < l; ++i)
-            lmax = fmax(lmax, S[i][i]);
-        sh_off = a.rcond * (double)l * lmax;
-    }
-    __syncthreads();
-    const double thresh = sh_off;
-    for (int e = tid; e < l; e += kLsqThreads) {
-        const double lam = S[e][e];
-        double proj = 0.0;
-        for (int i = 0; i < l; ++i)
-            proj += V[i][e] * cvec[i];
-        wvec[e] = lam > thresh ? proj / lam : 0.0;
-    }
-    __syncthreads();
-    for (int i = tid; i < l; i += kLsqThreads) {
-        double g = 0.0;
-        for (int e = 0; e < l; ++e)
-            g += V[i][e] * wvec[e];
-        gam[i] = g;
-    }
-    __syncthreads();
-    }   // !fast
+    if (!fast)
+        jacobi_pinv(l, a.rcond, (double)l, S, V, cvec, wvec, gam, rot_c, rot_s, pair_p, pair_q, sh_off, sh_stop);
 
     // ---- update plan ----
     // x_{k+1} = x_k + beta f_k - sum_i gamma_i (dX_i + beta dF_i), column i

@@ -236,6 +236,12 @@ struct aar_solver_t {
     std::vector<int64_t> last_log_count;
     int last_instance = 0;
 
+    // complex-valued system (aar_create_complex): A = A_r + i shift_im I,
+    // complex omega and beta; vectors interleaved (re, im)
+    bool cplx = false;
+    double shift_im = 0.0, omega_im = 0.0, beta_im = 0.0;
+    Path<zd> pz;
+
     // batched engine (count > 1 with one stencil radius and convection kind)
     struct Batch {
         bool on = false;
@@ -684,6 +690,96 @@ hipError_t enqueue_cycle(aar_solver_t *S, const Path<T> &P, bool inner, hipStrea
         return launch_update(P.hist, nullptr, &u, P.upd_blocks, s);
 }
 
+// One AAR cycle of a complex-valued system (complex.hip kernels): p - 1
+// sweeps from x and b with x ping-ponged, the Anderson-step residual, the
+// Hermitian Gram products, the one-wave solve and the update.
+hipError_t enqueue_cycle_complex(aar_solver_t *S, const Path<zd> &P, hipStream_t s)
+{
+    const aar_params &pa = S->params;
+    StencilArgs<zd> a;
+    std::memset(&a, 0, sizeof(a));
+    a.st = P.st;
+    a.b = P.b;
+    a.fring = P.fring;
+    a.state = S->state;
+    a.slot_stride = P.slot_stride;
+    a.p = pa.p;
+    a.nslots = pa.m + 1;
+    a.omega = zd(pa.omega, S->omega_im);
+    hipError_t e;
+    for (int j = 0; j < pa.p - 1; ++j) {
+        a.j = j;
+        a.x = (j & 1) ? P.xb : P.xa;
+        a.out = (j & 1) ? P.xa : P.xb;
+        if ((e = launch_stencil_complex(kSweep, P.radius, P.ts, a, nullptr, s)) != hipSuccess)
+            return e;
+    }
+    const int jk = pa.p - 1;
+    zd *xk = (jk & 1) ? P.xb : P.xa;
+    a.j = jk;
+    a.x = xk;
+    a.out = nullptr;
+    a.partial = S->part_rho;
+    if ((e = launch_stencil_complex(kFk, P.radius, P.ts, a, nullptr, s)) != hipSuccess)
+        return e;
+    GramArgs g;
+    g.fring = P.fring;
+    g.partial = S->part_gram;
+    g.state = S->state;
+    g.N = P.N;
+    g.slot_stride = P.slot_stride;
+    g.m = pa.m;
+    g.p = pa.p;
+    g.nslots = pa.m + 1;
+    g.ne = 2 * S->ne;
+    if ((e = launch_cgram(g, P.gram_blocks, s)) != hipSuccess)
+        return e;
+    if ((e = launch_gram_finish(S->part_gram, P.gram_blocks, S->gram_final, 2 * S->ne, S->state, pa.p, s)) !=
+        hipSuccess)
+        return e;
+    LsqArgs l;
+    l.state = S->state;
+    l.rho_partial = S->part_rho;
+    l.rho_blocks = P.rho_blocks;
+    l.gram_final = S->gram_final;
+    l.ne = S->ne;
+    l.m = pa.m;
+    l.p = pa.p;
+    l.nslots = pa.m + 1;
+    l.q = S->q;
+    l.omega = pa.omega;
+    l.beta = pa.beta;
+    l.rcond = std::ldexp(1.0, -52);
+    l.stagnation_window = 0;
+    l.stagnation_factor = 0.9;
+    l.log = S->log;
+    l.rank_log = S->rank_log;
+    l.log_cap = S->log_cap;
+    if ((e = launch_clsq(l, S->omega_im, S->beta_im, s)) != hipSuccess)
+        return e;
+    UpdateArgs<zd> u;
+    u.xin = xk;
+    u.xout = P.xa;
+    u.fring = P.fring;
+    u.fcur = nullptr;
+    u.dxring = P.dx;
+    u.state = S->state;
+    u.N = P.N;
+    u.slot_stride = P.slot_stride;
+    u.dx_stride = P.dx_stride;
+    u.status_out = S->status_dev;
+    return launch_cupdate(u, P.upd_blocks, s);
+}
+
+template <typename T>
+hipError_t enqueue_any(aar_solver_t *S, const Path<T> &P, bool inner, hipStream_t s, int64_t cycle_tag)
+{
+    if constexpr (std::is_same<T, zd>::value)
+        return enqueue_cycle_complex(S, P, s);
+    else
+        return enqueue_cycle<T>(S, P, inner, s, cycle_tag);
+}
+
 constexpr int kGraphCycles = 4;
 
 // Run cycles until the device state leaves kRunning (or every cycle up to
@@ -699,7 +795,7 @@ aar_status run_cycles(aar_solver_t *S, const Path<T> &P, int64_t max_iter, bool 
         AAR_HIP(hipStreamBeginCapture(S->capture_stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
         for (int c = 0; c < kGraphCycles && e == hipSuccess; ++c)
-            e = enqueue_cycle<T>(S, P, inner, S->capture_stream, 0);
+            e = enqueue_any<T>(S, P, inner, S->capture_stream, 0);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(S->capture_stream, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
@@ -720,7 +816,7 @@ aar_status run_cycles(aar_solver_t *S, const Path<T> &P, int64_t max_iter, bool 
         // run state after every group of cycles
         while (issued < needed) {
             for (int c = 0; c < kGraphCycles && issued < needed; ++c, ++issued) {
-                hipError_t e = enqueue_cycle<T>(S, P, inner, s, issued);
+                hipError_t e = enqueue_any<T>(S, P, inner, s, issued);
                 if (e != hipSuccess)
                     return fail(AAR_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
             }
@@ -739,7 +835,7 @@ aar_status run_cycles(aar_solver_t *S, const Path<T> &P, int64_t max_iter, bool 
             issued += S->graph_cycles;
         } else {
             for (int c = 0; c < kGraphCycles && issued < needed; ++c, ++issued) {
-                hipError_t e = enqueue_cycle<T>(S, P, inner, s, issued);
+                hipError_t e = enqueue_any<T>(S, P, inner, s, issued);
                 if (e != hipSuccess)
                     return fail(AAR_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
             }
@@ -1177,6 +1273,57 @@ aar_status solve_fp64(aar_solver_t *S, const Operator &op, const double *b, doub
     r.rel_residual = st.last_r;
     r.outer_steps = 0;
     *log_count = st.log_count;
+    if (res)
+        *res = r;
+    return (aar_status)r.status;
+}
+
+// Complex system: x (2N doubles, interleaved) holds x0 on entry and the answer on exit.
+aar_status solve_complex(aar_solver_t *S, const double *b, double *x, aar_result *res)
+{
+    const aar_params &pa = S->params;
+    Path<zd> &P = S->pz;
+    const int64_t N = P.N;
+    hipStream_t s = S->stream;
+    const bool use_graph = !(pa.flags & AAR_FLAG_NO_GRAPH) && !S->timing;
+    aar_result r{};
+    InstState st{};
+    AAR_HIP(hipMemcpyAsync(P.b, b, sizeof(zd) * N, hipMemcpyDeviceToDevice, s));
+    AAR_HIP(hipMemcpyAsync(P.xa, x, sizeof(zd) * N, hipMemcpyDeviceToDevice, s));
+    const int nb_blocks = stream_blocks(N);
+    AAR_HIP(launch_cnorm_partial(P.b, N, S->part_norm, nb_blocks, s));
+    AAR_HIP(launch_init_state(S->state, S->part_norm, nb_blocks, pa.max_iter, pa.tol, s));
+    AAR_HIP(hipMemcpyAsync(&st, S->state, sizeof(InstState), hipMemcpyDeviceToHost, s));
+    AAR_HIP(hipStreamSynchronize(s));
+    if (st.nb == 0.0) {
+        AAR_HIP(launch_zero_f64(x, 2 * N, s));
+        AAR_HIP(hipStreamSynchronize(s));
+        r.status = AAR_OK;
+        if (res)
+            *res = r;
+        S->last_log_count[0] = 0;
+        return AAR_OK;
+    }
+    aar_status e = run_cycles<zd>(S, P, pa.max_iter, false, use_graph, &st);
+    if (e != AAR_OK)
+        return e;
+    const int64_t done = (st.status == kMaxIter || st.status == kRunning) ? pa.max_iter : st.iters;
+    const int64_t j = (done - 1) % pa.p;
+    const bool anderson_last = (st.status == kMaxIter || st.status == kRunning) && j == pa.p - 1;
+    const zd *xf;
+    if (st.status == kConverged || st.status == kBreakdown)
+        xf = ((pa.p - 1) & 1) ? P.xb : P.xa;
+    else if (anderson_last)
+        xf = P.xa;
+    else
+        xf = ((j + 1) & 1) ? P.xb : P.xa;
+    AAR_HIP(hipMemcpyAsync(x, xf, sizeof(zd) * N, hipMemcpyDeviceToDevice, s));
+    AAR_HIP(hipStreamSynchronize(s));
+    r.status = status_of(st);
+    r.iterations = done;
+    r.rel_residual = st.last_r;
+    r.outer_steps = 0;
+    S->last_log_count[0] = st.log_count;
     if (res)
         *res = r;
     return (aar_status)r.status;
@@ -2284,6 +2431,106 @@ aar_status aar_solve_noalloc(const aar_problem *problem, const aar_params *param
     return solve_noalloc(problem, params, b, x, r, hip_stream);
 }
 
+aar_status aar_create_complex(aar_solver *out, const aar_problem *problem, const aar_params *params,
+                              double shift_imag, double omega_imag, double beta_imag, void *hip_stream)
+{
+    g_error.clear();
+    if (!out)
+        return fail(AAR_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!problem)
+        return fail(AAR_ERR_INVALID_ARG, "problem is NULL");
+    aar_status st = validate_params(params);
+    if (st != AAR_OK)
+        return st;
+    // the real part of a complex shift may be negative (Eq. 7: Re Q < 0)
+    aar_problem pr = *problem;
+    if (!std::isfinite(pr.shift))
+        return fail(AAR_ERR_INVALID_ARG, "shift must be finite");
+    pr.shift = std::fabs(pr.shift);
+    if ((st = validate_problem(pr, 0)) != AAR_OK)
+        return st;
+    if (!std::isfinite(shift_imag) || !std::isfinite(omega_imag) || !std::isfinite(beta_imag))
+        return fail(AAR_ERR_INVALID_ARG, "imaginary parts must be finite");
+    if (params->precision != AAR_FP64)
+        return fail(AAR_ERR_UNSUPPORTED, "complex systems run the FP64 iteration only");
+    if (params->m > 8)
+        return fail(AAR_ERR_UNSUPPORTED, "complex systems need m <= 8");
+    if (problem->velocity)
+        return fail(AAR_ERR_UNSUPPORTED, "complex systems take no convection");
+    if (params->flags & AAR_FLAG_DEFLATE_CONSTANT)
+        return fail(AAR_ERR_UNSUPPORTED, "AAR_FLAG_DEFLATE_CONSTANT is for real systems");
+    std::unique_ptr<aar_solver_t> S(new aar_solver_t());
+    S->params = *params;
+    S->stream = (hipStream_t)hip_stream;
+    S->cplx = true;
+    S->shift_im = shift_imag;
+    S->omega_im = omega_imag;
+    S->beta_im = beta_imag;
+    AAR_HIP(hipGetDevice(&S->device));
+    AAR_HIP(hipStreamCreateWithFlags(&S->capture_stream, hipStreamNonBlocking));
+    AAR_HIP(hipHostMalloc((void **)&S->host_status, 2 * sizeof(int32_t),
+                          hipHostMallocMapped | hipHostMallocCoherent));
+    S->host_status[0] = S->host_status[1] = kRunning;
+    AAR_HIP(hipHostGetDevicePointer((void **)&S->status_dev, S->host_status, 0));
+    for (auto &e : S->poll_ev)
+        AAR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    const Sizes z = compute_sizes(problem, 1, params);
+    S->maxN = z.maxN;
+    S->q = z.q;
+    S->ne = z.ne;
+    S->last_log_count.assign(1, 0);
+    Operator op = build_operator(*problem);
+    op.ts[0] = default_tile(problem->radius, true);
+    op.ts[0].ry = std::min(op.ts[0].ry, 2);   // complex tiles hold at most 2 rows per thread
+    S->ops.push_back(op);
+    const int64_t N = (z.maxN + 7) / 8 * 8;
+    const int slots = params->m + 1;
+    st = AAR_OK;
+    S->state = S->alloc<InstState>(1, &st);
+    S->part_rho = S->alloc<double>(z.max_stencil_blocks, &st);
+    S->part_rho_cap = z.max_stencil_blocks;
+    S->part_gram = S->alloc<double>((size_t)std::max(z.gram_blocks, z.max_stencil_blocks) * 2 * z.ne, &st);
+    S->part_norm = S->alloc<double>(z.gram_blocks, &st);
+    S->gram_final = S->alloc<double>(2 * z.ne, &st);
+    S->scal = S->alloc<double>(8, &st);
+    if (z.log_cap > 0) {
+        S->log_cap = z.log_cap;
+        S->log = S->alloc<double>(z.log_cap, &st);
+        S->rank_log = S->alloc<int32_t>(z.log_cap, &st);
+    }
+    Path<zd> &P = S->pz;
+    P.xa = S->alloc<zd>(N, &st);
+    P.xb = S->alloc<zd>(N, &st);
+    P.b = S->alloc<zd>(N, &st);
+    P.fring = S->alloc<zd>((size_t)N * slots, &st);
+    P.dx = S->q > 0 ? (void *)S->alloc<zd>((size_t)N * S->q, &st) : nullptr;
+    if (st != AAR_OK)
+        return st;
+    P.hist = Prec::F64;
+    P.N = op.N;
+    P.radius = problem->radius;
+    P.conv = false;
+    P.ts = op.ts[0];
+    int tx, ty, tz, blocks;
+    stencil_grid(problem->n[0], problem->n[1], problem->n[2], P.ts, &tx, &ty, &tz, &blocks);
+    P.rho_blocks = blocks;
+    P.gram_blocks = gram_blocks(op.N, params->m);
+    P.upd_blocks = stream_blocks(op.N);
+    P.slot_stride = N;
+    P.dx_stride = N;
+    P.st = make_stencil<zd>(op, (const zd *)nullptr);
+    // the imaginary shift enters the centre weight, sigma and the Jacobi diagonal
+    P.st.sigma = zd(problem->shift, shift_imag);
+    P.st.diag = zd(op.diag, shift_imag);
+    P.st.jdiag = zd(op.jdiag, shift_imag);
+    P.st.inv_diag = zd(1.0) / P.st.jdiag;
+    if (P.rho_blocks > S->part_rho_cap)
+        return fail(AAR_ERR_DEVICE, "stencil grid exceeds the partial-sum workspace");
+    *out = S.release();
+    return AAR_OK;
+}
+
 aar_status aar_destroy(aar_solver s)
 {
     if (!s)
@@ -2300,6 +2547,8 @@ aar_status aar_solve(aar_solver s, const double *b, double *x, aar_result *r)
         return fail(AAR_ERR_INVALID_ARG, "solver, b or x is NULL");
     if (s->ops.size() != 1)
         return fail(AAR_ERR_INVALID_ARG, "aar_solve needs a solver created with count == 1");
+    if (s->cplx)
+        return solve_complex(s, b, x, r);
     return solve_one(s, 0, b, x, r);
 }
 
@@ -2315,6 +2564,8 @@ aar_status aar_solve_batched(aar_solver s, const double *b, double *x, const int
             return fail(AAR_ERR_INVALID_ARG, "offsets do not match the system sizes (system " +
                                                  std::to_string(i) + ")");
     }
+    if (s->cplx)
+        return fail(AAR_ERR_UNSUPPORTED, "complex systems are solved one by one (aar_solve)");
     if (s->B.on)
         return batch_solve(s, b, x, offsets, results);
     aar_status worst = AAR_OK;
@@ -2335,6 +2586,16 @@ aar_status aar_apply(aar_solver s, int32_t instance, const double *x, double *y)
         return fail(AAR_ERR_INVALID_ARG, "solver, x or y is NULL");
     if (instance < 0 || instance >= (int)s->ops.size())
         return fail(AAR_ERR_INVALID_ARG, "instance out of range");
+    if (s->cplx) {
+        StencilArgs<zd> a;
+        std::memset(&a, 0, sizeof(a));
+        a.st = s->pz.st;
+        a.x = reinterpret_cast<const zd *>(x);
+        a.out = reinterpret_cast<zd *>(y);
+        AAR_HIP(launch_stencil_complex(kApply, s->pz.radius, s->pz.ts, a, nullptr, s->stream));
+        AAR_HIP(hipStreamSynchronize(s->stream));
+        return AAR_OK;
+    }
     Path<double> P;
     bind_path(s, P, instance, true);
     StencilArgs<double> a;

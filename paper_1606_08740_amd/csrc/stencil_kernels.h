@@ -62,7 +62,7 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs<T> &a, int lin, d
 {
     // FP64 hot passes use the weighted-sum form (half the flops); FP32 passes
     // and the FP64 refinement residual keep the difference form.
-    constexpr bool kStd = sizeof(T) == 8 && MODE != kResid;
+    constexpr bool kStd = (std::is_same<T, double>::value || std::is_same<T, zd>::value) && MODE != kResid;
     constexpr int TY = kWY * RY;
     constexpr int LX = kTX + 2 * R;
     constexpr int LY = TY + 2 * R;
@@ -296,7 +296,7 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs<T> &a, int lin, d
             } else if constexpr (MODE == kResid) {
                 const T res = bcur[ry] - ax;
                 a.out[id] = res;
-                acc += (double)res * (double)res;
+                acc += sqnorm(res);
             } else {
                 T f, res;
                 if (recur) {
@@ -314,7 +314,7 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs<T> &a, int lin, d
                 } else {
                     if (a.fcur)
                         a.fcur[id] = f;
-                    acc += (double)res * (double)res;
+                    acc += sqnorm(res);
                 }
             }
         }

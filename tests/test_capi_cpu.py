@@ -127,3 +127,18 @@ def test_tile_file_block_depth_field(tmp_path, monkeypatch):
     monkeypatch.setenv("AAR_TUNE_CACHE", str(f))
     for n in (12, 13, 14):
         assert _ws(inputs.dirichlet_poisson_problem(n), inputs.Params()) > 0
+
+
+@pytest.mark.parametrize("change,status", [
+    (dict(m=9), aar.AAR_ERR_UNSUPPORTED), (dict(precision=1), aar.AAR_ERR_UNSUPPORTED),
+    (dict(flags=2), aar.AAR_ERR_UNSUPPORTED), (dict(p=0), aar.AAR_ERR_INVALID_ARG),
+])
+def test_complex_create_rejects(change, status):
+    """aar_create_complex checks its arguments before any device work."""
+    prm = inputs.Params()
+    for k, v in change.items():
+        setattr(prm, k, v)
+    prob = inputs.periodic_problem(8, 3, shift=0.5)
+    with pytest.raises(aar.AarError) as ei:
+        aar.aar_create_complex(aar.make_problem(prob), aar.make_params(prm), -0.07)
+    assert ei.value.status == status
