@@ -21,7 +21,9 @@ the error against the oracle's stored FP64 solution:
   batched  512 periodic shifted Helmholtz systems of uneven sizes in one call:
            the paper's method in FP64 and, with the exact constant-mode
            deflation (not in the paper), FP64, mixed and FP64 + FP32 ring;
-           each with a whole-call bandwidth figure.
+           each with a whole-call bandwidth figure;
+  complex_helmholtz  the complex periodic Helmholtz problem of orbital-free
+           DFT (the paper's P and Q), 72^3 and 144^3, complex FP64.
 `roofline` covers the dominant kernel of the headline, the Richardson sweep:
 algorithmic bytes per launch over the mean launch time measured with HIP
 events on the solver's stream, against the 8 TB/s HBM peak.  Each solve also
@@ -159,6 +161,56 @@ def cycle_bytes(precision, m, p, fused_gram=False):
     return sweeps + resid + gram + update
 
 
+def complex_cycle_bytes(m, p):
+    """Algorithmic bytes per point of one cycle of the complex iteration
+    (16-byte values; every Richardson sweep reads x and b and writes x and f,
+    the Anderson-step residual reads x and b and writes f, the Gram pass reads
+    the m + 1 slots, the update reads x, the slots and the q increments and
+    writes x and one increment)."""
+    z, q = 16, m // p
+    return (p - 1) * 4 * z + 3 * z + (m + 1) * z + (z + (m + 1) * z + q * z + 2 * z)
+
+
+def run_complex(args):
+    """The complex periodic Helmholtz problem of orbital-free DFT (the
+    paper's P, Q and alpha; sixth-order FD) on one and on eight aluminium
+    cells at h = 0.108 Bohr, complex FP64."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1606_08740_amd import aar, inputs
+    out = {}
+    for n, cells in ((72, 1), (144, 2)):
+        log(f"complex helmholtz n={n}")
+        prob, s_im, b, prm = inputs.ofdft_helmholtz(n, cells=cells)
+        bt = torch.as_tensor(b, device="cuda:0")
+        s = aar.ComplexSolver(prob, prm, s_im)
+        res = None
+        for _ in range(max(args.warmup, 1)):
+            res = s.solve(bt, torch.zeros_like(bt))
+        xs = [torch.zeros_like(bt) for _ in range(args.side_steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for x in xs:
+            res = s.solve(bt, x)
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - t0) / args.side_steps
+        s.close()
+        x = xs[-1].cpu().numpy()
+        cb = complex_cycle_bytes(prm.m, prm.p)
+        gbs = prob.size * cb * (res["iterations"] / prm.p) / per / 1e9
+        out[f"n{n}"] = {"workload": f"OF-DFT periodic Helmholtz (Eq. 7), {cells}^3 Al FCC cells, {n}^3 grid, "
+                                    "h = 0.108 Bohr, sixth-order FD, Jacobi, m=7, p=6, tol 1e-10, complex FP64",
+                        "value": 1.0 / per, "unit": "solves/s", "ms_per_solve": per * 1e3,
+                        "iterations": res["iterations"], "status": res["status"],
+                        "rel_residual": res["rel_residual"],
+                        "rel_residual_oracle_operator": oracle.relative_residual_complex(prob, s_im, b, x),
+                        "effective_GBs": gbs, "effective_frac_of_peak": gbs / HBM_PEAK_GBS,
+                        "bytes_per_point_per_cycle": cb}
+        del bt, xs
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,7 +221,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=120)
     ap.add_argument("--kernel-timing-solves", type=int, default=1)
-    ap.add_argument("--only", choices=["headline", "c1", "c2", "c3", "c4", "c5"],
+    ap.add_argument("--only", choices=["headline", "c1", "c2", "c3", "c4", "c5", "complex"],
                     help="run one part only and print its JSON object (for profiling)")
     ap.add_argument("--precision", type=int, choices=[0, 1, 2, 3, 4],
                     help="with --only: the one precision mode to time")
@@ -468,6 +520,9 @@ def main():
     if args.only == "c1":
         print(json.dumps(c1(args)))
         return
+    if args.only == "complex":
+        print(json.dumps(run_complex(args)))
+        return
     if args.only == "c5":
         modes = None
         if args.precision is not None:
@@ -525,6 +580,7 @@ def main():
     del w4
     out["c1_32"] = c1(args)
     out["batched"] = run_batched(args)
+    out["complex_helmholtz"] = run_complex(args)
 
     # ---- CPU oracle baseline (bounded sample) ----
     if not args.no_cpu_baseline:

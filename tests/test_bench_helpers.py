@@ -63,3 +63,8 @@ def test_byte_models():
     assert bench.cycle_bytes(bench.FP64_FP32HIST, 7, 6) == 20 + 4 * 8 + 8 + 32 + 56
     assert bench.cycle_bytes(bench.MIXED, 7, 6) == 12 + 4 * 8 + 8 + 32 + 4 + 32 + 4 + 4 + 4
     assert bench.cycle_bytes(bench.FP64_BF16HIST, 7, 6) is None
+
+
+def test_complex_byte_model():
+    # 5 sweeps x 64 + residual 48 + Gram 8 x 16 + update 16 + 128 + 16 + 32
+    assert bench.complex_cycle_bytes(7, 6) == 5 * 64 + 48 + 128 + 192
