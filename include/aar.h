@@ -109,7 +109,8 @@ enum {
     AAR_FLAG_DEFLATE_CONSTANT = 2, /* exact FP64 removal of the constant mode, see below        */
     AAR_FLAG_NO_GRAPH = 4,         /* launch kernels one by one instead of replaying HIP graphs */
     AAR_FLAG_NO_AUTOTUNE = 8,      /* use the default tile shape instead of timing candidates   */
-    AAR_FLAG_FORCE_PINV = 16       /* every m x m solve by the eigendecomposition, see below    */
+    AAR_FLAG_FORCE_PINV = 16,      /* every m x m solve by the eigendecomposition, see below    */
+    AAR_FLAG_RECYCLE_HISTORY = 32  /* mixed modes: inner runs keep the previous run's history     */
 };
 /* AAR_FLAG_DEFLATE_CONSTANT: when every axis is periodic and sigma > 0, the
  * constant vector is an exact eigenvector, A 1 = sigma 1 (upwind convection
@@ -127,6 +128,17 @@ enum {
  * proves every eigenvalue of F^T F above the pseudoinverse threshold (the
  * pseudoinverse is then the inverse), and the Jacobi eigendecomposition
  * otherwise.  With the flag every solve takes the eigendecomposition. */
+
+/* AAR_FLAG_RECYCLE_HISTORY (mixed precision modes, single solves): each inner
+ * FP32 run after the first starts with the history of the previous run
+ * instead of an empty one.  The history is never cleared within a run
+ * (Sec. 2); its difference pairs satisfy dF = -D^-1 A dX for any right-hand
+ * side, so they stay valid extrapolation directions for the next correction
+ * equation A d = r / ||r||.  The one difference that spans the restart pairs
+ * residuals of two right-hand sides and enters as a null column (its rows of
+ * F^T F and F^T f are zero; the pseudoinverse gives it no weight, as the
+ * footnote to Eq. 5 allows).  aar_create returns AAR_ERR_UNSUPPORTED for the
+ * flag with an FP64 mode or a batch. */
 
 /* One linear system A x = b (Sec. 2, Eq. 1). */
 typedef struct {
@@ -241,6 +253,25 @@ aar_status aar_rank_log(aar_solver s, int32_t instance, int32_t *out, int64_t ca
  * several threads or streams) race and must be serialized by the caller. */
 aar_status aar_solve_noalloc(const aar_problem *problem, const aar_params *params, const double *b, double *x,
                              aar_result *r, void *hip_stream);
+
+/* Choose the Anderson relaxation beta and the period p for one real system
+ * by timing short trial solves (a setup call: it creates and destroys a
+ * solver per candidate and allocates one vector).  The paper fixes
+ * {omega, beta, m, p} = {0.6, 0.6, 9, 8} and notes that the method is
+ * insensitive to them over a broad range but that a larger beta can speed up
+ * well-conditioned problems (Sec. 2, closing paragraphs; Sec. 3.1 tunes beta
+ * per matrix).  For every pair (betas[i], ps[j]) the solve of `problem` with
+ * right-hand side b (device FP64) from x_0 = 0 runs trial_iterations
+ * iterations (rounded up to a multiple of that p) twice, and the second run is
+ * scored by the decimal digits its residual fell per second,
+ * -log10(r_last) / seconds (0 after a breakdown).  The best pair is written to
+ * *beta_out, *p_out; scores (may be NULL) receives all of them, index
+ * j * nbeta + i.  Other fields of params are used as given (its beta and p are
+ * ignored). */
+aar_status aar_select_parameters(const aar_problem *problem, const aar_params *params, const double *b,
+                                 const double *betas, int32_t nbeta, const int32_t *ps, int32_t np,
+                                 int64_t trial_iterations, void *hip_stream, double *beta_out, int32_t *p_out,
+                                 double *scores);
 
 /* Device bytes aar_create would allocate for these arguments. */
 aar_status aar_workspace_bytes(const aar_problem *problems, int32_t count, const aar_params *params,

@@ -25,7 +25,7 @@ AAR_ERR_INVALID_ARG, AAR_ERR_UNSUPPORTED, AAR_ERR_DEVICE, AAR_ERR_OUT_OF_MEMORY 
 AAR_BC_ZERO_DIRICHLET, AAR_BC_PERIODIC = 0, 1
 AAR_FP64, AAR_MIXED_FP32, AAR_MIXED_FP32_BF16HIST, AAR_FP64_FP32HIST, AAR_FP64_BF16HIST = 0, 1, 2, 3, 4
 AAR_FLAG_RECORD_RESIDUALS, AAR_FLAG_DEFLATE_CONSTANT, AAR_FLAG_NO_GRAPH, AAR_FLAG_NO_AUTOTUNE = 1, 2, 4, 8
-AAR_FLAG_FORCE_PINV = 16
+AAR_FLAG_FORCE_PINV, AAR_FLAG_RECYCLE_HISTORY = 16, 32
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "BREAKDOWN", -1: "INVALID_ARG", -2: "UNSUPPORTED",
                 -3: "DEVICE", -4: "OUT_OF_MEMORY"}
@@ -79,6 +79,8 @@ def load_library():
     lib.aar_solve_noalloc.argtypes = [P(aar_problem), P(aar_params), vp, vp, P(aar_result), vp]
     d = ctypes.c_double
     lib.aar_create_complex.argtypes = [P(vp), P(aar_problem), P(aar_params), d, d, d, vp]
+    lib.aar_select_parameters.argtypes = [P(aar_problem), P(aar_params), vp, P(d), i32, P(i32), i32, i64, vp,
+                                          P(d), P(i32), P(d)]
     lib.aar_workspace_bytes.argtypes = [P(aar_problem), i32, P(aar_params), P(ctypes.c_size_t)]
     lib.aar_destroy.argtypes = [vp]
     lib.aar_last_error.argtypes = []
@@ -86,7 +88,7 @@ def load_library():
     lib.aar_set_timing.argtypes = [vp, i32]
     lib.aar_sweep_time.argtypes = [vp, P(ctypes.c_double), P(i64)]
     for name in ["aar_create", "aar_solve", "aar_solve_batched", "aar_apply", "aar_residual_log",
-                 "aar_rank_log", "aar_solve_noalloc", "aar_create_complex", "aar_workspace_bytes", "aar_destroy", "aar_set_timing",
+                 "aar_rank_log", "aar_solve_noalloc", "aar_create_complex", "aar_select_parameters", "aar_workspace_bytes", "aar_destroy", "aar_set_timing",
                  "aar_sweep_time"]:
         getattr(lib, name).restype = st
     _lib = lib
@@ -125,6 +127,19 @@ def aar_create_complex(problem, params, shift_imag: float, omega_imag: float = 0
                                              float(shift_imag), float(omega_imag), float(beta_imag),
                                              ctypes.c_void_p(hip_stream)), "aar_create_complex")
     return h
+
+
+def aar_select_parameters(problem, params, b_ptr: int, betas, ps, trial_iterations: int, hip_stream: int = 0):
+    """Returns (beta, p, scores[len(ps)][len(betas)])."""
+    nb, npp = len(betas), len(ps)
+    bet = (ctypes.c_double * nb)(*[float(v) for v in betas])
+    pp = (ctypes.c_int32 * npp)(*[int(v) for v in ps])
+    sc = (ctypes.c_double * (nb * npp))()
+    bo, po = ctypes.c_double(0.0), ctypes.c_int32(0)
+    _check(load_library().aar_select_parameters(ctypes.byref(problem), ctypes.byref(params), ctypes.c_void_p(b_ptr),
+                                                bet, nb, pp, npp, int(trial_iterations), ctypes.c_void_p(hip_stream),
+                                                ctypes.byref(bo), ctypes.byref(po), sc), "aar_select_parameters")
+    return bo.value, po.value, np.array(list(sc)).reshape(npp, nb)
 
 
 def aar_solve(handle, b_ptr: int, x_ptr: int) -> aar_result:

@@ -49,6 +49,10 @@ struct alignas(64) InstState {
     int32_t since_best;
     int32_t log_count;
     // update plan of the current Anderson step, x_{k+1} = x_k + sum alpha_t f_t + sum delta_a dx_a
+    // first history position of the current run when the history is carried
+    // over from a previous run (0: none); the difference column that spans it
+    // pairs residuals of two right-hand sides and is left out (a null column)
+    int64_t restart_pos;
     int32_t nf;             // number of f slots used (l + 1); the last one is f_k
     int32_t nd;             // number of dx slots used
     int32_t wslot;          // dx slot receiving x_{k+1} - x_k (-1: none kept)
@@ -545,6 +549,10 @@ hipError_t launch_finalize_f32(float *x, const void *fring, const InstState *sta
 hipError_t launch_norm_partial(bool f64, const void *v, int64_t N, double *partial, int blocks, hipStream_t s);
 hipError_t launch_init_state(InstState *st, const double *partial, int blocks, int64_t max_iter, double tol,
                              hipStream_t s);
+// Start a run that keeps the history of the previous one (which ended at an
+// Anderson step): the positions continue after it, budget iterations from there.
+hipError_t launch_init_state_keep(InstState *st, const double *partial, int blocks, int64_t budget, double tol,
+                                  int p, hipStream_t s);
 hipError_t launch_finish_norm(double *out, const double *partial, int blocks, hipStream_t s);
 hipError_t launch_cast_f64_to_f32(const double *in, float *out, int64_t N, const double *scale_inv_of,
                                   hipStream_t s);

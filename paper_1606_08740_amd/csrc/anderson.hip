@@ -593,7 +593,37 @@ __global__ __launch_bounds__(64) void k_init_state(InstState *st, const double *
         st->nf = 0;
         st->nd = 0;
         st->wslot = -1;
+        st->restart_pos = 0;
     }
+}
+
+__global__ __launch_bounds__(64) void k_init_state_keep(InstState *st, const double *partial, int blocks,
+                                                        int64_t budget, double tol, int p)
+{
+    const double s = block_fixed_sum(partial, blocks);
+    if (threadIdx.x == 0) {
+        // the previous run stopped at an Anderson step without extrapolating:
+        // the next cycle starts the new run
+        const int64_t cycle = st->cycle + 1;
+        st->cycle = cycle;
+        st->restart_pos = cycle * p;
+        st->max_iter = cycle * p + budget;
+        st->tol = tol;
+        st->iters = 0;
+        st->status = kRunning;
+        st->nb = sqrt(s);
+        st->last_r = 0.0;
+        st->best_r = INFINITY;
+        st->since_best = 0;
+        st->log_count = 0;
+    }
+}
+
+hipError_t launch_init_state_keep(InstState *st, const double *partial, int blocks, int64_t budget, double tol,
+                                  int p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init_state_keep, dim3(1), dim3(64), 0, s, st, partial, blocks, budget, tol, p);
+    return hipGetLastError();
 }
 
 hipError_t launch_init_state(InstState *st, const double *partial, int blocks, int64_t max_iter, double tol,

@@ -300,6 +300,7 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
     const int64_t cycle0 = st->cycle, max_iter0 = st->max_iter;
     const double nb0 = st->nb, tol0 = st->tol, best_r0 = st->best_r;
     const int log_count0 = st->log_count, since_best0 = st->since_best;
+    const int64_t restart0 = st->restart_pos;
     if (status0 != kRunning)
         return;
     const int64_t k = cycle0 * a.p + a.p - 1;
@@ -311,6 +312,39 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
         return;
     }
     const int l = (int)(k < a.m ? k : a.m);
+    // the column k - l + cb -> k - l + cb + 1 that spans a carried-over
+    // history's restart (its two residuals belong to different right-hand
+    // sides) is a null column: its row and column of F^T F and its entry of
+    // F^T f are zero, so the pseudoinverse gives it no weight (footnote to Eq. 5)
+    const int64_t cb64 = restart0 > 0 ? restart0 - 1 - (k - l) : -1;
+    const int cb = (cb64 >= 0 && cb64 < l) ? (int)cb64 : -1;
+    if (cb >= 0) {
+        if (small) {
+#pragma unroll
+            for (int i = 0; i < kRegM; ++i) {
+#pragma unroll
+                for (int j = 0; j <= i; ++j)
+                    R[i][j] = (i == cb || j == cb) ? 0.0 : R[i][j];
+                cr[i] = i == cb ? 0.0 : cr[i];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int e = tid + u * kLsqThreads;
+                if (e < np) {
+                    int row = 0, rem = e;
+                    while (rem >= a.m - row) {
+                        rem -= a.m - row;
+                        ++row;
+                    }
+                    if (row == cb || row + rem == cb)
+                        gv[u] = 0.0;
+                } else if (e - np == cb) {
+                    gv[u] = 0.0;
+                }
+            }
+        }
+    }
 
     const double rel = sqrt(rho2) / nb0;
     if (tid == 0) {
@@ -463,10 +497,10 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
             // the Jacobi path works on S and c in LDS
             for (int idx = tid; idx < l * l; idx += kLsqThreads) {
                 const int i = idx / l, j = idx % l;
-                S[i][j] = gram_vals[i <= j ? tri_index(i, j, a.m) : tri_index(j, i, a.m)];
+                S[i][j] = (i == cb || j == cb) ? 0.0 : gram_vals[i <= j ? tri_index(i, j, a.m) : tri_index(j, i, a.m)];
             }
             for (int i = tid; i < l; i += kLsqThreads)
-                cvec[i] = gram_vals[np + i];
+                cvec[i] = i == cb ? 0.0 : gram_vals[np + i];
             __syncthreads();
         }
     } else if (l > 0 && !a.force_pinv) {

@@ -670,6 +670,7 @@ __global__ __launch_bounds__(64) void k_ctl_batched(const BatchCtlArgs a)
         st.nf = 0;
         st.nd = 0;
         st.wslot = -1;
+        st.restart_pos = 0;
         if (!(st.nb > 0.0)) {       // b = 0: x = 0 after zero iterations
             st.status = kConverged;
             c.phase = kPhaseDone;

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -1380,6 +1381,7 @@ aar_status solve_one(aar_solver_t *S, int idx, const double *b, double *x, aar_r
     }
     const double inner_tol = pa.inner_tol > 0.0 ? pa.inner_tol : 1e-5;
     const int max_outer = pa.max_outer > 0 ? pa.max_outer : 30;
+    const bool recycle = (pa.flags & AAR_FLAG_RECYCLE_HISTORY) != 0;
     int64_t used = 0;
     int outer = 0;
     aar_status final = AAR_NOT_CONVERGED;
@@ -1420,16 +1422,25 @@ aar_status solve_one(aar_solver_t *S, int idx, const double *b, double *x, aar_r
         AAR_HIP(launch_zero_f32(P.xa, N, s));
         AAR_HIP(launch_norm_partial(false, P.b, N, S->part_norm, nb_blocks, s));
         const int64_t budget = pa.max_iter - used;
-        AAR_HIP(launch_init_state(S->state, S->part_norm, nb_blocks, budget, inner_tol, s));
-        aar_status e = run_cycles<float>(S, P, budget, true, use_graph, &st);
+        // with AAR_FLAG_RECYCLE_HISTORY the inner runs after the first keep the
+        // history of the previous one: its difference pairs satisfy
+        // dF = -D^-1 A dX whatever the right-hand side, so they remain valid
+        // extrapolation directions for the next correction equation
+        const bool keep = recycle && outer > 0;
+        const int64_t start = keep ? (st.cycle + 1) * pa.p : 0;   // the run's first position
+        if (keep)
+            AAR_HIP(launch_init_state_keep(S->state, S->part_norm, nb_blocks, budget, inner_tol, pa.p, s));
+        else
+            AAR_HIP(launch_init_state(S->state, S->part_norm, nb_blocks, budget, inner_tol, s));
+        aar_status e = run_cycles<float>(S, P, start + budget, true, use_graph, &st);
         if (e != AAR_OK)
             return e;
         if (st.status == kBreakdown) {
             final = AAR_BREAKDOWN;
-            used += st.iters;
+            used += st.iters - start;
             break;
         }
-        const int64_t done = (st.status == kMaxIter || st.status == kRunning) ? budget : st.iters;
+        const int64_t done = (st.status == kMaxIter || st.status == kRunning) ? budget : st.iters - start;
         used += done;
         const int64_t j = (done - 1) % pa.p;
         const bool anderson_last = (st.status == kMaxIter || st.status == kRunning) && j == pa.p - 1;
@@ -2294,6 +2305,10 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
         }
     }
 
+    if ((params->flags & AAR_FLAG_RECYCLE_HISTORY) &&
+        (!is_mixed(params->precision) || batch_eligible(problems, count, params)))
+        return fail(AAR_ERR_UNSUPPORTED, "AAR_FLAG_RECYCLE_HISTORY needs a mixed precision mode and single solves");
+
     std::unique_ptr<aar_solver_t> S(new aar_solver_t());
     S->params = *params;
     S->stream = (hipStream_t)hip_stream;
@@ -2529,6 +2544,84 @@ aar_status aar_create_complex(aar_solver *out, const aar_problem *problem, const
         return fail(AAR_ERR_DEVICE, "stencil grid exceeds the partial-sum workspace");
     *out = S.release();
     return AAR_OK;
+}
+
+aar_status aar_select_parameters(const aar_problem *problem, const aar_params *params, const double *b,
+                                 const double *betas, int32_t nbeta, const int32_t *ps, int32_t np,
+                                 int64_t trial_iterations, void *hip_stream, double *beta_out, int32_t *p_out,
+                                 double *scores)
+{
+    g_error.clear();
+    if (!problem || !params || !b || !betas || !ps || nbeta < 1 || np < 1 || !beta_out || !p_out)
+        return fail(AAR_ERR_INVALID_ARG, "problem, params, b, candidates or outputs invalid");
+    if (trial_iterations < 1)
+        return fail(AAR_ERR_INVALID_ARG, "trial_iterations must be >= 1");
+    aar_status st = validate_params(params);
+    if (st != AAR_OK)
+        return st;
+    if ((st = validate_problem(*problem, 0)) != AAR_OK)
+        return st;
+    for (int i = 0; i < nbeta; ++i)
+        if (!std::isfinite(betas[i]))
+            return fail(AAR_ERR_INVALID_ARG, "beta candidates must be finite");
+    for (int i = 0; i < np; ++i)
+        if (ps[i] < 1)
+            return fail(AAR_ERR_INVALID_ARG, "p candidates must be >= 1");
+    const int64_t N = (int64_t)problem->n[0] * problem->n[1] * problem->n[2];
+    hipStream_t s = (hipStream_t)hip_stream;
+    double *x = nullptr;
+    hipError_t he = hipMalloc(&x, sizeof(double) * N);
+    if (he != hipSuccess)
+        return fail(he == hipErrorOutOfMemory ? AAR_ERR_OUT_OF_MEMORY : AAR_ERR_DEVICE,
+                    std::string("hipMalloc: ") + hipGetErrorString(he));
+    double best = -1.0;
+    aar_status result = AAR_OK;
+    for (int ip = 0; ip < np && result == AAR_OK; ++ip) {
+        for (int ib = 0; ib < nbeta && result == AAR_OK; ++ib) {
+            aar_params pa = *params;
+            pa.beta = betas[ib];
+            pa.p = ps[ip];
+            // a common budget: the trial's iterations rounded up to a multiple of p
+            pa.max_iter = (trial_iterations + pa.p - 1) / pa.p * pa.p;
+            pa.flags &= ~(uint32_t)AAR_FLAG_RECORD_RESIDUALS;
+            aar_solver h = nullptr;
+            if ((result = aar_create(&h, problem, 1, &pa, hip_stream)) != AAR_OK)
+                break;
+            double score = 0.0;
+            aar_result r{};
+            for (int rep = 0; rep < 2 && result == AAR_OK; ++rep) {   // the first run warms up
+                if (hipMemsetAsync(x, 0, sizeof(double) * N, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess) {
+                    result = fail(AAR_ERR_DEVICE, "aar_select_parameters: clearing x failed");
+                    break;
+                }
+                const auto t0 = std::chrono::steady_clock::now();
+                const aar_status e = aar_solve(h, b, x, &r);
+                const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                if (e < 0) {
+                    result = e;
+                    break;
+                }
+                // decimal digits of residual reduction per second (0 for a
+                // trial that broke down or grew the residual)
+                const double digits = (e == AAR_BREAKDOWN || !(r.rel_residual > 0.0)) ? 0.0
+                                      : -std::log10(r.rel_residual);
+                score = std::max(0.0, digits) / std::max(dt, 1e-9);
+            }
+            (void)aar_destroy(h);
+            if (result != AAR_OK)
+                break;
+            if (scores)
+                scores[ip * nbeta + ib] = score;
+            if (score > best) {
+                best = score;
+                *beta_out = pa.beta;
+                *p_out = pa.p;
+            }
+        }
+    }
+    (void)hipFree(x);
+    return result;
 }
 
 aar_status aar_destroy(aar_solver s)

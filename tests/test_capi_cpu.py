@@ -142,3 +142,11 @@ def test_complex_create_rejects(change, status):
     with pytest.raises(aar.AarError) as ei:
         aar.aar_create_complex(aar.make_problem(prob), aar.make_params(prm), -0.07)
     assert ei.value.status == status
+
+
+def test_select_parameters_rejects_bad_candidates():
+    prob = inputs.dirichlet_poisson_problem(8)
+    for betas, ps, trial in (([], [2], 10), ([0.6], [0], 10), ([0.6], [2], 0), ([float("nan")], [2], 10)):
+        with pytest.raises(aar.AarError) as ei:
+            aar.aar_select_parameters(aar.make_problem(prob), aar.make_params(inputs.Params()), 1, betas, ps, trial)
+        assert ei.value.status == aar.AAR_ERR_INVALID_ARG
