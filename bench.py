@@ -306,17 +306,22 @@ def fused_gram_used(n, m, radius=6):
 
 
 def run_modes(w, key, modes, steps, warmup, n=None):
-    """Solve the workload's system in each mode; returns {mode: record} plus
-    the FP64 solve's seconds per solve (when FP64 is among the modes)."""
+    """Solve the workload's system in each mode (a precision, or a pair
+    (precision, flags) recorded as "<mode>_recycle" for the carried history);
+    returns {mode: record}, with the speedup over FP64 when FP64 is among the
+    modes."""
     import torch
     from paper_1606_08740_amd import aar, inputs
     prob, b = w.problems[0], w.b[0]
     bt = torch.as_tensor(b, device="cuda:0")
     out, t64 = {}, None
-    for prec in modes:
-        log(f"{w.name} {MODE_NAMES[prec]}")
+    for mode in modes:
+        prec, flags = mode if isinstance(mode, tuple) else (mode, 0)
+        name = MODE_NAMES[prec] + ("_recycle" if flags & aar.AAR_FLAG_RECYCLE_HISTORY else "")
+        log(f"{w.name} {name}")
         pm = inputs.Params(**{**w.params.__dict__})
         pm.precision = prec
+        pm.flags |= flags
         s = aar.Solver([prob], pm)
         dt, r, xt = timed_solves(s, bt, steps, warmup)
         s.close()
@@ -331,9 +336,9 @@ def run_modes(w, key, modes, steps, warmup, n=None):
             rec["effective_GBs"] = gbs
             rec["effective_frac_of_peak"] = gbs / HBM_PEAK_GBS
             rec["bytes_per_point_per_cycle"] = cb
-        if prec == FP64:
+        if prec == FP64 and not flags:
             t64 = per
-        out[MODE_NAMES[prec]] = rec
+        out[name] = rec
         del xt
     if t64 is not None:
         for name, rec in out.items():
@@ -493,6 +498,27 @@ def c1(args):
         r["oracle_iterations"] = (golden(key) or {}).get("iterations")
         out[label] = r
     out["note"] = "working set in L2 / Infinity Cache: launch latency, not HBM, bounds it; reported per iteration"
+    # beta / p chosen by timed trial solves, then the full solve with them
+    import torch
+    from paper_1606_08740_amd import aar
+    w = inputs.workload(1, tol=1e-10)
+    prob, b = w.problems[0], w.b[0]
+    bt = torch.as_tensor(b, device="cuda:0")
+    betas, ps = [0.3, 0.6, 1.0, 1.3], [2, 4, 6, 8]
+    log("c1 parameter selection")
+    t0 = time.perf_counter()
+    beta, p, scores = aar.aar_select_parameters(aar.make_problem(prob), aar.make_params(w.params), bt.data_ptr(),
+                                                 betas, ps, 96)
+    t_sel = time.perf_counter() - t0
+    pm = inputs.Params(**{**w.params.__dict__})
+    pm.beta, pm.p = beta, p
+    sv = aar.Solver([prob], pm)
+    dt, r, _ = timed_solves(sv, bt, steps, 3)
+    sv.close()
+    out["parameter_selection"] = {
+        "candidates": {"beta": betas, "p": ps}, "trial_iterations": 96, "selection_seconds": t_sel,
+        "chosen": {"beta": beta, "p": p}, "ms_per_solve": dt / steps * 1e3, "iterations": r["iterations"],
+        "status": r["status"], "speedup_vs_default": out["tol_1e-10"]["fp64"]["ms_per_solve"] / (dt / steps * 1e3)}
     return out
 
 
@@ -560,7 +586,10 @@ def main():
     out["roofline"]["frac_of_measured_copy"] = out["roofline"]["achieved"] / copy_gbs
 
     # ---- the headline grid in the other modes ----
-    c3 = run_modes(w, f"periodic_poisson_r6_{args.n}", [MIXED, MIXED_BF16, FP64_FP32HIST], steps, warm, n=args.n)
+    from paper_1606_08740_amd import aar
+    rec_flag = aar.AAR_FLAG_RECYCLE_HISTORY
+    c3 = run_modes(w, f"periodic_poisson_r6_{args.n}", [MIXED, (MIXED, rec_flag), MIXED_BF16, FP64_FP32HIST], steps,
+                   warm, n=args.n)
     t64 = h["dt"] / args.steps
     for rec in c3.values():
         rec["speedup_vs_fp64"] = t64 / (rec["ms_per_solve"] * 1e-3)
@@ -572,11 +601,12 @@ def main():
     # ---- the other evaluation workloads ----
     if args.n != 192:
         w2 = inputs.workload(2)
-        out["c2_192"] = run_modes(w2, "periodic_poisson_r6_192", [FP64, MIXED, FP64_FP32HIST], steps, warm, n=192)
+        out["c2_192"] = run_modes(w2, "periodic_poisson_r6_192", [FP64, MIXED, (MIXED, rec_flag), FP64_FP32HIST],
+                                  steps, warm, n=192)
         del w2
     w4 = inputs.workload(4, precision=FP64)
-    out["c4_128"] = run_modes(w4, "convection_diffusion_upwind_128", [FP64, MIXED, FP64_FP32HIST], steps, warm,
-                              n=128)
+    out["c4_128"] = run_modes(w4, "convection_diffusion_upwind_128", [FP64, MIXED, (MIXED, rec_flag), FP64_FP32HIST],
+                              steps, warm, n=128)
     del w4
     out["c1_32"] = c1(args)
     out["batched"] = run_batched(args)
