@@ -43,15 +43,20 @@ def workloads():
 
 def candidates(prob, f64):
     """Tile shapes tried for one grid: one-point tiles (rows {1, 2, 4} x z
-    depths, with temporal blocks of 2, 3 or 5 steps where the radius allows),
+    depths, along x or (small grids) along z first, and with temporal blocks
+    of 2, 3 or 5 steps where the radius allows),
     and paired tiles of 4 and 8 waves (16 too in FP32) with both z orders."""
     n = prob.n
     out = []
-    depths = [4, 8, 16, 32] if n[2] <= 64 else [16, 28, 32, 64]
+    small = n[2] <= 64
+    depths = [2, 4, 8, 16, 32] if small else [16, 28, 32, 64]
     for ry in (1, 2, 4):
         for cz in depths:
-            out.append((ry, cz, 0, 0, 0))
-            if prob.radius <= 2:
+            # small grids: also tiles numbered along z first (more z chunks
+            # per XCD), which matter when the launches are latency-bound
+            for order in ((0, 2) if small else (0,)):
+                out.append((ry, cz, order, 0, 0))
+            if prob.radius <= 2 and cz >= 4:
                 for tb in (2, 3, 5):
                     out.append((ry, cz, 0, 0, tb))
     if n[0] % 2 == 0 and prob.velocity is None:
