@@ -246,6 +246,88 @@ __device__ inline void jacobi_pinv(int l, double rcond, double thresh_order, dou
     __syncthreads();
 }
 
+// Cholesky solve of the symmetric l x l matrix S (LDS) when it provably
+// equals the pseudoinverse solve: S = L L^T succeeds and every eigenvalue
+// exceeds rcond * thresh_order * lambda_max, shown by lambda_min >=
+// 1 / ||L^-1||_F^2 and lambda_max <= trace_scale * trace(S) (trace_scale 1 for
+// a real matrix; 1/2 for the real form of a Hermitian one, whose eigenvalues
+// come in pairs).  One wave; V receives L, Li its inverse; gamma goes to gam.
+// Returns whether the solve was taken.
+__device__ inline bool cholesky_proved_solve(int l, double rcond, double thresh_order, double trace_scale,
+                                             double (*S)[kMaxM + 1], double (*V)[kMaxM + 1],
+                                             double (*Li)[kMaxM + 1], const double *cvec, double *wvec,
+                                             double *gam, int &sh_fail)
+{
+    const int tid = threadIdx.x;
+    bool fast = false;
+    for (int i = tid; i < l * l; i += kLsqThreads)
+        V[i / l][i % l] = S[i / l][i % l];
+    if (tid == 0)
+        sh_fail = 0;
+    __syncthreads();
+    for (int j = 0; j < l; ++j) {
+        if (tid == 0) {
+            const double piv = V[j][j];
+            if (!(piv > 0.0))
+                sh_fail = 1;
+            else
+                V[j][j] = sqrt(piv);
+        }
+        __syncthreads();
+        if (sh_fail)
+            break;
+        for (int i = j + 1 + tid; i < l; i += kLsqThreads)
+            V[i][j] /= V[j][j];
+        __syncthreads();
+        const int w = l - j - 1;   // trailing block (j+1 .. l-1)^2, lower part
+        for (int idx = tid; idx < w * w; idx += kLsqThreads) {
+            const int i = j + 1 + idx / w, kk = j + 1 + idx % w;
+            if (kk <= i)
+                V[i][kk] -= V[i][j] * V[kk][j];
+        }
+        __syncthreads();
+    }
+    if (!sh_fail) {
+        // columns of L^-1, one lane per column
+        for (int c = tid; c < l; c += kLsqThreads) {
+            for (int i = 0; i < c; ++i)
+                Li[i][c] = 0.0;
+            for (int i = c; i < l; ++i) {
+                double acc = i == c ? 1.0 : 0.0;
+                for (int kk = c; kk < i; ++kk)
+                    acc -= V[i][kk] * Li[kk][c];
+                Li[i][c] = acc / V[i][i];
+            }
+        }
+        __syncthreads();
+        double fro = 0.0, tr = 0.0;
+        for (int i = tid; i < l * l; i += kLsqThreads)
+            fro += Li[i / l][i % l] * Li[i / l][i % l];
+        for (int i = tid; i < l; i += kLsqThreads)
+            tr += S[i][i];
+        fro = __shfl(wave_sum_a(fro), 0, 64);
+        tr = __shfl(wave_sum_a(tr), 0, 64);
+        fast = (1.0 / fro > rcond * thresh_order * (tr * trace_scale)) && fro == fro;
+        if (fast) {
+            for (int i = tid; i < l; i += kLsqThreads) {   // y = L^-1 c
+                double y = 0.0;
+                for (int kk = 0; kk <= i; ++kk)
+                    y += Li[i][kk] * cvec[kk];
+                wvec[i] = y;
+            }
+            __syncthreads();
+            for (int i = tid; i < l; i += kLsqThreads) {   // gamma = L^-T y
+                double g = 0.0;
+                for (int kk = i; kk < l; ++kk)
+                    g += Li[kk][i] * wvec[kk];
+                gam[i] = g;
+            }
+            __syncthreads();
+        }
+    }
+    return fast;
+}
+
 // The least-squares step of one system: convergence test, gamma and the
 // update plan.  rho2 = ||b - A x_k||^2 and gram_vals (the m(m+1)/2 entries of
 // the upper triangle of F^T F, then F^T f_k) are already summed.  Run by one
@@ -504,71 +586,7 @@ __device__ inline void lsq_core(const LsqArgs &a, InstState *st, double rho2, co
             __syncthreads();
         }
     } else if (l > 0 && !a.force_pinv) {
-        for (int i = tid; i < l * l; i += kLsqThreads)
-            V[i / l][i % l] = S[i / l][i % l];
-        if (tid == 0)
-            sh_fail = 0;
-        __syncthreads();
-        for (int j = 0; j < l; ++j) {
-            if (tid == 0) {
-                const double piv = V[j][j];
-                if (!(piv > 0.0))
-                    sh_fail = 1;
-                else
-                    V[j][j] = sqrt(piv);
-            }
-            __syncthreads();
-            if (sh_fail)
-                break;
-            for (int i = j + 1 + tid; i < l; i += kLsqThreads)
-                V[i][j] /= V[j][j];
-            __syncthreads();
-            const int w = l - j - 1;   // trailing block (j+1 .. l-1)^2, lower part
-            for (int idx = tid; idx < w * w; idx += kLsqThreads) {
-                const int i = j + 1 + idx / w, kk = j + 1 + idx % w;
-                if (kk <= i)
-                    V[i][kk] -= V[i][j] * V[kk][j];
-            }
-            __syncthreads();
-        }
-        if (!sh_fail) {
-            // columns of L^-1, one lane per column
-            for (int c = tid; c < l; c += kLsqThreads) {
-                for (int i = 0; i < c; ++i)
-                    Li[i][c] = 0.0;
-                for (int i = c; i < l; ++i) {
-                    double acc = i == c ? 1.0 : 0.0;
-                    for (int kk = c; kk < i; ++kk)
-                        acc -= V[i][kk] * Li[kk][c];
-                    Li[i][c] = acc / V[i][i];
-                }
-            }
-            __syncthreads();
-            double fro = 0.0, tr = 0.0;
-            for (int i = tid; i < l * l; i += kLsqThreads)
-                fro += Li[i / l][i % l] * Li[i / l][i % l];
-            for (int i = tid; i < l; i += kLsqThreads)
-                tr += S[i][i];
-            fro = __shfl(wave_sum_a(fro), 0, 64);
-            tr = __shfl(wave_sum_a(tr), 0, 64);
-            fast = (1.0 / fro > a.rcond * (double)l * tr) && fro == fro;
-            if (fast) {
-                for (int i = tid; i < l; i += kLsqThreads) {   // y = L^-1 c
-                    double y = 0.0;
-                    for (int kk = 0; kk <= i; ++kk)
-                        y += Li[i][kk] * cvec[kk];
-                    wvec[i] = y;
-                }
-                __syncthreads();
-                for (int i = tid; i < l; i += kLsqThreads) {   // gamma = L^-T y
-                    double g = 0.0;
-                    for (int kk = i; kk < l; ++kk)
-                        g += Li[kk][i] * wvec[kk];
-                    gam[i] = g;
-                }
-                __syncthreads();
-            }
-        }
+        fast = cholesky_proved_solve(l, a.rcond, (double)l, 1.0, S, V, Li, cvec, wvec, gam, sh_fail);
     }
 
     if (!fast)

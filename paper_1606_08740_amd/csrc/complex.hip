@@ -181,8 +181,9 @@ __global__ __launch_bounds__(kLsqThreads) void k_clsq(const LsqArgs a, double om
     __shared__ double cvec[kMaxM], wvec[kMaxM], gam[kMaxM];
     __shared__ double rot_c[kMaxM / 2], rot_s[kMaxM / 2];
     __shared__ int pair_p[kMaxM / 2], pair_q[kMaxM / 2];
+    __shared__ double Li[kMaxM][kMaxM + 1];
     __shared__ double sh_off;
-    __shared__ int sh_stop;
+    __shared__ int sh_stop, sh_fail;
     InstState *st = a.state;
     const int tid = threadIdx.x;
     double r = 0.0;
@@ -241,7 +242,13 @@ __global__ __launch_bounds__(kLsqThreads) void k_clsq(const LsqArgs a, double om
         return;
     }
     __syncthreads();
-    if (l > 0)
+    // the Cholesky solve of the real form when it provably equals the
+    // pseudoinverse (its eigenvalues are those of G, each twice), else the
+    // Jacobi eigendecomposition
+    bool fast = false;
+    if (l > 0 && !a.force_pinv)
+        fast = cholesky_proved_solve(2 * l, a.rcond, (double)l, 0.5, S, V, Li, cvec, wvec, gam, sh_fail);
+    if (l > 0 && !fast)
         jacobi_pinv(2 * l, a.rcond, (double)l, S, V, cvec, wvec, gam, rot_c, rot_s, pair_p, pair_q, sh_off,
                     sh_stop);
     // gamma_t = gam[t] + i gam[t + l]; lane t writes history position t
@@ -271,9 +278,12 @@ __global__ __launch_bounds__(kLsqThreads) void k_clsq(const LsqArgs a, double om
         st->fslot[t] = (slot0 + t) % a.nslots;
     }
     if (tid == 0) {
-        int kept = 0;
-        for (int e = 0; e < 2 * l; ++e)
-            kept += S[e][e] > sh_off;
+        int kept = 2 * l;
+        if (!fast) {
+            kept = 0;
+            for (int e = 0; e < 2 * l; ++e)
+                kept += S[e][e] > sh_off;
+        }
         st->rank = kept / 2;
         if (a.rank_log && log_count0 < a.log_cap)
             a.rank_log[log_count0] = kept / 2;

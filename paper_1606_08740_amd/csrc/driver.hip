@@ -756,6 +756,7 @@ hipError_t enqueue_cycle_complex(aar_solver_t *S, const Path<zd> &P, hipStream_t
     l.log = S->log;
     l.rank_log = S->rank_log;
     l.log_cap = S->log_cap;
+    l.force_pinv = (pa.flags & AAR_FLAG_FORCE_PINV) ? 1 : 0;
     if ((e = launch_clsq(l, S->omega_im, S->beta_im, s)) != hipSuccess)
         return e;
     UpdateArgs<zd> u;

@@ -75,14 +75,18 @@ ITER_CASES = [
 ]
 
 
+@pytest.mark.parametrize("force", [0, aar.AAR_FLAG_FORCE_PINV], ids=["auto", "forced_pinv"])
 @pytest.mark.parametrize("name,make,kw,omega,beta", ITER_CASES, ids=[c[0] for c in ITER_CASES])
-def test_complex_iterates_match_oracle(name, make, kw, omega, beta):
+def test_complex_iterates_match_oracle(name, make, kw, omega, beta, force):
+    """Both branches of the m x m solve: the Cholesky solve of the real form
+    (taken when a bound proves it equals the pseudoinverse) and, forced, the
+    Jacobi eigendecomposition."""
     prob, s_im = make()
     b = cnormal(5, prob.size)
     p = kw["p"]
     for K in sorted({1, max(p - 1, 1), p, p + 1, 3 * p + 2}):
-        say(f"complex iterates {name} K={K}")
-        x, res, _, _ = csolve(prob, params(max_iter=K, tol=1e-30, **kw), s_im, b, omega, beta)
+        say(f"complex iterates {name} K={K} force={force}")
+        x, res, _, _ = csolve(prob, params(max_iter=K, tol=1e-30, flags=force, **kw), s_im, b, omega, beta)
         ref = oracle.aar_solve_complex(prob, b, s_im, omega=omega, beta=beta, m=kw["m"], p=p, tol=1e-30,
                                        max_iter=K)
         assert res["status"] == aar.AAR_NOT_CONVERGED and res["iterations"] == K, res
