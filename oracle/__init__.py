@@ -55,6 +55,11 @@ class _Problem(ctypes.Structure):
                 ("shift", ctypes.c_double), ("velocity", ctypes.c_void_p)]
 
 
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("val", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -93,6 +98,22 @@ def _load_from(path: str):
                                              ctypes.c_double, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), dp,
                                              dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     lib.oracle_aar_solve_complex.restype = ctypes.c_int
+    cp = ctypes.POINTER(_Csr)
+    lib.oracle_csr_check.argtypes = [cp]
+    lib.oracle_csr_check.restype = ctypes.c_int
+    lib.oracle_csr_apply.argtypes = [cp, dp, dp]
+    lib.oracle_ilu0.argtypes = [cp, ctypes.c_int, dp]
+    lib.oracle_ilu0.restype = ctypes.c_int
+    lib.oracle_ilu0_solve.argtypes = [cp, ctypes.c_int, dp, dp, dp]
+    lib.oracle_csr_precondition.argtypes = [cp, ctypes.c_int, ctypes.c_int, dp, dp]
+    lib.oracle_csr_precondition.restype = ctypes.c_int
+    lib.oracle_aar_solve_csr.argtypes = [cp, ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_int64), dp, dp, ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_int64)]
+    lib.oracle_aar_solve_csr.restype = ctypes.c_int
+    lib.oracle_relative_residual_csr.argtypes = [cp, dp, dp]
+    lib.oracle_relative_residual_csr.restype = ctypes.c_double
     _lib = lib
 
 
@@ -259,6 +280,115 @@ def relative_residual(prob, b, x) -> float:
     return float(_load().oracle_relative_residual(bd.ref, _ptr(_f64(b)), _ptr(_f64(x))))
 
 
+# ---- general sparse A (Sec. 3.1; block-Jacobi ILU(0), Secs. 3.2-3.3) ----
+
+PRECOND_JACOBI, PRECOND_ILU0 = 0, 1
+
+
+class _BoundCsr:
+    """A ctypes CSR struct plus the arrays it points into (kept alive).
+    `A` is any object with rowptr, col, val arrays (n = len(rowptr) - 1)."""
+
+    def __init__(self, A):
+        self.rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(A.col, dtype=np.int32)
+        self.val = _f64(A.val)
+        s = _Csr()
+        s.n = len(self.rowptr) - 1
+        s.rowptr = self.rowptr.ctypes.data
+        s.col = self.col.ctypes.data
+        s.val = self.val.ctypes.data
+        self.s = s
+        self.n = int(s.n)
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+
+def csr_check(A) -> bool:
+    """True when A's arrays form a valid CSR matrix (sorted columns in range,
+    diagonal present in every row)."""
+    return _load().oracle_csr_check(_BoundCsr(A).ref) == OK
+
+
+def csr_apply(A, x) -> np.ndarray:
+    """y = A x for a CSR matrix."""
+    bd = _BoundCsr(A)
+    x = _f64(x)
+    y = np.empty(bd.n)
+    _load().oracle_csr_apply(bd.ref, _ptr(x), _ptr(y))
+    return y
+
+
+def ilu0(A, nblocks: int = 1) -> np.ndarray:
+    """ILU(0) factors of each of the `nblocks` contiguous diagonal blocks of A
+    (block Jacobi with ILU(0) per block; nblocks = 1 is ILU(0) of A), stored in
+    A's pattern: strictly lower entries hold L (unit diagonal not stored), the
+    others U.  Entries that couple two blocks keep A's values and are unused.
+    Raises ZeroDivisionError on a zero or non-finite pivot."""
+    bd = _BoundCsr(A)
+    lu = np.empty(len(bd.val))
+    st = _load().oracle_ilu0(bd.ref, int(nblocks), _ptr(lu))
+    if st == BREAKDOWN:
+        raise ZeroDivisionError("ILU(0) met a zero or non-finite pivot")
+    if st != OK:
+        raise ValueError("bad matrix or block count")
+    return lu
+
+
+def ilu0_solve(A, lu, r, nblocks: int = 1) -> np.ndarray:
+    """z = (L U)^-1 r block by block for factors from ilu0()."""
+    bd = _BoundCsr(A)
+    lu = _f64(lu)
+    r = _f64(r)
+    z = np.empty(bd.n)
+    _load().oracle_ilu0_solve(bd.ref, int(nblocks), _ptr(lu), _ptr(r), _ptr(z))
+    return z
+
+
+def precondition(A, r, precond: int = PRECOND_ILU0, nblocks: int = 1) -> np.ndarray:
+    """z = M^-1 r for the Jacobi diagonal or block ILU(0) of A."""
+    bd = _BoundCsr(A)
+    r = _f64(r)
+    z = np.empty(bd.n)
+    st = _load().oracle_csr_precondition(bd.ref, int(precond), int(nblocks), _ptr(r), _ptr(z))
+    if st == BREAKDOWN:
+        raise ZeroDivisionError("ILU(0) met a zero or non-finite pivot")
+    if st != OK:
+        raise ValueError("bad matrix, preconditioner or block count")
+    return z
+
+
+def aar_solve_csr(A, b, x0=None, precond: int = PRECOND_ILU0, nblocks: int = 1, omega=0.6, beta=0.6, m=9, p=8,
+                  tol=1e-6, max_iter=1_000_000, trace_cap: int = 0) -> dict:
+    """Preconditioned AAR (Eqs. 2-6) for a CSR matrix with the Jacobi or
+    block ILU(0) preconditioner; the paper's defaults for its sparse study
+    (Sec. 3.1) are omega = beta = 0.6, m = 9, p = 8, tol 1e-6.  Returns the
+    same dict as aar_solve."""
+    bd = _BoundCsr(A)
+    b = _f64(b)
+    x = np.zeros(bd.n) if x0 is None else _f64(x0).copy()
+    it = ctypes.c_int64(0)
+    rr = ctypes.c_double(0.0)
+    tl = ctypes.c_int64(0)
+    tr = np.zeros((max(trace_cap, 1), 6))
+    st = _load().oracle_aar_solve_csr(bd.ref, int(precond), int(nblocks), _ptr(b), _ptr(x), float(omega),
+                                      float(beta), int(m), int(p), float(tol), int(max_iter), ctypes.byref(it),
+                                      ctypes.byref(rr), _ptr(tr) if trace_cap > 0 else None, int(trace_cap),
+                                      ctypes.byref(tl))
+    out = {"x": x, "status": st, "iterations": it.value, "relres": rr.value}
+    if trace_cap > 0:
+        out["trace"] = tr[: tl.value].copy()
+    return out
+
+
+def relative_residual_csr(A, b, x) -> float:
+    """||b - A x|| / ||b|| for a CSR matrix."""
+    bd = _BoundCsr(A)
+    return float(_load().oracle_relative_residual_csr(bd.ref, _ptr(_f64(b)), _ptr(_f64(x))))
+
+
 def threads() -> int:
     """OpenMP threads the oracle runs with."""
     return int(_load().oracle_threads())
@@ -271,6 +401,7 @@ def solve_workload_params(params) -> dict:
 
 
 __all__ = ["build", "fd_weights", "apply", "diagonal", "jacobi_eigen", "pinv_solve", "aar_solve",
-           "relative_residual", "threads", "solve_workload_params",
+           "relative_residual", "threads", "solve_workload_params", "csr_check", "csr_apply", "ilu0",
+           "ilu0_solve", "precondition", "aar_solve_csr", "relative_residual_csr", "PRECOND_JACOBI", "PRECOND_ILU0",
            "OK", "NOT_CONVERGED", "BREAKDOWN", "BAD_ARG"]
 

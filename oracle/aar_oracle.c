@@ -361,12 +361,19 @@ static double dot(int64_t N, const double *a, const double *b)
  * Returns ORACLE_OK, ORACLE_NOT_CONVERGED, ORACLE_BREAKDOWN (NaN/Inf residual)
  * or ORACLE_BAD_ARG.
  */
-int oracle_aar_solve(const oracle_problem *P, const double *b, double *x,
-                     double omega, double beta, int m, int p, double tol, int64_t max_iter,
-                     int64_t *iters_out, double *relres_out,
-                     double *trace, int64_t trace_cap, int64_t *trace_len)
+/* The residual step of one iteration for whichever operator and
+ * preconditioner the caller holds: res = b - A x_k and f_k = M^{-1} res
+ * (Eq. 6). */
+typedef void (*residual_step)(void *ctx, const double *x, double *res, double *f);
+
+/* The AAR iteration itself (Eqs. 2-5, Sec. 2) over vectors of length N, with
+ * the residual step supplied by the caller; arguments and return values as
+ * described above. */
+static int aar_iterate(int64_t N, residual_step step, void *ctx, const double *b, double *x,
+                       double omega, double beta, int m, int p, double tol, int64_t max_iter,
+                       int64_t *iters_out, double *relres_out,
+                       double *trace, int64_t trace_cap, int64_t *trace_len)
 {
-    const int64_t N = problem_size(P);
     if (N <= 0 || m < 1 || p < 1 || !(tol > 0.0) || max_iter < 1)
         return ORACLE_BAD_ARG;
     if (trace_len)
@@ -380,7 +387,6 @@ int oracle_aar_solve(const oracle_problem *P, const double *b, double *x,
         return ORACLE_OK;
     }
 
-    double *D = malloc(sizeof(double) * N);
     double *res = malloc(sizeof(double) * N);
     double *f = malloc(sizeof(double) * N);
     double *x_prev = malloc(sizeof(double) * N);
@@ -395,16 +401,9 @@ int oracle_aar_solve(const oracle_problem *P, const double *b, double *x,
     int status = ORACLE_NOT_CONVERGED;
     double r = 0.0;
 
-    oracle_diagonal(P, D);
-
     for (int64_t k = 0;; ++k) {
-        /* residual and preconditioned residual f_k = D^{-1}(b - A x_k)  (Eq. 6) */
-        oracle_apply(P, x, res);
-#pragma omp parallel for schedule(static)
-        for (int64_t i = 0; i < N; ++i) {
-            res[i] = b[i] - res[i];
-            f[i] = res[i] / D[i];
-        }
+        /* residual and preconditioned residual f_k = M^{-1}(b - A x_k)  (Eq. 6) */
+        step(ctx, x, res, f);
 
         /* history push: x_k - x_{k-1} and f_k - f_{k-1}  (Eqs. 4-5) */
         if (k >= 1) {
@@ -500,7 +499,6 @@ int oracle_aar_solve(const oracle_problem *P, const double *b, double *x,
     }
     *relres_out = r;
 
-    free(D);
     free(res);
     free(f);
     free(x_prev);
@@ -512,6 +510,43 @@ int oracle_aar_solve(const oracle_problem *P, const double *b, double *x,
     free(c);
     free(gamma);
     return status;
+}
+
+/* Residual step of the stencil operator with the Jacobi preconditioner
+ * M = D = diag(A): f_k = D^{-1}(b - A x_k). */
+typedef struct {
+    const oracle_problem *P;
+    const double *b;
+    const double *D;
+} stencil_ctx;
+
+static void stencil_residual(void *c, const double *x, double *res, double *f)
+{
+    const stencil_ctx *S = (const stencil_ctx *)c;
+    const int64_t N = problem_size(S->P);
+    oracle_apply(S->P, x, res);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        res[i] = S->b[i] - res[i];
+        f[i] = res[i] / S->D[i];
+    }
+}
+
+int oracle_aar_solve(const oracle_problem *P, const double *b, double *x,
+                     double omega, double beta, int m, int p, double tol, int64_t max_iter,
+                     int64_t *iters_out, double *relres_out,
+                     double *trace, int64_t trace_cap, int64_t *trace_len)
+{
+    const int64_t N = problem_size(P);
+    if (N <= 0)
+        return ORACLE_BAD_ARG;
+    double *D = malloc(sizeof(double) * N);
+    oracle_diagonal(P, D);
+    stencil_ctx c = {P, b, D};
+    int st = aar_iterate(N, stencil_residual, &c, b, x, omega, beta, m, p, tol, max_iter, iters_out, relres_out,
+                         trace, trace_cap, trace_len);
+    free(D);
+    return st;
 }
 
 /* ||b - A x|| / ||b|| in FP64 (used to check any solver's final answer). */
@@ -806,4 +841,245 @@ int oracle_aar_solve_complex(const oracle_problem *P, double shift_im, const dou
     free(gamma);
     free(order);
     return status;
+}
+
+/* ------------------------------------------------------------------------
+ * General sparse A (Sec. 3.1: nonsymmetric systems with Jacobi and ILU(0)
+ * preconditioning; Secs. 3.2-3.3: block-Jacobi with ILU(0) on each block,
+ * the parallel preconditioner of the Helmholtz and Poisson runs).
+ *
+ * A is held in compressed sparse rows: the entries of row i are
+ * val[rowptr[i] .. rowptr[i+1]-1] in columns col[...], strictly increasing,
+ * the diagonal present.  Block Jacobi splits the rows into `nblocks`
+ * contiguous ranges, block t holding rows floor(t n / nblocks) ..
+ * floor((t+1) n / nblocks) - 1; its preconditioner M is block diagonal with
+ * the ILU(0) factors of each diagonal block of A, and entries of A that
+ * couple two blocks do not enter M.  nblocks = 1 is ILU(0) of A itself.
+ *
+ * ILU(0): L unit lower triangular and U upper triangular, both with the
+ * sparsity pattern of (the block of) A, such that (L U)_ij = a_ij wherever a_ij
+ * is in the pattern.  They come from Gaussian elimination in row order that
+ * drops every fill-in outside the pattern: for row i and each k < i of its
+ * pattern in increasing order, l_ik = a_ik / u_kk, then a_ij -= l_ik u_kj for
+ * each j > k with both (i, j) and (k, j) in the pattern.  L and U overwrite a
+ * copy of A's values (the unit diagonal of L is not stored).
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t n;
+    const int64_t *rowptr;  /* n + 1 */
+    const int32_t *col;
+    const double *val;
+} oracle_csr;
+
+enum { ORACLE_PRECOND_JACOBI = 0, ORACLE_PRECOND_ILU0 = 1 };
+
+static int64_t block_first_row(int64_t n, int nblocks, int64_t t)
+{
+    return t * n / nblocks;
+}
+
+/* Position of the diagonal entry of row i, or -1. */
+static int64_t diag_pos(const oracle_csr *A, int64_t i)
+{
+    for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; ++e)
+        if (A->col[e] == i)
+            return e;
+    return -1;
+}
+
+/* ORACLE_OK when the arrays describe a valid matrix as above. */
+int oracle_csr_check(const oracle_csr *A)
+{
+    if (A->n < 1 || A->rowptr[0] != 0)
+        return ORACLE_BAD_ARG;
+    for (int64_t i = 0; i < A->n; ++i) {
+        if (A->rowptr[i + 1] < A->rowptr[i])
+            return ORACLE_BAD_ARG;
+        for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; ++e) {
+            if (A->col[e] < 0 || A->col[e] >= A->n)
+                return ORACLE_BAD_ARG;
+            if (e > A->rowptr[i] && A->col[e] <= A->col[e - 1])
+                return ORACLE_BAD_ARG;
+        }
+        if (diag_pos(A, i) < 0)
+            return ORACLE_BAD_ARG;
+    }
+    return ORACLE_OK;
+}
+
+/* y = A x, each row summed in stored order. */
+void oracle_csr_apply(const oracle_csr *A, const double *x, double *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < A->n; ++i) {
+        double s = 0.0;
+        for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; ++e)
+            s += A->val[e] * x[A->col[e]];
+        y[i] = s;
+    }
+}
+
+/* ILU(0) factors of each diagonal block into lu (a copy of A's values on
+ * entry is not needed: lu is written whole).  Entries of lu outside their
+ * row's block keep A's values and are never used.  Returns ORACLE_BREAKDOWN
+ * when a pivot u_kk is zero or not finite. */
+int oracle_ilu0(const oracle_csr *A, int nblocks, double *lu)
+{
+    const int64_t n = A->n;
+    if (nblocks < 1 || nblocks > n)
+        return ORACLE_BAD_ARG;
+    memcpy(lu, A->val, sizeof(double) * (size_t)A->rowptr[n]);
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic) reduction(| : bad)
+    for (int t = 0; t < nblocks; ++t) {
+        const int64_t lo = block_first_row(n, nblocks, t), hi = block_first_row(n, nblocks, t + 1);
+        for (int64_t i = lo; i < hi; ++i) {
+            const int64_t end = A->rowptr[i + 1];
+            for (int64_t e = A->rowptr[i]; e < end && A->col[e] < i; ++e) {
+                const int64_t k = A->col[e];
+                if (k < lo)
+                    continue;                    /* couples two blocks: not in M */
+                const double lik = lu[e] / lu[diag_pos(A, k)];
+                lu[e] = lik;
+                for (int64_t e2 = e + 1; e2 < end; ++e2) {
+                    const int64_t j = A->col[e2];
+                    if (j >= hi)
+                        break;                   /* later columns lie outside the block */
+                    /* u_kj, if (k, j) is in the pattern */
+                    for (int64_t ek = A->rowptr[k]; ek < A->rowptr[k + 1]; ++ek)
+                        if (A->col[ek] == j) {
+                            lu[e2] -= lik * lu[ek];
+                            break;
+                        }
+                }
+            }
+            const double u = lu[diag_pos(A, i)];
+            if (u == 0.0 || !isfinite(u))
+                bad = 1;
+        }
+    }
+    return bad ? ORACLE_BREAKDOWN : ORACLE_OK;
+}
+
+/* z = M^{-1} r for the block ILU(0) factors in lu: L y = r by forward
+ * substitution, then U z = y by backward substitution, within each block. */
+void oracle_ilu0_solve(const oracle_csr *A, int nblocks, const double *lu, const double *r, double *z)
+{
+    const int64_t n = A->n;
+#pragma omp parallel for schedule(dynamic)
+    for (int t = 0; t < nblocks; ++t) {
+        const int64_t lo = block_first_row(n, nblocks, t), hi = block_first_row(n, nblocks, t + 1);
+        for (int64_t i = lo; i < hi; ++i) {
+            double y = r[i];
+            for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1] && A->col[e] < i; ++e)
+                if (A->col[e] >= lo)
+                    y -= lu[e] * z[A->col[e]];
+            z[i] = y;
+        }
+        for (int64_t i = hi - 1; i >= lo; --i) {
+            const int64_t d = diag_pos(A, i);
+            double v = z[i];
+            for (int64_t e = d + 1; e < A->rowptr[i + 1] && A->col[e] < hi; ++e)
+                v -= lu[e] * z[A->col[e]];
+            z[i] = v / lu[d];
+        }
+    }
+}
+
+typedef struct {
+    const oracle_csr *A;
+    const double *b;
+    int precond;
+    int nblocks;
+    const double *lu;    /* ILU(0) factors, or NULL for Jacobi */
+} csr_ctx;
+
+/* Residual step of a sparse A: res = b - A x, f = M^{-1} res with M the
+ * Jacobi diagonal or the block ILU(0) factors. */
+static void csr_residual(void *c, const double *x, double *res, double *f)
+{
+    const csr_ctx *C = (const csr_ctx *)c;
+    const oracle_csr *A = C->A;
+    oracle_csr_apply(A, x, res);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < A->n; ++i)
+        res[i] = C->b[i] - res[i];
+    if (C->precond == ORACLE_PRECOND_JACOBI) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < A->n; ++i)
+            f[i] = res[i] / A->val[diag_pos(A, i)];
+    } else {
+        oracle_ilu0_solve(A, C->nblocks, C->lu, res, f);
+    }
+}
+
+/* z = M^{-1} r for the preconditioner `precond` (Jacobi, or block ILU(0)
+ * with nblocks blocks).  Returns ORACLE_BREAKDOWN when the factorization
+ * meets a zero pivot. */
+int oracle_csr_precondition(const oracle_csr *A, int precond, int nblocks, const double *r, double *z)
+{
+    if (oracle_csr_check(A) != ORACLE_OK)
+        return ORACLE_BAD_ARG;
+    if (precond == ORACLE_PRECOND_JACOBI) {
+        for (int64_t i = 0; i < A->n; ++i)
+            z[i] = r[i] / A->val[diag_pos(A, i)];
+        return ORACLE_OK;
+    }
+    if (precond != ORACLE_PRECOND_ILU0)
+        return ORACLE_BAD_ARG;
+    double *lu = malloc(sizeof(double) * (size_t)A->rowptr[A->n]);
+    int st = oracle_ilu0(A, nblocks, lu);
+    if (st == ORACLE_OK)
+        oracle_ilu0_solve(A, nblocks, lu, r, z);
+    free(lu);
+    return st;
+}
+
+/* Preconditioned AAR for a sparse A (Sec. 2 with M from Sec. 3.1 / 3.2):
+ * the same iteration, arguments and trace as oracle_aar_solve, with M the
+ * Jacobi diagonal (precond 0) or block ILU(0) with nblocks blocks
+ * (precond 1).  A zero ILU(0) pivot returns ORACLE_BREAKDOWN before any
+ * iteration. */
+int oracle_aar_solve_csr(const oracle_csr *A, int precond, int nblocks, const double *b, double *x,
+                         double omega, double beta, int m, int p, double tol, int64_t max_iter,
+                         int64_t *iters_out, double *relres_out,
+                         double *trace, int64_t trace_cap, int64_t *trace_len)
+{
+    if (oracle_csr_check(A) != ORACLE_OK)
+        return ORACLE_BAD_ARG;
+    if (precond != ORACLE_PRECOND_JACOBI && precond != ORACLE_PRECOND_ILU0)
+        return ORACLE_BAD_ARG;
+    if (precond == ORACLE_PRECOND_ILU0 && (nblocks < 1 || nblocks > A->n))
+        return ORACLE_BAD_ARG;
+    *iters_out = 0;
+    *relres_out = 0.0;
+    if (trace_len)
+        *trace_len = 0;
+    double *lu = NULL;
+    if (precond == ORACLE_PRECOND_ILU0) {
+        lu = malloc(sizeof(double) * (size_t)A->rowptr[A->n]);
+        int st = oracle_ilu0(A, nblocks, lu);
+        if (st != ORACLE_OK) {
+            free(lu);
+            return st;
+        }
+    }
+    csr_ctx c = {A, b, precond, nblocks, lu};
+    int st = aar_iterate(A->n, csr_residual, &c, b, x, omega, beta, m, p, tol, max_iter, iters_out, relres_out,
+                         trace, trace_cap, trace_len);
+    free(lu);
+    return st;
+}
+
+/* ||b - A x|| / ||b|| for a sparse A. */
+double oracle_relative_residual_csr(const oracle_csr *A, const double *b, const double *x)
+{
+    double *r = malloc(sizeof(double) * (size_t)A->n);
+    oracle_csr_apply(A, x, r);
+    for (int64_t i = 0; i < A->n; ++i)
+        r[i] = b[i] - r[i];
+    const double out = sqrt(dot(A->n, r, r)) / sqrt(dot(A->n, b, b));
+    free(r);
+    return out;
 }

@@ -306,6 +306,132 @@ def ofdft_helmholtz(n: int = 72, seed: int = 6, cells: int = 1, tol: float = 1e-
     return prob, OFDFT_Q.imag, b.astype(np.complex128), Params(omega=0.6, beta=0.6, m=7, p=6, tol=tol)
 
 
+# ---- general sparse matrices (stand-ins for the nonsymmetric Matrix Market
+# systems of Sec. 3.1, which are not available here) ----
+
+@dataclasses.dataclass
+class CsrMatrix:
+    """A square matrix in compressed sparse rows: row i holds
+    val[rowptr[i]:rowptr[i+1]] in columns col[...], strictly increasing,
+    with the diagonal present."""
+    rowptr: np.ndarray   # int64, n + 1
+    col: np.ndarray      # int32, nnz
+    val: np.ndarray      # float64, nnz
+
+    @property
+    def n(self) -> int:
+        return len(self.rowptr) - 1
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+    def to_dense(self) -> np.ndarray:
+        d = np.zeros((self.n, self.n))
+        rows = np.repeat(np.arange(self.n), np.diff(self.rowptr))
+        d[rows, self.col] = self.val
+        return d
+
+
+def _csr_from_bands(cols: np.ndarray, vals: np.ndarray, present: np.ndarray) -> CsrMatrix:
+    """Rows from k bands given in increasing column order: cols, vals and
+    present are (k, N) arrays; absent entries are dropped."""
+    present = present.T
+    counts = present.sum(axis=1)
+    rowptr = np.zeros(len(counts) + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    return CsrMatrix(rowptr, cols.T[present].astype(np.int32), vals.T[present].astype(np.float64))
+
+
+def reservoir_matrix(n: int = 16, seed: int = 7, log_sigma: float = 1.5, peclet: float = 0.5,
+                     storage: float = 1e-2) -> CsrMatrix:
+    """Single-phase flow through a heterogeneous medium on an n^3 grid (unit
+    cube, h = 1/n, no-flow boundaries), the structure of the oil-reservoir
+    matrices of the paper's sparse study: seven-point two-point-flux finite
+    volumes with permeability K = exp(log_sigma g), g ~ N(0,1) per cell,
+    face transmissibility 2 K_a K_b / (K_a + K_b) / h^2, first-order upwind
+    convection by a smooth random velocity (peak cell Peclet `peclet` for unit
+    permeability), and an accumulation term storage * mean(transmissibility)
+    on the diagonal.  Nonsymmetric; every row strictly diagonally dominant."""
+    N = n ** 3
+    h = 1.0 / n
+    K = np.exp(log_sigma * normal(seed, 1, N))
+    vel = convection_field(n, seed + 100, peclet=peclet)
+    idx = np.arange(N, dtype=np.int64)
+    ii, jj, kk = idx % n, (idx // n) % n, idx // (n * n)
+    coord = (ii, jj, kk)
+    strides = (1, n, n * n)
+    # bands in column order: -z, -y, -x, self, +x, +y, +z
+    order = [(2, -1), (1, -1), (0, -1), None, (0, 1), (1, 1), (2, 1)]
+    cols = np.zeros((7, N), dtype=np.int64)
+    vals = np.zeros((7, N))
+    present = np.zeros((7, N), dtype=bool)
+    diag = np.zeros(N)
+    tsum = 0.0
+    tcount = 0
+    for b, o in enumerate(order):
+        if o is None:
+            cols[b] = idx
+            present[b] = True
+            continue
+        ax, d = o
+        inside = (coord[ax] + d >= 0) & (coord[ax] + d < n)
+        nb = np.where(inside, idx + d * strides[ax], idx)
+        T = 2.0 * K * K[nb] / (K + K[nb]) / h ** 2
+        T = np.where(inside, T, 0.0)
+        cols[b] = nb
+        present[b] = inside
+        vals[b] -= T
+        diag += T
+        tsum += T.sum()
+        tcount += int(inside.sum())
+        # upwind: v > 0 takes the -axis neighbour, v < 0 the +axis one
+        v = vel[ax]
+        up = inside & ((v > 0) if d < 0 else (v < 0))
+        vals[b] -= np.where(up, np.abs(v) / h, 0.0)
+        diag += np.where(up, np.abs(v) / h, 0.0)
+    diag += storage * tsum / max(tcount, 1)
+    vals[3] = diag
+    return _csr_from_bands(cols, vals, present)
+
+
+def convection_matrix_2d(n: int = 64, peclet: float = 2.0) -> CsrMatrix:
+    """-Lap u + v . grad u on an n x n grid (unit square, zero Dirichlet,
+    h = 1/(n+1)) with centred differences for both terms and the rotating
+    field v = c (sin(pi x) cos(pi y), -cos(pi x) sin(pi y)), c chosen for a
+    peak cell Peclet number max |v_i| h / 2 = `peclet`.  Above Peclet 1 the off-diagonals change sign, so the matrix
+    is no M-matrix: a hard nonsymmetric case of the kind the paper's fluid
+    dynamics matrices are (Sec. 3.1)."""
+    N = n * n
+    h = 1.0 / (n + 1)
+    idx = np.arange(N, dtype=np.int64)
+    ii, jj = idx % n, idx // n
+    x, y = (ii + 1) * h, (jj + 1) * h
+    vx = np.sin(np.pi * x) * np.cos(np.pi * y)
+    vy = -np.cos(np.pi * x) * np.sin(np.pi * y)
+    scale = peclet * 2.0 / h / max(np.abs(vx).max(), np.abs(vy).max())
+    vx, vy = vx * scale, vy * scale
+    coord = (ii, jj)
+    strides = (1, n)
+    order = [(1, -1), (0, -1), None, (0, 1), (1, 1)]
+    cols = np.zeros((5, N), dtype=np.int64)
+    vals = np.zeros((5, N))
+    present = np.zeros((5, N), dtype=bool)
+    for b, o in enumerate(order):
+        if o is None:
+            cols[b] = idx
+            vals[b] = 4.0 / h ** 2
+            present[b] = True
+            continue
+        ax, d = o
+        inside = (coord[ax] + d >= 0) & (coord[ax] + d < n)
+        v = vx if ax == 0 else vy
+        cols[b] = np.where(inside, idx + d * strides[ax], idx)
+        vals[b] = -1.0 / h ** 2 + d * v / (2.0 * h)
+        present[b] = inside
+    return _csr_from_bands(cols, vals, present)
+
+
 def workload(index: int, **kw) -> Workload:
     """The five evaluation workloads, 1-based, at full size unless overridden."""
     if index == 1:

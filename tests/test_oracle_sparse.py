@@ -1,0 +1,250 @@
+"""Pins of the oracle's general sparse path (Sec. 3.1: nonsymmetric sparse
+systems with the Jacobi and ILU(0) preconditioners; Secs. 3.2-3.3: block
+Jacobi with ILU(0) per block).
+
+Each test checks the oracle against something other than itself: a dense or
+library product, the defining property of ILU(0), the exact LU of a library
+routine where ILU(0) has no fill to drop, the fill structure of ILU(0) on a
+five-point matrix, the Jacobi special case, the stencil oracle, GMRES on the
+preconditioned operator and a dense solve.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.sparse
+
+import oracle
+from paper_1606_08740_amd import inputs
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def csr_from_dense(D: np.ndarray) -> inputs.CsrMatrix:
+    """CSR of the nonzero pattern of D plus its whole diagonal."""
+    n = D.shape[0]
+    mask = (D != 0) | np.eye(n, dtype=bool)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(mask.sum(axis=1), out=rowptr[1:])
+    cols = np.nonzero(mask)[1].astype(np.int32)
+    return inputs.CsrMatrix(rowptr, cols, D[mask].astype(np.float64))
+
+
+def block_bounds(n, nblocks):
+    return [t * n // nblocks for t in range(nblocks + 1)]
+
+
+def factors(A: inputs.CsrMatrix, lu: np.ndarray, nblocks: int):
+    """Dense unit-lower L and upper U from the oracle's in-pattern factors,
+    keeping only entries inside each row's block."""
+    n = A.n
+    L, U = np.eye(n), np.zeros((n, n))
+    bb = block_bounds(n, nblocks)
+    for t in range(nblocks):
+        lo, hi = bb[t], bb[t + 1]
+        for i in range(lo, hi):
+            for e in range(A.rowptr[i], A.rowptr[i + 1]):
+                j = int(A.col[e])
+                if lo <= j < i:
+                    L[i, j] = lu[e]
+                elif i <= j < hi:
+                    U[i, j] = lu[e]
+    return L, U
+
+
+def in_block_pattern(A: inputs.CsrMatrix, nblocks: int) -> np.ndarray:
+    n = A.n
+    P = np.zeros((n, n), dtype=bool)
+    bb = block_bounds(n, nblocks)
+    for t in range(nblocks):
+        for i in range(bb[t], bb[t + 1]):
+            for e in range(A.rowptr[i], A.rowptr[i + 1]):
+                if bb[t] <= A.col[e] < bb[t + 1]:
+                    P[i, A.col[e]] = True
+    return P
+
+
+def test_csr_apply_matches_library_product():
+    A = inputs.reservoir_matrix(6, seed=3)
+    x = inputs.normal(3, 2, A.n)
+    ref = scipy.sparse.csr_matrix((A.val, A.col, A.rowptr), shape=(A.n, A.n)) @ x
+    np.testing.assert_allclose(oracle.csr_apply(A, x), ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("make,nblocks", [
+    (lambda: inputs.reservoir_matrix(6, seed=4), 1),
+    (lambda: inputs.reservoir_matrix(6, seed=4), 5),
+    (lambda: inputs.convection_matrix_2d(12, 2.0), 1),
+    (lambda: inputs.convection_matrix_2d(12, 2.0), 7),
+])
+def test_ilu0_reproduces_a_on_its_pattern(make, nblocks):
+    """ILU(0)'s defining property: (L U)_ij = a_ij wherever a_ij is in the
+    pattern of its block; L U is block diagonal."""
+    A = make()
+    lu = oracle.ilu0(A, nblocks)
+    L, U = factors(A, lu, nblocks)
+    M = L @ U
+    D = A.to_dense()
+    P = in_block_pattern(A, nblocks)
+    scale = np.abs(D).max()
+    np.testing.assert_allclose(M[P], D[P], rtol=0, atol=1e-12 * scale)
+    bb = block_bounds(A.n, nblocks)
+    for t in range(nblocks):
+        lo, hi = bb[t], bb[t + 1]
+        assert not M[lo:hi, :lo].any() and not M[lo:hi, hi:].any()
+
+
+def test_ilu0_of_a_full_pattern_is_the_exact_lu():
+    """Without entries to drop, ILU(0) is Gaussian elimination: the LU
+    factors of a library routine (no row exchange for a column diagonally
+    dominant matrix)."""
+    n = 9
+    D = inputs.normal(11, 1, n * n).reshape(n, n)
+    D += np.diag(np.abs(D).sum(axis=0) + 1.0)
+    A = csr_from_dense(D)
+    assert A.nnz == n * n
+    P, Lr, Ur = scipy.linalg.lu(D)
+    np.testing.assert_array_equal(P, np.eye(n))
+    L, U = factors(A, oracle.ilu0(A, 1), 1)
+    np.testing.assert_allclose(L, Lr, atol=1e-13)
+    np.testing.assert_allclose(U, Ur, rtol=1e-13, atol=1e-13 * np.abs(Ur).max())
+
+
+def test_ilu0_is_exact_on_a_tridiagonal_matrix():
+    """A tridiagonal matrix has no fill, so M = A and M^-1 A x = x."""
+    n = 40
+    rng = inputs.uniform(12, 1, 3 * n).reshape(3, n)
+    D = np.diag(4.0 + rng[0]) + np.diag(-1.0 - rng[1, 1:], -1) + np.diag(-0.5 - rng[2, 1:], 1)
+    A = csr_from_dense(D)
+    x = inputs.normal(12, 2, n)
+    z = oracle.precondition(A, D @ x, oracle.PRECOND_ILU0, 1)
+    np.testing.assert_allclose(z, x, rtol=1e-12, atol=1e-12)
+
+
+def test_ilu0_remainder_of_a_five_point_matrix_lies_on_the_fill_diagonals():
+    """For a five-point matrix in natural order the dropped fill, and with it
+    R = L U - A, lies only on the diagonals at offsets +-(n - 1)."""
+    n = 8
+    A = inputs.convection_matrix_2d(n, 0.7)
+    L, U = factors(A, oracle.ilu0(A, 1), 1)
+    R = L @ U - A.to_dense()
+    i, j = np.nonzero(np.abs(R) > 1e-10 * np.abs(A.val).max())
+    assert len(i) > 0
+    assert set(np.unique(j - i)) <= {n - 1, -(n - 1)}
+
+
+def test_one_row_blocks_are_the_jacobi_preconditioner():
+    """Blocks of one row: M = diag(A), so the preconditioner and every AAR
+    iterate equal those of Jacobi bit for bit."""
+    A = inputs.reservoir_matrix(5, seed=6)
+    r = inputs.normal(6, 3, A.n)
+    np.testing.assert_array_equal(oracle.precondition(A, r, oracle.PRECOND_ILU0, A.n),
+                                  oracle.precondition(A, r, oracle.PRECOND_JACOBI))
+    np.testing.assert_array_equal(oracle.precondition(A, r, oracle.PRECOND_JACOBI), r / np.diag(A.to_dense()))
+    b = inputs.normal(6, 4, A.n)
+    kw = dict(x0=np.ones(A.n), m=5, p=3, tol=1e-30, max_iter=23)
+    a = oracle.aar_solve_csr(A, b, precond=oracle.PRECOND_ILU0, nblocks=A.n, **kw)
+    j = oracle.aar_solve_csr(A, b, precond=oracle.PRECOND_JACOBI, **kw)
+    np.testing.assert_array_equal(a["x"], j["x"])
+
+
+def test_jacobi_csr_matches_the_stencil_oracle():
+    """The stencil system assembled into CSR and solved with the Jacobi
+    preconditioner follows the stencil oracle's iterates (only the summation
+    order of A x differs)."""
+    prob = inputs.Problem(n=(5, 4, 6), h=(0.2, 0.25, 1 / 7), bc=(0, 1, 0), radius=1, diffusion=1.0, shift=0.3)
+    N = 5 * 4 * 6
+    D = np.stack([oracle.apply(prob, e) for e in np.eye(N)], axis=1)
+    A = csr_from_dense(D)
+    b = inputs.normal(13, 1, N)
+    for K in (1, 5, 6, 7, 20):
+        s = oracle.aar_solve(prob, b, m=4, p=3, tol=1e-30, max_iter=K)
+        c = oracle.aar_solve_csr(A, b, precond=oracle.PRECOND_JACOBI, m=4, p=3, tol=1e-30, max_iter=K)
+        np.testing.assert_allclose(c["x"], s["x"], rtol=0, atol=1e-11 * np.abs(s["x"]).max())
+
+
+def gmres_residuals(Mi_A, r0, K):
+    """Residual norms of textbook GMRES (Arnoldi with modified Gram-Schmidt,
+    dense least squares on the Hessenberg matrix), k = 0..K."""
+    N = r0.size
+    Q = np.zeros((N, K + 1))
+    H = np.zeros((K + 1, K))
+    beta0 = np.linalg.norm(r0)
+    Q[:, 0] = r0 / beta0
+    res = [beta0]
+    for j in range(K):
+        w = Mi_A @ Q[:, j]
+        for i in range(j + 1):
+            H[i, j] = Q[:, i] @ w
+            w = w - H[i, j] * Q[:, i]
+        H[j + 1, j] = np.linalg.norm(w)
+        Q[:, j + 1] = w / H[j + 1, j]
+        e1 = np.zeros(j + 2)
+        e1[0] = beta0
+        y = np.linalg.lstsq(H[: j + 2, : j + 1], e1, rcond=None)[0]
+        res.append(np.linalg.norm(e1 - H[: j + 2, : j + 1] @ y))
+    return np.array(res)
+
+
+@pytest.mark.parametrize("p,nblocks", [(1, 1), (2, 1), (3, 4)])
+def test_complete_history_matches_gmres_with_ilu0(p, nblocks):
+    """With complete history AAR minimizes ||M^-1 (b - A x)|| over the Krylov
+    space of M^-1 A at every Anderson step, as GMRES does (Sec. 2), here with
+    M from block ILU(0); M^-1 A is formed densely from the library product
+    and a dense solve with the pinned factors."""
+    A = inputs.convection_matrix_2d(9, 1.5)
+    D = A.to_dense()
+    L, U = factors(A, oracle.ilu0(A, nblocks), nblocks)
+    M = L @ U
+    b = inputs.normal(14, 1, A.n)
+    K = 30
+    out = oracle.aar_solve_csr(A, b, precond=oracle.PRECOND_ILU0, nblocks=nblocks, m=K + 2, p=p, tol=1e-30,
+                               max_iter=K + 1, trace_cap=K + 1)
+    tr = out["trace"]
+    g = gmres_residuals(np.linalg.solve(M, D), np.linalg.solve(M, b), K)
+    ks = tr[:, 0].astype(int)
+    keep = g[ks] > 1e-7 * g[0]   # deeper, the conditioning of F^T F limits both
+    assert keep.sum() >= 5
+    np.testing.assert_allclose(tr[keep, 3], g[ks][keep], rtol=1e-7)
+
+
+@pytest.mark.parametrize("precond,nblocks", [(0, 1), (1, 1), (1, 6)])
+def test_solution_matches_a_dense_solve(precond, nblocks):
+    A = inputs.reservoir_matrix(7, seed=15)
+    D = A.to_dense()
+    b = inputs.normal(15, 1, A.n)
+    tol = 1e-10
+    out = oracle.aar_solve_csr(A, b, x0=np.ones(A.n), precond=precond, nblocks=nblocks, tol=tol)
+    assert out["status"] == oracle.OK
+    assert out["iterations"] % 8 == 0
+    ref = np.linalg.solve(D, b)
+    kappa = np.linalg.cond(D)
+    assert np.linalg.norm(out["x"] - ref) <= kappa * tol * np.linalg.norm(ref)
+    assert oracle.relative_residual_csr(A, b, out["x"]) == out["relres"] < tol
+
+
+def test_ilu0_needs_far_fewer_iterations_than_jacobi():
+    """The paper's observation on its nonsymmetric systems (Sec. 3.1): ILU(0)
+    converges where Jacobi needs many times the iterations."""
+    A = inputs.convection_matrix_2d(32, 2.0)
+    b = inputs.normal(16, 1, A.n)
+    j = oracle.aar_solve_csr(A, b, x0=np.ones(A.n), precond=0, max_iter=200000)
+    i = oracle.aar_solve_csr(A, b, x0=np.ones(A.n), precond=1)
+    assert j["status"] == i["status"] == oracle.OK
+    assert 5 * i["iterations"] < j["iterations"]
+
+
+def test_zero_rhs_and_bad_matrices():
+    A = inputs.reservoir_matrix(4, seed=2)
+    out = oracle.aar_solve_csr(A, np.zeros(A.n), x0=np.ones(A.n))
+    assert out["status"] == oracle.OK and out["iterations"] == 0 and not out["x"].any()
+    no_diag = inputs.CsrMatrix(np.array([0, 1, 2], dtype=np.int64), np.array([1, 0], dtype=np.int32),
+                               np.array([1.0, 1.0]))
+    unsorted = inputs.CsrMatrix(np.array([0, 2, 3], dtype=np.int64), np.array([1, 0, 1], dtype=np.int32),
+                                np.array([1.0, 2.0, 3.0]))
+    for bad in (no_diag, unsorted):
+        assert not oracle.csr_check(bad)
+        assert oracle.aar_solve_csr(bad, np.ones(2))["status"] == oracle.BAD_ARG
+    singular = csr_from_dense(np.array([[1.0, 1.0], [1.0, 1.0]]))
+    with pytest.raises(ZeroDivisionError):
+        oracle.ilu0(singular, 1)
+    assert oracle.aar_solve_csr(singular, np.ones(2))["status"] == oracle.BREAKDOWN
