@@ -202,6 +202,46 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
 aar_status aar_create_complex(aar_solver *out, const aar_problem *problem, const aar_params *params,
                               double shift_imag, double omega_imag, double beta_imag, void *hip_stream);
 
+/* Preconditioners of a general sparse system (aar_create_csr). */
+enum { AAR_PRECOND_JACOBI = 0, AAR_PRECOND_ILU0 = 1 };
+
+/* Create a solver for one general sparse system A x = b (Sec. 2, Eq. 1, with
+ * any preconditioner M in Eq. 6: Sec. 3.1 solves nonsymmetric sparse systems
+ * with the Jacobi and the ILU(0) preconditioner; Secs. 3.2-3.3 use block
+ * Jacobi with ILU(0) on each block in parallel).
+ *   n                  rows (1 .. 2^31 - 1)
+ *   rowptr, col, val   host arrays of A in compressed sparse rows: row i
+ *                      holds val[rowptr[i] .. rowptr[i+1]-1] in columns
+ *                      col[...], strictly increasing, diagonal present,
+ *                      values finite (n + 1, nnz and nnz entries; copied at
+ *                      creation, not kept)
+ *   preconditioner     AAR_PRECOND_JACOBI: M = diag(A);
+ *                      AAR_PRECOND_ILU0: M = block diagonal of the ILU(0)
+ *                      factors of the `nblocks` diagonal blocks of A, block
+ *                      t holding rows floor(t n / nblocks) ..
+ *                      floor((t+1) n / nblocks) - 1 (nblocks = 1: ILU(0) of
+ *                      A).  ILU(0): L unit lower and U upper triangular in
+ *                      the pattern of the block, (L U)_ij = a_ij on that
+ *                      pattern, by elimination in row order with fill outside
+ *                      the pattern dropped; entries of A that couple two
+ *                      blocks do not enter M.  The factors are formed on the
+ *                      device at creation.
+ *   nblocks            1 .. n for ILU(0), each block at most 16384 rows
+ *                      (AAR_ERR_UNSUPPORTED beyond); ignored for Jacobi
+ * The handle then takes vectors of n doubles (one value per row) in
+ * aar_solve, aar_apply and aar_precondition.  Every Richardson step forms f
+ * from x and b.  Supported: precision AAR_FP64 and the flags
+ * AAR_FLAG_RECORD_RESIDUALS, AAR_FLAG_NO_GRAPH, AAR_FLAG_FORCE_PINV
+ * (AAR_ERR_UNSUPPORTED for the others); aar_solve_batched is not.  A zero or
+ * non-finite ILU(0) pivot returns AAR_ERR_UNSUPPORTED. */
+aar_status aar_create_csr(aar_solver *out, int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                          int32_t preconditioner, int32_t nblocks, const aar_params *params, void *hip_stream);
+
+/* z = M^{-1} r for the preconditioner of a solver from aar_create_csr (the
+ * M^{-1} of Eq. 6; a check of the factors and substitutions).  r and z are
+ * device vectors of n doubles and must not overlap. */
+aar_status aar_precondition(aar_solver s, const double *r, double *z);
+
 /* Solve system 0 (count must be 1) by AAR (Sec. 2, Eqs. 2-6).  x holds x_0
  * on entry and the answer on return (the iterate x_k whose test passed, or
  * the last iterate); b is read only.  r receives the outcome (may be NULL). */
@@ -217,8 +257,8 @@ aar_status aar_solve_batched(aar_solver s, const double *b, double *x, const int
                              aar_result *results);
 
 /* y = A x in FP64 for system `instance` (the operator of Eq. 1; a check of
- * the stencil).  x and y are device vectors of that system's size and must
- * not overlap. */
+ * the stencil, or of the sparse product for a solver from aar_create_csr).
+ * x and y are device vectors of that system's size and must not overlap. */
 aar_status aar_apply(aar_solver s, int32_t instance, const double *x, double *y);
 
 /* Copy up to `cap` recorded Anderson-step residuals r_k (Sec. 2, text after

@@ -26,6 +26,7 @@ AAR_BC_ZERO_DIRICHLET, AAR_BC_PERIODIC = 0, 1
 AAR_FP64, AAR_MIXED_FP32, AAR_MIXED_FP32_BF16HIST, AAR_FP64_FP32HIST, AAR_FP64_BF16HIST = 0, 1, 2, 3, 4
 AAR_FLAG_RECORD_RESIDUALS, AAR_FLAG_DEFLATE_CONSTANT, AAR_FLAG_NO_GRAPH, AAR_FLAG_NO_AUTOTUNE = 1, 2, 4, 8
 AAR_FLAG_FORCE_PINV, AAR_FLAG_RECYCLE_HISTORY = 16, 32
+AAR_PRECOND_JACOBI, AAR_PRECOND_ILU0 = 0, 1
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "BREAKDOWN", -1: "INVALID_ARG", -2: "UNSUPPORTED",
                 -3: "DEVICE", -4: "OUT_OF_MEMORY"}
@@ -81,6 +82,8 @@ def load_library():
     lib.aar_create_complex.argtypes = [P(vp), P(aar_problem), P(aar_params), d, d, d, vp]
     lib.aar_select_parameters.argtypes = [P(aar_problem), P(aar_params), vp, P(d), i32, P(i32), i32, i64, vp,
                                           P(d), P(i32), P(d)]
+    lib.aar_create_csr.argtypes = [P(vp), i64, vp, vp, vp, i32, i32, P(aar_params), vp]
+    lib.aar_precondition.argtypes = [vp, vp, vp]
     lib.aar_workspace_bytes.argtypes = [P(aar_problem), i32, P(aar_params), P(ctypes.c_size_t)]
     lib.aar_destroy.argtypes = [vp]
     lib.aar_last_error.argtypes = []
@@ -88,8 +91,8 @@ def load_library():
     lib.aar_set_timing.argtypes = [vp, i32]
     lib.aar_sweep_time.argtypes = [vp, P(ctypes.c_double), P(i64)]
     for name in ["aar_create", "aar_solve", "aar_solve_batched", "aar_apply", "aar_residual_log",
-                 "aar_rank_log", "aar_solve_noalloc", "aar_create_complex", "aar_select_parameters", "aar_workspace_bytes", "aar_destroy", "aar_set_timing",
-                 "aar_sweep_time"]:
+                 "aar_rank_log", "aar_solve_noalloc", "aar_create_complex", "aar_create_csr", "aar_precondition",
+                 "aar_select_parameters", "aar_workspace_bytes", "aar_destroy", "aar_set_timing", "aar_sweep_time"]:
         getattr(lib, name).restype = st
     _lib = lib
     return lib
@@ -127,6 +130,23 @@ def aar_create_complex(problem, params, shift_imag: float, omega_imag: float = 0
                                              float(shift_imag), float(omega_imag), float(beta_imag),
                                              ctypes.c_void_p(hip_stream)), "aar_create_complex")
     return h
+
+
+def aar_create_csr(rowptr, col, val, preconditioner: int, nblocks: int, params, hip_stream: int = 0):
+    """rowptr (int64), col (int32), val (float64): host numpy arrays."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    h = ctypes.c_void_p()
+    _check(load_library().aar_create_csr(ctypes.byref(h), len(rowptr) - 1, rowptr.ctypes.data, col.ctypes.data,
+                                         val.ctypes.data, int(preconditioner), int(nblocks), ctypes.byref(params),
+                                         ctypes.c_void_p(hip_stream)), "aar_create_csr")
+    return h
+
+
+def aar_precondition(handle, r_ptr: int, z_ptr: int) -> None:
+    _check(load_library().aar_precondition(handle, ctypes.c_void_p(r_ptr), ctypes.c_void_p(z_ptr)),
+           "aar_precondition")
 
 
 def aar_select_parameters(problem, params, b_ptr: int, betas, ps, trial_iterations: int, hip_stream: int = 0):
@@ -388,3 +408,70 @@ class ComplexSolver:
         if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()
                 and t.numel() == self.size):
             raise ValueError(f"expected a contiguous complex128 CUDA tensor of {self.size} elements")
+
+
+class CsrSolver:
+    """A solver handle for one general sparse system (aar_create_csr): A in
+    compressed sparse rows (any object with rowptr, col, val arrays), the
+    Jacobi (AAR_PRECOND_JACOBI) or block ILU(0) (AAR_PRECOND_ILU0, `nblocks`
+    contiguous row blocks) preconditioner.  Vectors are float64 CUDA tensors of
+    n elements."""
+
+    def __init__(self, A, params, preconditioner=AAR_PRECOND_ILU0, nblocks=1, device=None, stream=None):
+        import torch
+        load_library()
+        self.device = torch.device(device or "cuda:0")
+        self.params = params
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        self.size = len(A.rowptr) - 1
+        with torch.cuda.device(self.device):
+            self.handle = aar_create_csr(A.rowptr, A.col, A.val, preconditioner, nblocks, make_params(params),
+                                         self.stream.cuda_stream)
+
+    def solve(self, b, x) -> dict:
+        self._check_vec(b)
+        self._check_vec(x)
+        return result_dict(aar_solve(self.handle, b.data_ptr(), x.data_ptr()))
+
+    def apply(self, x):
+        import torch
+        self._check_vec(x)
+        y = torch.empty_like(x)
+        aar_apply(self.handle, 0, x.data_ptr(), y.data_ptr())
+        return y
+
+    def precondition(self, r):
+        import torch
+        self._check_vec(r)
+        z = torch.empty_like(r)
+        aar_precondition(self.handle, r.data_ptr(), z.data_ptr())
+        return z
+
+    def residual_log(self) -> np.ndarray:
+        return aar_residual_log(self.handle, 0)
+
+    def rank_log(self) -> np.ndarray:
+        return aar_rank_log(self.handle, 0)
+
+    def set_timing(self, enable: bool) -> None:
+        aar_set_timing(self.handle, enable)
+
+    def sweep_time(self) -> tuple:
+        return aar_sweep_time(self.handle)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            aar_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_vec(self, t):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                and t.numel() == self.size):
+            raise ValueError(f"expected a contiguous float64 CUDA tensor of {self.size} elements")

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libaar_hip.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["stencil.hip", "stencil_narrow.hip", "stencil_f32.hip", "tblock.hip", "complex.hip", "anderson.hip",
+SOURCES = ["stencil.hip", "stencil_narrow.hip", "stencil_f32.hip", "tblock.hip", "complex.hip", "sparse.hip", "anderson.hip",
            "batched.hip", "driver.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -175,6 +175,7 @@ enum StencilMode : int {
     kFk = 1,      // f_k = D^-1 (b - A x); ring <- f_k; partial += ||b - A x||^2
     kResid = 2,   // out = b - A x; partial += ||b - A x||^2
     kApply = 3,   // out = A x
+    kPrecond = 4, // sparse A only: out = M^-1 x
 };
 
 template <typename T> struct StencilArgs {
@@ -577,5 +578,54 @@ hipError_t launch_cnorm_partial(const zd *v, int64_t N, double *partial, int blo
 
 int stream_blocks(int64_t N);
 int gram_blocks(int64_t N, int m);
+
+// ---------------------------------------------------------------------------
+// General sparse A (compressed sparse rows) with the Jacobi or block-Jacobi
+// ILU(0) preconditioner (sparse.hip).
+// ---------------------------------------------------------------------------
+
+// Largest LDS a sparse block may hold: its rows' values during the
+// substitutions (FP64).
+constexpr size_t kCsrMaxLds = 128 * 1024;
+constexpr int kCsrMaxBlockRows = (int)(kCsrMaxLds / sizeof(double));
+
+struct CsrDev {
+    int64_t n;
+    const int64_t *rowptr;   // n + 1
+    const int32_t *col;      // strictly increasing per row, diagonal present
+    const double *val;
+    double *lu;              // ILU(0) factors in A's pattern (entries inside each block), or null
+    const int64_t *dpos;     // position of each row's diagonal entry
+    const int64_t *bstart;   // nblocks + 1 row bounds of the blocks
+    // level schedules of each block: rows grouped by level of the forward
+    // (lrows, lptr) and backward (urows, uptr) substitution; block t owns
+    // levels blev_l[t] .. blev_l[t+1] - 1 (and likewise blev_u)
+    const int32_t *lrows, *urows;
+    const int32_t *lptr, *uptr;
+    const int32_t *blev_l, *blev_u;
+    int nblocks;
+    int max_block_rows;
+    int ilu;                 // 1: block ILU(0); 0: Jacobi (blocks are plain row chunks)
+};
+
+struct CsrArgs {
+    CsrDev c;
+    const double *x;         // kSweep / kFk / kApply: the iterate (any row is read); kPrecond: the input
+    const double *b;
+    double *xout;            // kSweep: x + omega f
+    double *out;             // kApply: A x; kPrecond: M^-1 x
+    void *fring;             // kSweep / kFk: history ring (FP64)
+    const InstState *state;
+    int64_t slot_stride;
+    int j, p, nslots;
+    double omega;
+    double *partial;         // kFk: one ||b - A x||^2 partial per block
+};
+
+// Allow the block-ILU(0) passes the LDS of the largest block (call once per
+// device before the first launch, outside any stream capture).
+hipError_t prepare_csr_kernels();
+hipError_t launch_csr(int mode, const CsrArgs &a, hipStream_t s);
+hipError_t launch_ilu0(const CsrDev &c, int *bad, hipStream_t s);
 
 }  // namespace aar

@@ -243,6 +243,11 @@ struct aar_solver_t {
     double shift_im = 0.0, omega_im = 0.0, beta_im = 0.0;
     Path<zd> pz;
 
+    // general sparse system (aar_create_csr): CSR arrays, block bounds,
+    // level schedules and ILU(0) factors on the device; vectors in p64
+    bool csr = false;
+    CsrDev cd{};
+
     // batched engine (count > 1 with one stencil radius and convection kind)
     struct Batch {
         bool on = false;
@@ -773,13 +778,124 @@ hipError_t enqueue_cycle_complex(aar_solver_t *S, const Path<zd> &P, hipStream_t
     return launch_cupdate(u, P.upd_blocks, s);
 }
 
+// One AAR cycle of a general sparse system (sparse.hip kernels): p - 1
+// sweeps from x and b with x ping-ponged (every row reads x anywhere), the
+// Anderson-step residual with its norm partials, the Gram products, the
+// one-wave solve and the update.
+hipError_t enqueue_cycle_csr(aar_solver_t *S, const Path<double> &P, hipStream_t s, int64_t cycle_tag)
+{
+    const aar_params &pa = S->params;
+    CsrArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.c = S->cd;
+    a.b = P.b;
+    a.fring = P.fring;
+    a.state = S->state;
+    a.slot_stride = P.slot_stride;
+    a.p = pa.p;
+    a.nslots = pa.m + 1;
+    a.omega = pa.omega;
+    hipError_t e;
+    for (int j = 0; j < pa.p - 1; ++j) {
+        a.j = j;
+        a.x = (j & 1) ? P.xb : P.xa;
+        a.xout = (j & 1) ? P.xa : P.xb;
+        // timing: one event pair around the cycle's p - 1 back-to-back sweeps
+        if (S->timing && j == 0) {
+            if (S->tused + 2 > S->tev.size()) {
+                for (int t = 0; t < 64; ++t) {
+                    hipEvent_t ev;
+                    if ((e = hipEventCreate(&ev)) != hipSuccess)
+                        return e;
+                    S->tev.push_back(ev);
+                }
+            }
+            if ((e = hipEventRecord(S->tev[S->tused], s)) != hipSuccess)
+                return e;
+        }
+        if ((e = launch_csr(kSweep, a, s)) != hipSuccess)
+            return e;
+        if (S->timing && j == pa.p - 2) {
+            if ((e = hipEventRecord(S->tev[S->tused + 1], s)) != hipSuccess)
+                return e;
+            S->tcycle.push_back(cycle_tag * pa.p + j);
+            S->tcount.push_back(pa.p - 1);
+            S->tused += 2;
+        }
+    }
+    const int jk = pa.p - 1;
+    double *xk = (jk & 1) ? P.xb : P.xa;
+    a.j = jk;
+    a.x = xk;
+    a.xout = nullptr;
+    a.partial = S->part_rho;
+    if ((e = launch_csr(kFk, a, s)) != hipSuccess)
+        return e;
+    GramArgs g;
+    g.fring = P.fring;
+    g.partial = S->part_gram;
+    g.state = S->state;
+    g.N = P.N;
+    g.slot_stride = P.slot_stride;
+    g.m = pa.m;
+    g.p = pa.p;
+    g.nslots = pa.m + 1;
+    g.ne = S->ne;
+    if ((e = launch_gram(Prec::F64, g, P.gram_blocks, s)) != hipSuccess)
+        return e;
+    if ((e = launch_gram_finish(S->part_gram, P.gram_blocks, S->gram_final, S->ne, S->state, pa.p, s)) !=
+        hipSuccess)
+        return e;
+    LsqArgs l;
+    std::memset(&l, 0, sizeof(l));
+    l.state = S->state;
+    l.rho_partial = S->part_rho;
+    l.rho_blocks = P.rho_blocks;
+    l.gram_final = S->gram_final;
+    l.ne = S->ne;
+    l.gram_partial = nullptr;
+    l.gram_blocks = 0;
+    l.m = pa.m;
+    l.p = pa.p;
+    l.nslots = pa.m + 1;
+    l.q = S->q;
+    l.omega = pa.omega;
+    l.beta = pa.beta;
+    l.rcond = std::ldexp(1.0, -52);
+    l.stagnation_window = 0;
+    l.stagnation_factor = 0.9;
+    l.log = S->log;
+    l.rank_log = S->rank_log;
+    l.log_cap = S->log_cap;
+    l.force_pinv = (pa.flags & AAR_FLAG_FORCE_PINV) ? 1 : 0;
+    if ((e = launch_lsq(l, s)) != hipSuccess)
+        return e;
+    UpdateArgs<double> u;
+    u.xin = xk;
+    u.xout = P.xa;
+    u.fring = P.fring;
+    u.fcur = nullptr;
+    u.dxring = P.dx;
+    u.state = S->state;
+    u.N = P.N;
+    u.slot_stride = P.slot_stride;
+    u.dx_stride = P.dx_stride;
+    u.status_out = S->status_dev;
+    return launch_update(Prec::F64, &u, nullptr, P.upd_blocks, s);
+}
+
 template <typename T>
 hipError_t enqueue_any(aar_solver_t *S, const Path<T> &P, bool inner, hipStream_t s, int64_t cycle_tag)
 {
-    if constexpr (std::is_same<T, zd>::value)
+    if constexpr (std::is_same<T, zd>::value) {
         return enqueue_cycle_complex(S, P, s);
-    else
+    } else {
+        if constexpr (std::is_same<T, double>::value) {
+            if (S->csr)
+                return enqueue_cycle_csr(S, P, s, cycle_tag);
+        }
         return enqueue_cycle<T>(S, P, inner, s, cycle_tag);
+    }
 }
 
 constexpr int kGraphCycles = 4;
@@ -1329,6 +1445,134 @@ aar_status solve_complex(aar_solver_t *S, const double *b, double *x, aar_result
     if (res)
         *res = r;
     return (aar_status)r.status;
+}
+
+// General sparse system: x holds x0 on entry and the answer on exit.
+aar_status solve_csr(aar_solver_t *S, const double *b, double *x, aar_result *res)
+{
+    const aar_params &pa = S->params;
+    Path<double> &P = S->p64;
+    const int64_t N = P.N;
+    hipStream_t s = S->stream;
+    const bool use_graph = !(pa.flags & AAR_FLAG_NO_GRAPH) && !S->timing;
+    aar_result r{};
+    InstState st{};
+    AAR_HIP(hipMemcpyAsync(P.b, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    AAR_HIP(hipMemcpyAsync(P.xa, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    const int nb_blocks = stream_blocks(N);
+    AAR_HIP(launch_norm_partial(true, P.b, N, S->part_norm, nb_blocks, s));
+    AAR_HIP(launch_init_state(S->state, S->part_norm, nb_blocks, pa.max_iter, pa.tol, s));
+    AAR_HIP(hipMemcpyAsync(&st, S->state, sizeof(InstState), hipMemcpyDeviceToHost, s));
+    AAR_HIP(hipStreamSynchronize(s));
+    if (st.nb == 0.0) {
+        AAR_HIP(launch_zero_f64(x, N, s));
+        AAR_HIP(hipStreamSynchronize(s));
+        r.status = AAR_OK;
+        if (res)
+            *res = r;
+        S->last_log_count[0] = 0;
+        return AAR_OK;
+    }
+    aar_status e = run_cycles<double>(S, P, pa.max_iter, false, use_graph, &st);
+    if (e != AAR_OK)
+        return e;
+    const int64_t done = (st.status == kMaxIter || st.status == kRunning) ? pa.max_iter : st.iters;
+    const int64_t j = (done - 1) % pa.p;
+    const bool anderson_last = (st.status == kMaxIter || st.status == kRunning) && j == pa.p - 1;
+    const double *xf;
+    if (st.status == kConverged || st.status == kBreakdown)
+        xf = ((pa.p - 1) & 1) ? P.xb : P.xa;     // x_k of the Anderson step
+    else if (anderson_last)
+        xf = P.xa;                              // the last iteration was an update
+    else
+        xf = ((j + 1) & 1) ? P.xb : P.xa;       // after j+1 sweeps of the cycle
+    AAR_HIP(hipMemcpyAsync(x, xf, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    AAR_HIP(hipStreamSynchronize(s));
+    r.status = status_of(st);
+    r.iterations = done;
+    r.rel_residual = st.last_r;
+    r.outer_steps = 0;
+    S->last_log_count[0] = st.log_count;
+    if (res)
+        *res = r;
+    return (aar_status)r.status;
+}
+
+// Block bounds and level schedules of a sparse matrix (host, at creation).
+// Rows of a block are grouped by the level of their forward substitution
+// (0 when no earlier row of the block enters the row; else one more than the
+// deepest such row) and, separately, of the backward substitution (the same
+// with later rows).  Rows of one level never depend on each other.
+struct CsrPlan {
+    std::vector<int64_t> dpos, bstart;
+    std::vector<int32_t> lrows, urows, lptr, uptr, blev_l, blev_u;
+    int max_block_rows = 0;
+};
+
+void plan_csr(int64_t n, const int64_t *rowptr, const int32_t *col, int nblocks, bool levels, CsrPlan *pl)
+{
+    pl->dpos.assign(n, -1);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+            if (col[e] == i)
+                pl->dpos[i] = e;
+    pl->bstart.resize(nblocks + 1);
+    for (int t = 0; t <= nblocks; ++t)
+        pl->bstart[t] = (int64_t)t * n / nblocks;
+    pl->max_block_rows = 0;
+    for (int t = 0; t < nblocks; ++t)
+        pl->max_block_rows = std::max<int64_t>(pl->max_block_rows, pl->bstart[t + 1] - pl->bstart[t]);
+    pl->lrows.clear();
+    pl->urows.clear();
+    pl->lptr.assign(1, 0);
+    pl->uptr.assign(1, 0);
+    pl->blev_l.assign(1, 0);
+    pl->blev_u.assign(1, 0);
+    if (!levels)
+        return;
+    pl->lrows.reserve(n);
+    pl->urows.reserve(n);
+    std::vector<int32_t> lev(n);
+    auto group = [&](int64_t lo, int64_t hi, int32_t top, std::vector<int32_t> &rows, std::vector<int32_t> &ptr,
+                     std::vector<int32_t> &blev) {
+        std::vector<int32_t> cnt(top + 1, 0);
+        for (int64_t i = lo; i < hi; ++i)
+            ++cnt[lev[i]];
+        const int32_t base = (int32_t)rows.size();
+        std::vector<int32_t> pos(top + 1);
+        int32_t run = base;
+        for (int32_t v = 0; v <= top; ++v) {
+            pos[v] = run;
+            run += cnt[v];
+            ptr.push_back(run);
+        }
+        rows.resize(run);
+        for (int64_t i = lo; i < hi; ++i)
+            rows[pos[lev[i]]++] = (int32_t)i;
+        blev.push_back((int32_t)ptr.size() - 1);
+    };
+    for (int t = 0; t < nblocks; ++t) {
+        const int64_t lo = pl->bstart[t], hi = pl->bstart[t + 1];
+        int32_t top = 0;
+        for (int64_t i = lo; i < hi; ++i) {
+            int32_t v = 0;
+            for (int64_t e = rowptr[i]; e < pl->dpos[i]; ++e)
+                if (col[e] >= lo)
+                    v = std::max(v, lev[col[e]] + 1);
+            lev[i] = v;
+            top = std::max(top, v);
+        }
+        group(lo, hi, top, pl->lrows, pl->lptr, pl->blev_l);
+        top = 0;
+        for (int64_t i = hi - 1; i >= lo; --i) {
+            int32_t v = 0;
+            for (int64_t e = pl->dpos[i] + 1; e < rowptr[i + 1] && col[e] < hi; ++e)
+                v = std::max(v, lev[col[e]] + 1);
+            lev[i] = v;
+            top = std::max(top, v);
+        }
+        group(lo, hi, top, pl->urows, pl->uptr, pl->blev_u);
+    }
 }
 
 // x (length N, FP64 device) on entry x0, on exit the answer of system idx.
@@ -2547,6 +2791,185 @@ aar_status aar_create_complex(aar_solver *out, const aar_problem *problem, const
     return AAR_OK;
 }
 
+aar_status aar_create_csr(aar_solver *out, int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                          int32_t preconditioner, int32_t nblocks, const aar_params *params, void *hip_stream)
+{
+    g_error.clear();
+    if (!out)
+        return fail(AAR_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!rowptr || !col || !val)
+        return fail(AAR_ERR_INVALID_ARG, "rowptr, col or val is NULL");
+    aar_status st = validate_params(params);
+    if (st != AAR_OK)
+        return st;
+    if (n < 1 || n > INT32_MAX)
+        return fail(AAR_ERR_INVALID_ARG, "n must be in 1 .. 2^31 - 1");
+    if (preconditioner != AAR_PRECOND_JACOBI && preconditioner != AAR_PRECOND_ILU0)
+        return fail(AAR_ERR_INVALID_ARG, "unknown preconditioner");
+    if (rowptr[0] != 0)
+        return fail(AAR_ERR_INVALID_ARG, "rowptr[0] must be 0");
+    for (int64_t i = 0; i < n; ++i) {
+        if (rowptr[i + 1] < rowptr[i])
+            return fail(AAR_ERR_INVALID_ARG, "rowptr decreases at row " + std::to_string(i));
+        bool diag = false;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            if (col[e] < 0 || col[e] >= n)
+                return fail(AAR_ERR_INVALID_ARG, "column out of range in row " + std::to_string(i));
+            if (e > rowptr[i] && col[e] <= col[e - 1])
+                return fail(AAR_ERR_INVALID_ARG, "columns not strictly increasing in row " + std::to_string(i));
+            if (!std::isfinite(val[e]))
+                return fail(AAR_ERR_INVALID_ARG, "non-finite value in row " + std::to_string(i));
+            diag = diag || col[e] == i;
+        }
+        if (!diag)
+            return fail(AAR_ERR_INVALID_ARG, "row " + std::to_string(i) + " has no diagonal entry");
+    }
+    const bool ilu = preconditioner == AAR_PRECOND_ILU0;
+    if (ilu && (nblocks < 1 || nblocks > n))
+        return fail(AAR_ERR_INVALID_ARG, "nblocks must be in 1 .. n for block ILU(0)");
+    // Jacobi: plain row chunks, one workgroup each
+    const int nb = ilu ? nblocks : (int)std::max<int64_t>(1, (n + 2047) / 2048);
+    if (ilu && (n + nb - 1) / nb > kCsrMaxBlockRows)
+        return fail(AAR_ERR_UNSUPPORTED, "block ILU(0) blocks hold at most " + std::to_string(kCsrMaxBlockRows) +
+                                             " rows: raise nblocks");
+    if (params->precision != AAR_FP64)
+        return fail(AAR_ERR_UNSUPPORTED, "sparse systems run the FP64 iteration only");
+    if (params->flags & (AAR_FLAG_DEFLATE_CONSTANT | AAR_FLAG_RECYCLE_HISTORY))
+        return fail(AAR_ERR_UNSUPPORTED, "deflation and recycling are for stencil systems");
+    std::unique_ptr<aar_solver_t> S(new aar_solver_t());
+    S->params = *params;
+    S->stream = (hipStream_t)hip_stream;
+    S->csr = true;
+    AAR_HIP(hipGetDevice(&S->device));
+    AAR_HIP(hipStreamCreateWithFlags(&S->capture_stream, hipStreamNonBlocking));
+    AAR_HIP(hipHostMalloc((void **)&S->host_status, 2 * sizeof(int32_t),
+                          hipHostMallocMapped | hipHostMallocCoherent));
+    S->host_status[0] = S->host_status[1] = kRunning;
+    AAR_HIP(hipHostGetDevicePointer((void **)&S->status_dev, S->host_status, 0));
+    for (auto &e : S->poll_ev)
+        AAR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    S->q = params->m / params->p;
+    S->ne = params->m * (params->m + 1) / 2 + params->m;
+    S->maxN = n;
+    S->last_log_count.assign(1, 0);
+    Operator op;
+    std::memset(&op.prob, 0, sizeof(op.prob));
+    op.N = n;
+    S->ops.push_back(op);
+
+    CsrPlan pl;
+    plan_csr(n, rowptr, col, nb, ilu, &pl);
+    const int64_t nnz = rowptr[n];
+    st = AAR_OK;
+    int64_t *d_rowptr = S->alloc<int64_t>(n + 1, &st);
+    int32_t *d_col = S->alloc<int32_t>(nnz, &st);
+    double *d_val = S->alloc<double>(nnz, &st);
+    double *d_lu = ilu ? S->alloc<double>(nnz, &st) : nullptr;
+    int64_t *d_dpos = S->alloc<int64_t>(n, &st);
+    int64_t *d_bstart = S->alloc<int64_t>(nb + 1, &st);
+    int32_t *d_lrows = S->alloc<int32_t>(pl.lrows.size(), &st);
+    int32_t *d_urows = S->alloc<int32_t>(pl.urows.size(), &st);
+    int32_t *d_lptr = S->alloc<int32_t>(pl.lptr.size(), &st);
+    int32_t *d_uptr = S->alloc<int32_t>(pl.uptr.size(), &st);
+    int32_t *d_blevl = S->alloc<int32_t>(pl.blev_l.size(), &st);
+    int32_t *d_blevu = S->alloc<int32_t>(pl.blev_u.size(), &st);
+    int *d_bad = S->alloc<int>(1, &st);
+    const int64_t N = (n + 7) / 8 * 8;
+    const int slots = params->m + 1;
+    const int gblocks = gram_blocks(n, params->m);
+    S->state = S->alloc<InstState>(1, &st);
+    S->part_rho = S->alloc<double>(nb, &st);
+    S->part_rho_cap = nb;
+    S->part_gram = S->alloc<double>((size_t)gblocks * S->ne, &st);
+    S->part_norm = S->alloc<double>(stream_blocks(n), &st);
+    S->gram_final = S->alloc<double>(S->ne, &st);
+    S->scal = S->alloc<double>(8, &st);
+    if (params->flags & AAR_FLAG_RECORD_RESIDUALS) {
+        S->log_cap = std::min<int64_t>(params->max_iter / params->p + 2, (int64_t)1 << 22);
+        S->log = S->alloc<double>(S->log_cap, &st);
+        S->rank_log = S->alloc<int32_t>(S->log_cap, &st);
+    }
+    Path<double> &P = S->p64;
+    P.xa = S->alloc<double>(N, &st);
+    P.xb = S->alloc<double>(N, &st);
+    P.b = S->alloc<double>(N, &st);
+    P.fring = S->alloc<double>((size_t)N * slots, &st);
+    P.dx = S->q > 0 ? (void *)S->alloc<double>((size_t)N * S->q, &st) : nullptr;
+    if (st != AAR_OK)
+        return st;
+    hipStream_t s = S->stream;
+    AAR_HIP(hipMemcpyAsync(d_rowptr, rowptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+    AAR_HIP(hipMemcpyAsync(d_col, col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
+    AAR_HIP(hipMemcpyAsync(d_val, val, sizeof(double) * nnz, hipMemcpyHostToDevice, s));
+    AAR_HIP(hipMemcpyAsync(d_dpos, pl.dpos.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+    AAR_HIP(hipMemcpyAsync(d_bstart, pl.bstart.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, s));
+    if (ilu) {
+        AAR_HIP(hipMemcpyAsync(d_lu, val, sizeof(double) * nnz, hipMemcpyHostToDevice, s));
+        AAR_HIP(hipMemcpyAsync(d_lrows, pl.lrows.data(), sizeof(int32_t) * pl.lrows.size(), hipMemcpyHostToDevice, s));
+        AAR_HIP(hipMemcpyAsync(d_urows, pl.urows.data(), sizeof(int32_t) * pl.urows.size(), hipMemcpyHostToDevice, s));
+    }
+    AAR_HIP(hipMemcpyAsync(d_lptr, pl.lptr.data(), sizeof(int32_t) * pl.lptr.size(), hipMemcpyHostToDevice, s));
+    AAR_HIP(hipMemcpyAsync(d_uptr, pl.uptr.data(), sizeof(int32_t) * pl.uptr.size(), hipMemcpyHostToDevice, s));
+    AAR_HIP(hipMemcpyAsync(d_blevl, pl.blev_l.data(), sizeof(int32_t) * pl.blev_l.size(), hipMemcpyHostToDevice, s));
+    AAR_HIP(hipMemcpyAsync(d_blevu, pl.blev_u.data(), sizeof(int32_t) * pl.blev_u.size(), hipMemcpyHostToDevice, s));
+    CsrDev &c = S->cd;
+    c.n = n;
+    c.rowptr = d_rowptr;
+    c.col = d_col;
+    c.val = d_val;
+    c.lu = d_lu;
+    c.dpos = d_dpos;
+    c.bstart = d_bstart;
+    c.lrows = d_lrows;
+    c.urows = d_urows;
+    c.lptr = d_lptr;
+    c.uptr = d_uptr;
+    c.blev_l = d_blevl;
+    c.blev_u = d_blevu;
+    c.nblocks = nb;
+    c.max_block_rows = pl.max_block_rows;
+    c.ilu = ilu ? 1 : 0;
+    if (ilu) {
+        AAR_HIP(prepare_csr_kernels());
+        // the factors: once, on the device
+        int bad = 0;
+        AAR_HIP(hipMemsetAsync(d_bad, 0, sizeof(int), s));
+        AAR_HIP(launch_ilu0(c, d_bad, s));
+        AAR_HIP(hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        AAR_HIP(hipStreamSynchronize(s));
+        if (bad)
+            return fail(AAR_ERR_UNSUPPORTED, "ILU(0) meets a zero or non-finite pivot");
+    }
+    AAR_HIP(hipStreamSynchronize(s));
+    P.hist = Prec::F64;
+    P.N = n;
+    P.rho_blocks = nb;
+    P.gram_blocks = gblocks;
+    P.upd_blocks = stream_blocks(n);
+    P.slot_stride = N;
+    P.dx_stride = N;
+    *out = S.release();
+    return AAR_OK;
+}
+
+aar_status aar_precondition(aar_solver s, const double *r, double *z)
+{
+    g_error.clear();
+    if (!s || !r || !z)
+        return fail(AAR_ERR_INVALID_ARG, "solver, r or z is NULL");
+    if (!s->csr)
+        return fail(AAR_ERR_UNSUPPORTED, "aar_precondition is for solvers from aar_create_csr");
+    CsrArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.c = s->cd;
+    a.x = r;
+    a.out = z;
+    AAR_HIP(launch_csr(kPrecond, a, s->stream));
+    AAR_HIP(hipStreamSynchronize(s->stream));
+    return AAR_OK;
+}
+
 aar_status aar_select_parameters(const aar_problem *problem, const aar_params *params, const double *b,
                                  const double *betas, int32_t nbeta, const int32_t *ps, int32_t np,
                                  int64_t trial_iterations, void *hip_stream, double *beta_out, int32_t *p_out,
@@ -2643,6 +3066,8 @@ aar_status aar_solve(aar_solver s, const double *b, double *x, aar_result *r)
         return fail(AAR_ERR_INVALID_ARG, "aar_solve needs a solver created with count == 1");
     if (s->cplx)
         return solve_complex(s, b, x, r);
+    if (s->csr)
+        return solve_csr(s, b, x, r);
     return solve_one(s, 0, b, x, r);
 }
 
@@ -2658,8 +3083,8 @@ aar_status aar_solve_batched(aar_solver s, const double *b, double *x, const int
             return fail(AAR_ERR_INVALID_ARG, "offsets do not match the system sizes (system " +
                                                  std::to_string(i) + ")");
     }
-    if (s->cplx)
-        return fail(AAR_ERR_UNSUPPORTED, "complex systems are solved one by one (aar_solve)");
+    if (s->cplx || s->csr)
+        return fail(AAR_ERR_UNSUPPORTED, "complex and sparse systems are solved one by one (aar_solve)");
     if (s->B.on)
         return batch_solve(s, b, x, offsets, results);
     aar_status worst = AAR_OK;
@@ -2680,6 +3105,16 @@ aar_status aar_apply(aar_solver s, int32_t instance, const double *x, double *y)
         return fail(AAR_ERR_INVALID_ARG, "solver, x or y is NULL");
     if (instance < 0 || instance >= (int)s->ops.size())
         return fail(AAR_ERR_INVALID_ARG, "instance out of range");
+    if (s->csr) {
+        CsrArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.c = s->cd;
+        a.x = x;
+        a.out = y;
+        AAR_HIP(launch_csr(kApply, a, s->stream));
+        AAR_HIP(hipStreamSynchronize(s->stream));
+        return AAR_OK;
+    }
     if (s->cplx) {
         StencilArgs<zd> a;
         std::memset(&a, 0, sizeof(a));

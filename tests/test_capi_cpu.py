@@ -150,3 +150,29 @@ def test_select_parameters_rejects_bad_candidates():
         with pytest.raises(aar.AarError) as ei:
             aar.aar_select_parameters(aar.make_problem(prob), aar.make_params(inputs.Params()), 1, betas, ps, trial)
         assert ei.value.status == aar.AAR_ERR_INVALID_ARG
+
+
+def _csr(rowptr, col, val):
+    return (np.asarray(rowptr, dtype=np.int64), np.asarray(col, dtype=np.int32), np.asarray(val, dtype=np.float64))
+
+
+@pytest.mark.parametrize("matrix,pc,nblocks,change,status", [
+    (_csr([0, 1, 2], [1, 0], [1.0, 1.0]), 1, 1, {}, aar.AAR_ERR_INVALID_ARG),            # no diagonal
+    (_csr([0, 2, 3], [1, 0, 1], [1.0, 2.0, 3.0]), 1, 1, {}, aar.AAR_ERR_INVALID_ARG),    # unsorted row
+    (_csr([0, 1, 2], [0, 2], [1.0, 1.0]), 1, 1, {}, aar.AAR_ERR_INVALID_ARG),            # column out of range
+    (_csr([0, 1, 2], [0, 1], [1.0, float("nan")]), 1, 1, {}, aar.AAR_ERR_INVALID_ARG),   # non-finite value
+    (_csr([0, 1, 2], [0, 1], [1.0, 1.0]), 1, 3, {}, aar.AAR_ERR_INVALID_ARG),            # nblocks > n
+    (_csr([0, 1, 2], [0, 1], [1.0, 1.0]), 1, 0, {}, aar.AAR_ERR_INVALID_ARG),            # nblocks < 1
+    (_csr([0, 1, 2], [0, 1], [1.0, 1.0]), 7, 1, {}, aar.AAR_ERR_INVALID_ARG),            # preconditioner
+    (_csr([0, 1, 2], [0, 1], [1.0, 1.0]), 1, 1, dict(precision=1), aar.AAR_ERR_UNSUPPORTED),
+    (_csr([0, 1, 2], [0, 1], [1.0, 1.0]), 0, 1, dict(flags=32), aar.AAR_ERR_UNSUPPORTED),
+    (_csr(np.arange(20001), np.arange(20000), np.ones(20000)), 1, 1, {}, aar.AAR_ERR_UNSUPPORTED),  # block too big
+])
+def test_csr_create_rejects(matrix, pc, nblocks, change, status):
+    """aar_create_csr checks the matrix and its arguments before any device work."""
+    prm = inputs.Params()
+    for k, v in change.items():
+        setattr(prm, k, v)
+    with pytest.raises(aar.AarError) as ei:
+        aar.aar_create_csr(*matrix, pc, nblocks, aar.make_params(prm))
+    assert ei.value.status == status
