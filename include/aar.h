@@ -5,8 +5,10 @@
  * method: an efficient alternative to preconditioned Krylov methods for
  * large, sparse linear systems", arXiv:1606.08740.  The solver applies the
  * fixed-point iteration x_{k+1} = x_k + B_k f_k of Sec. 2, Eqs. 2-3, with the
- * left-preconditioned residual f_k = M^{-1}(b - A x_k) (Eq. 6) and the Jacobi
- * preconditioner M = D = diag(A) (Sec. 2, the AAJ special case; Secs. 3.2-3.3):
+ * left-preconditioned residual f_k = M^{-1}(b - A x_k) (Eq. 6) and, for the
+ * stencil systems, the Jacobi preconditioner M = D = diag(A) (Sec. 2, the AAJ
+ * special case; Secs. 3.2-3.3; general sparse systems, aar_create_csr, also
+ * take block ILU(0), Secs. 3.1-3.3):
  *   - Richardson, B_k = omega I, when (k+1)/p is not a natural number;
  *   - Anderson, B_k = beta I - (X_k + beta F_k)(F_k^T F_k)^+ F_k^T, when it is,
  *     with X_k, F_k the last m iterate and residual differences (Eqs. 4-5)

@@ -606,7 +606,32 @@ struct CsrDev {
     int nblocks;
     int max_block_rows;
     int ilu;                 // 1: block ILU(0); 0: Jacobi (blocks are plain row chunks)
+    // packed substitution records (kp > 0): for position q of lrows (urows),
+    // the block-local row frow[q] (brow[q]) and kp slots of (block-local
+    // column, factor value) in increasing column order, padded with column
+    // -1; bdiag[q] = u_ii.  kp = 0: the substitutions walk the CSR arrays.
+    int kp;
+    const int16_t *frow, *fcol, *brow, *bcol;
+    const double *fval, *bval, *bdiag;
+    // > 0: the packed substitutions stage each block's level bounds in LDS
+    // after its values; lev_lds = the most levels of a block (forward plus
+    // backward) + 2
+    int lev_lds;
+    // levels the packed records are loaded ahead: 1, 2 or 4 (4 with kp = 4
+    // only)
+    int depth;
 };
+
+// Dynamic LDS of a block-ILU(0) pass: the block's values, then (packed
+// substitutions) its level bounds.
+inline size_t csr_lds_bytes(const CsrDev &c)
+{
+    return (size_t)c.max_block_rows * sizeof(double) + (size_t)c.lev_lds * sizeof(int32_t);
+}
+
+// Largest number of in-block entries per triangular row the packed records
+// hold.
+constexpr int kCsrMaxPack = 8;
 
 struct CsrArgs {
     CsrDev c;
@@ -627,5 +652,10 @@ struct CsrArgs {
 hipError_t prepare_csr_kernels();
 hipError_t launch_csr(int mode, const CsrArgs &a, hipStream_t s);
 hipError_t launch_ilu0(const CsrDev &c, int *bad, hipStream_t s);
+// Fill the packed records' values from the factors (after launch_ilu0):
+// fval/bval slot s of record q takes lu[fe/be[q kp + s]] (0 for padding),
+// bdiag[q] = lu[dpos[urows[q]]].
+hipError_t launch_pack_factors(const CsrDev &c, const int32_t *fe, const int32_t *be, double *fval, double *bval,
+                               double *bdiag, hipStream_t s);
 
 }  // namespace aar

@@ -1507,7 +1507,66 @@ struct CsrPlan {
     std::vector<int64_t> dpos, bstart;
     std::vector<int32_t> lrows, urows, lptr, uptr, blev_l, blev_u;
     int max_block_rows = 0;
+    // packed substitution records (kp slots per row; kp = 0: none): block-
+    // local rows and columns, and the CSR entry of each slot (-1: padding)
+    int kp = 0;
+    std::vector<int16_t> frow, fcol, brow, bcol;
+    std::vector<int32_t> fe, be;
 };
+
+// Packed records of the substitutions, in the order of lrows and urows:
+// each row's in-block entries below (above) the diagonal in increasing
+// column order.  Left empty (kp = 0) when a row has more than kCsrMaxPack
+// such entries or the entry indices exceed 32 bits.
+void pack_csr(int64_t n, const int64_t *rowptr, const int32_t *col, CsrPlan *pl)
+{
+    pl->kp = 0;
+    const int nblocks = (int)pl->bstart.size() - 1;
+    if (rowptr[n] > INT32_MAX)
+        return;
+    std::vector<int64_t> blk_lo(n);
+    for (int t = 0; t < nblocks; ++t)
+        for (int64_t i = pl->bstart[t]; i < pl->bstart[t + 1]; ++i)
+            blk_lo[i] = t;
+    int kl = 0, ku = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t lo = pl->bstart[blk_lo[i]], hi = pl->bstart[blk_lo[i] + 1];
+        int cl = 0, cu = 0;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            cl += col[e] >= lo && col[e] < i;
+            cu += col[e] > i && col[e] < hi;
+        }
+        kl = std::max(kl, cl);
+        ku = std::max(ku, cu);
+    }
+    const int k = std::max(kl, ku);
+    if (k > kCsrMaxPack)
+        return;
+    pl->kp = k <= 4 ? 4 : 8;
+    const int kp = pl->kp;
+    auto fill = [&](const std::vector<int32_t> &rows, bool upper, std::vector<int16_t> &prow,
+                    std::vector<int16_t> &pcol, std::vector<int32_t> &pe) {
+        prow.assign(n, -1);
+        pcol.assign((size_t)n * kp, -1);
+        pe.assign((size_t)n * kp, -1);
+        for (int64_t q = 0; q < n; ++q) {
+            const int64_t i = rows[q];
+            const int64_t lo = pl->bstart[blk_lo[i]], hi = pl->bstart[blk_lo[i] + 1];
+            prow[q] = (int16_t)(i - lo);
+            int sl = 0;
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+                const bool in = upper ? (col[e] > i && col[e] < hi) : (col[e] >= lo && col[e] < i);
+                if (!in)
+                    continue;
+                pcol[q * kp + sl] = (int16_t)(col[e] - lo);
+                pe[q * kp + sl] = (int32_t)e;
+                ++sl;
+            }
+        }
+    };
+    fill(pl->lrows, false, pl->frow, pl->fcol, pl->fe);
+    fill(pl->urows, true, pl->brow, pl->bcol, pl->be);
+}
 
 void plan_csr(int64_t n, const int64_t *rowptr, const int32_t *col, int nblocks, bool levels, CsrPlan *pl)
 {
@@ -2860,6 +2919,8 @@ aar_status aar_create_csr(aar_solver *out, int64_t n, const int64_t *rowptr, con
 
     CsrPlan pl;
     plan_csr(n, rowptr, col, nb, ilu, &pl);
+    if (ilu)
+        pack_csr(n, rowptr, col, &pl);
     const int64_t nnz = rowptr[n];
     st = AAR_OK;
     int64_t *d_rowptr = S->alloc<int64_t>(n + 1, &st);
@@ -2875,6 +2936,16 @@ aar_status aar_create_csr(aar_solver *out, int64_t n, const int64_t *rowptr, con
     int32_t *d_blevl = S->alloc<int32_t>(pl.blev_l.size(), &st);
     int32_t *d_blevu = S->alloc<int32_t>(pl.blev_u.size(), &st);
     int *d_bad = S->alloc<int>(1, &st);
+    const size_t pk = (size_t)n * pl.kp;
+    int16_t *d_frow = pl.kp ? S->alloc<int16_t>(n, &st) : nullptr;
+    int16_t *d_brow = pl.kp ? S->alloc<int16_t>(n, &st) : nullptr;
+    int16_t *d_fcol = pl.kp ? S->alloc<int16_t>(pk, &st) : nullptr;
+    int16_t *d_bcol = pl.kp ? S->alloc<int16_t>(pk, &st) : nullptr;
+    int32_t *d_fe = pl.kp ? S->alloc<int32_t>(pk, &st) : nullptr;
+    int32_t *d_be = pl.kp ? S->alloc<int32_t>(pk, &st) : nullptr;
+    double *d_fval = pl.kp ? S->alloc<double>(pk, &st) : nullptr;
+    double *d_bval = pl.kp ? S->alloc<double>(pk, &st) : nullptr;
+    double *d_bdiag = pl.kp ? S->alloc<double>(n, &st) : nullptr;
     const int64_t N = (n + 7) / 8 * 8;
     const int slots = params->m + 1;
     const int gblocks = gram_blocks(n, params->m);
@@ -2930,6 +3001,32 @@ aar_status aar_create_csr(aar_solver *out, int64_t n, const int64_t *rowptr, con
     c.nblocks = nb;
     c.max_block_rows = pl.max_block_rows;
     c.ilu = ilu ? 1 : 0;
+    c.kp = pl.kp;
+    c.depth = 1;
+    c.lev_lds = 0;
+    if (pl.kp) {
+        // the level bounds of the deepest block beside its values, if they fit
+        int most = 0;
+        for (int t = 0; t < nb; ++t)
+            most = std::max(most, (pl.blev_l[t + 1] - pl.blev_l[t]) + (pl.blev_u[t + 1] - pl.blev_u[t]) + 2);
+        if ((size_t)pl.max_block_rows * sizeof(double) + (size_t)most * sizeof(int32_t) <= kCsrMaxLds)
+            c.lev_lds = most;
+    }
+    c.frow = d_frow;
+    c.fcol = d_fcol;
+    c.brow = d_brow;
+    c.bcol = d_bcol;
+    c.fval = d_fval;
+    c.bval = d_bval;
+    c.bdiag = d_bdiag;
+    if (pl.kp) {
+        AAR_HIP(hipMemcpyAsync(d_frow, pl.frow.data(), sizeof(int16_t) * n, hipMemcpyHostToDevice, s));
+        AAR_HIP(hipMemcpyAsync(d_brow, pl.brow.data(), sizeof(int16_t) * n, hipMemcpyHostToDevice, s));
+        AAR_HIP(hipMemcpyAsync(d_fcol, pl.fcol.data(), sizeof(int16_t) * pk, hipMemcpyHostToDevice, s));
+        AAR_HIP(hipMemcpyAsync(d_bcol, pl.bcol.data(), sizeof(int16_t) * pk, hipMemcpyHostToDevice, s));
+        AAR_HIP(hipMemcpyAsync(d_fe, pl.fe.data(), sizeof(int32_t) * pk, hipMemcpyHostToDevice, s));
+        AAR_HIP(hipMemcpyAsync(d_be, pl.be.data(), sizeof(int32_t) * pk, hipMemcpyHostToDevice, s));
+    }
     if (ilu) {
         AAR_HIP(prepare_csr_kernels());
         // the factors: once, on the device
@@ -2940,6 +3037,49 @@ aar_status aar_create_csr(aar_solver *out, int64_t n, const int64_t *rowptr, con
         AAR_HIP(hipStreamSynchronize(s));
         if (bad)
             return fail(AAR_ERR_UNSUPPORTED, "ILU(0) meets a zero or non-finite pivot");
+        if (pl.kp) {
+            AAR_HIP(launch_pack_factors(c, d_fe, d_be, d_fval, d_bval, d_bdiag, s));
+            // prefetch depth of the packed substitutions: the fastest of three
+            // preconditioner passes each (the iterate buffers serve as input
+            // and output; their contents do not matter)
+            AAR_HIP(launch_fill_pattern_f64(P.xa, n, s));
+            hipEvent_t e0, e1;
+            AAR_HIP(hipEventCreate(&e0));
+            AAR_HIP(hipEventCreate(&e1));
+            float best = 0.0f;
+            int best_depth = 1;
+            bool timed = false;
+            // AAR_CSR_DEPTH fixes the depth instead (a tuning override, as the
+            // tile file is for stencils)
+            const char *fixed = std::getenv("AAR_CSR_DEPTH");
+            const int want = fixed ? std::atoi(fixed) : 0;
+            for (int d : {1, 2, 4}) {
+                if ((d == 4 && pl.kp != 4) || (want && d != want))
+                    continue;
+                c.depth = d;
+                CsrArgs a;
+                std::memset(&a, 0, sizeof(a));
+                a.c = c;
+                a.x = P.xa;
+                a.out = P.xb;
+                AAR_HIP(launch_csr(kPrecond, a, s));   // warm-up
+                AAR_HIP(hipEventRecord(e0, s));
+                for (int r = 0; r < 3; ++r)
+                    AAR_HIP(launch_csr(kPrecond, a, s));
+                AAR_HIP(hipEventRecord(e1, s));
+                AAR_HIP(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                AAR_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (!timed || ms < best) {
+                    best = ms;
+                    best_depth = d;
+                    timed = true;
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            c.depth = best_depth;
+        }
     }
     AAR_HIP(hipStreamSynchronize(s));
     P.hist = Prec::F64;

@@ -68,3 +68,11 @@ def test_byte_models():
 def test_complex_byte_model():
     # 5 sweeps x 64 + residual 48 + Gram 8 x 16 + update 16 + 128 + 16 + 32
     assert bench.complex_cycle_bytes(7, 6) == 5 * 64 + 48 + 128 + 192
+
+
+def test_csr_sweep_bytes():
+    """A's values, columns and row pointers once, x, b, new x and f, plus the
+    ILU(0) factors with their columns."""
+    import bench
+    assert bench.csr_sweep_bytes(10, 50) == 12 * 50 + 8 * 11 + 32 * 10
+    assert bench.csr_sweep_bytes(10, 50, 40) == bench.csr_sweep_bytes(10, 50) + 12 * 40

@@ -9,6 +9,9 @@ through the C ABI:
     paper's parameters m = 9, p = 8 and a shorter window);
   * full solves to the paper's 1e-6 and to 1e-10: iteration count, residual
     of the returned x by the oracle's product;
+  * both forms of the substitutions: packed per-row records (seven- and
+    five-point matrices) and the walk over the CSR arrays (rows with more
+    in-block entries than the records hold);
   * one-row blocks equal the Jacobi preconditioner; the largest block the
     LDS holds; a 1 x 1 system; a 262144-row reservoir matrix in 64 blocks.
 """
@@ -21,10 +24,33 @@ from tests.gpu_util import params, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
+def wide_rows(n: int, per_row: int, seed: int) -> inputs.CsrMatrix:
+    """A random nonsymmetric pattern with `per_row` off-diagonal entries per
+    row (more in-block entries per triangular row than the packed
+    substitution records hold, so the substitutions walk the CSR arrays),
+    strictly diagonally dominant."""
+    u = inputs.uniform(seed, 1, n * per_row).reshape(n, per_row)
+    v = inputs.normal(seed, 2, n * per_row).reshape(n, per_row)
+    rowptr, cols, vals = [0], [], []
+    for i in range(n):
+        # offsets within +-40 rows, so most entries fall inside a block
+        js = sorted({min(n - 1, max(0, i + int((u[i, s] - 0.5) * 80))) for s in range(per_row)} - {i})
+        row = {j: v[i, s] for s, j in enumerate(js)}
+        row[i] = sum(abs(x) for x in row.values()) + 1.0
+        for j in sorted(row):
+            cols.append(j)
+            vals.append(row[j])
+        rowptr.append(len(cols))
+    return inputs.CsrMatrix(np.array(rowptr, dtype=np.int64), np.array(cols, dtype=np.int32),
+                            np.array(vals, dtype=np.float64))
+
+
 MATRICES = {
     "reservoir_8": lambda: inputs.reservoir_matrix(8, seed=21),
     "reservoir_11": lambda: inputs.reservoir_matrix(11, seed=22, log_sigma=2.0),
     "convection_2d_20": lambda: inputs.convection_matrix_2d(20, 2.0),
+    "wide_rows_600": lambda: wide_rows(600, 24, 25),
+    "reservoir_16": lambda: inputs.reservoir_matrix(16, seed=26),
 }
 
 
@@ -85,6 +111,7 @@ ITER_CASES = [
     ("convection_2d_20", 1, 1, dict(m=4, p=3)),
     ("convection_2d_20", 1, 4, dict(m=9, p=8, flags=aar.AAR_FLAG_FORCE_PINV)),
     ("convection_2d_20", 1, 1, dict(m=5, p=1)),
+    ("wide_rows_600", 1, 3, dict(m=9, p=8)),
 ]
 
 
@@ -147,6 +174,25 @@ def test_one_row_blocks_equal_jacobi():
     xj, _, _ = run(A, prm, aar.AAR_PRECOND_JACOBI, 1, b, x0)
     xi, _, _ = run(A, prm, aar.AAR_PRECOND_ILU0, A.n, b, x0)
     np.testing.assert_array_equal(xi, xj)
+
+
+@pytest.mark.parametrize("depth", [1, 2, 4])
+def test_every_prefetch_depth_matches_oracle_bitwise(depth, monkeypatch):
+    """The packed substitutions load each level's records 1, 2 or 4 levels
+    ahead (chosen per matrix by timing at creation; AAR_CSR_DEPTH fixes it):
+    every depth gives the oracle's preconditioner bit for bit, with blocks
+    whose level bounds sit far into the level table, and with 2048 or more
+    blocks (one-wave workgroups)."""
+    monkeypatch.setenv("AAR_CSR_DEPTH", str(depth))
+    for name, nb in (("reservoir_11", 37), ("convection_2d_20", 5), ("reservoir_8", 512),
+                     ("reservoir_16", 2048), ("reservoir_16", 4096)):
+        A = MATRICES[name]()
+        say(f"csr precondition depth={depth} {name} nblocks={nb}")
+        r = inputs.normal(10, 1, A.n)
+        s = aar.CsrSolver(A, params(), aar.AAR_PRECOND_ILU0, nb)
+        z = s.precondition(to_dev(r)).cpu().numpy()
+        s.close()
+        np.testing.assert_array_equal(z, oracle.precondition(A, r, 1, nb))
 
 
 def test_largest_block_and_a_one_by_one_system():
