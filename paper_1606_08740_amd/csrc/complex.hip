@@ -11,10 +11,12 @@
 //   stencil passes   the one-point 2.5D tile of the real passes, instantiated
 //                    for the complex type (sweep, Anderson-step residual with
 //                    the |b - A x|^2 partials, operator apply);
-//   k_cgram          G = F^H F (upper triangle) and c = F^H f_k, columns of F
+//   Gram products   G = F^H F (upper triangle) and c = F^H f_k, columns of F
 //                    formed as differences of consecutive history slots,
-//                    products accumulated in FP64; per-workgroup partials,
-//                    summed in a fixed order by the real k_gram_finish;
+//                    products accumulated in FP64: the real parts by the real
+//                    k_gram over the interleaved vectors, the imaginary parts
+//                    by k_cgram_im; per-workgroup partials, summed in a fixed
+//                    order by k_gram_finish into [Re G, Re c | Im G, Im c];
 //   k_clsq           one wave: convergence test, gamma = G^+ c through the real
 //                    form [[Re G, -Im G], [Im G, Re G]] of the Hermitian G (the
 //                    one-wave Jacobi pseudoinverse of the real solve, with the
@@ -79,11 +81,21 @@ hipError_t launch_stencil_complex(int mode, int radius, const TileShape &ts, Ste
 // ---------------------------------------------------------------------------
 // Hermitian Gram products
 // ---------------------------------------------------------------------------
+// Imaginary parts of G = F^H F and c = F^H f_k.  The real parts,
+// Re(conj(a) b) = a_re b_re + a_im b_im summed over the points, are the real
+// Gram products of the history viewed as interleaved (re, im) vectors of
+// twice the length, which the real k_gram forms; this pass forms the rest:
+// Im G_cc2 = sum (dr_c di_c2 - di_c dr_c2) for c < c2 (the diagonal of a
+// Hermitian matrix is real: those entries stay exactly 0), and
+// Im c_c = sum (dr_c fi_k - di_c fr_k).  Entries in the real pass's order;
+// per-workgroup partials in the entry-major table k_gram_finish sums.  With a
+// full history the loads of the next point are issued before the products
+// of the current one.
 template <int MC>
-__global__ __launch_bounds__(kThreads) void k_cgram(const GramArgs a)
+__global__ __launch_bounds__(kThreads) void k_cgram_im(const GramArgs a)
 {
     constexpr int NP = MC * (MC + 1) / 2;
-    constexpr int NE = 2 * (NP + MC);            // doubles: (re, im) per entry
+    constexpr int NE = NP + MC;
     __shared__ double red[kThreads / 64][NE];
     const InstState *s = a.state;
     if (s->status != kRunning)
@@ -103,36 +115,57 @@ __global__ __launch_bounds__(kThreads) void k_cgram(const GramArgs a)
 #pragma unroll
     for (int e = 0; e < NE; ++e)
         acc[e] = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.N; i += stride) {
-        zd fv[MC + 1];
-#pragma unroll
-        for (int t = 0; t <= MC; ++t)
-            fv[t] = slot[t][i];
+    // products of one point: fv[0..MC] the history values, f_k at position
+    // fkpos, differences past the history length l are zero
+    auto accumulate = [&](const zd *fv, int lh) {
         zd fk = zd();
 #pragma unroll
         for (int t = 0; t <= MC; ++t)
-            fk = t == l ? fv[t] : fk;
+            fk = t == lh ? fv[t] : fk;
         zd d[MC];
 #pragma unroll
         for (int c = 0; c < MC; ++c)
-            d[c] = c < l ? fv[c + 1] - fv[c] : zd();
+            d[c] = c < lh ? fv[c + 1] - fv[c] : zd();
         int e = 0;
 #pragma unroll
         for (int c = 0; c < MC; ++c) {
+            ++e;   // diagonal: real
 #pragma unroll
-            for (int c2 = c; c2 < MC; ++c2) {
-                const zd g = conj(d[c]) * d[c2];
-                acc[2 * e] += g.re;
-                acc[2 * e + 1] += g.im;
-                ++e;
-            }
+            for (int c2 = c + 1; c2 < MC; ++c2)
+                acc[e++] += d[c].re * d[c2].im - d[c].im * d[c2].re;
         }
 #pragma unroll
-        for (int c = 0; c < MC; ++c) {
-            const zd g = conj(d[c]) * fk;
-            acc[2 * (NP + c)] += g.re;
-            acc[2 * (NP + c) + 1] += g.im;
+        for (int c = 0; c < MC; ++c)
+            acc[NP + c] += d[c].re * fk.im - d[c].im * fk.re;
+    };
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l == MC) {
+        zd cur[MC + 1], nxt[MC + 1];
+        if (i < a.N) {
+#pragma unroll
+            for (int t = 0; t <= MC; ++t)
+                cur[t] = slot[t][i];
+        }
+        for (; i < a.N; i += stride) {
+            const int64_t in = i + stride;
+            if (in < a.N) {
+#pragma unroll
+                for (int t = 0; t <= MC; ++t)
+                    nxt[t] = slot[t][in];
+            }
+            accumulate(cur, MC);
+#pragma unroll
+            for (int t = 0; t <= MC; ++t)
+                cur[t] = nxt[t];
+        }
+    } else {
+        for (; i < a.N; i += stride) {
+            zd fv[MC + 1];
+#pragma unroll
+            for (int t = 0; t <= MC; ++t)
+                fv[t] = slot[t][i];
+            accumulate(fv, l);
         }
     }
     const int w = threadIdx.x >> 6;
@@ -150,22 +183,22 @@ __global__ __launch_bounds__(kThreads) void k_cgram(const GramArgs a)
 // m x m solve has order 2m <= kMaxM)
 constexpr int kMaxComplexM = 8;
 
-hipError_t launch_cgram(const GramArgs &a, int blocks, hipStream_t s)
+hipError_t launch_cgram_im(const GramArgs &a, int blocks, hipStream_t s)
 {
     switch (a.m) {
-#define AAR_CG(M)                                                                          \
+#define AAR_CGI(M)                                                                         \
     case M:                                                                                \
-        hipLaunchKernelGGL((k_cgram<M>), dim3(blocks), dim3(kThreads), 0, s, a);           \
+        hipLaunchKernelGGL((k_cgram_im<M>), dim3(blocks), dim3(kThreads), 0, s, a);        \
         return hipGetLastError();
-        AAR_CG(1)
-        AAR_CG(2)
-        AAR_CG(3)
-        AAR_CG(4)
-        AAR_CG(5)
-        AAR_CG(6)
-        AAR_CG(7)
-        AAR_CG(8)
-#undef AAR_CG
+        AAR_CGI(1)
+        AAR_CGI(2)
+        AAR_CGI(3)
+        AAR_CGI(4)
+        AAR_CGI(5)
+        AAR_CGI(6)
+        AAR_CGI(7)
+        AAR_CGI(8)
+#undef AAR_CGI
     default:
         return hipErrorInvalidValue;
     }
@@ -212,7 +245,7 @@ __global__ __launch_bounds__(kLsqThreads) void k_clsq(const LsqArgs a, double om
     for (int idx = tid; idx < l * l; idx += kLsqThreads) {
         const int i = idx / l, j = idx % l;
         const int e = i <= j ? tri_index(i, j, a.m) : tri_index(j, i, a.m);
-        const double gr = a.gram_final[2 * e], gi0 = a.gram_final[2 * e + 1];
+        const double gr = a.gram_final[e], gi0 = a.gram_final[a.ne + e];
         const double gi = i <= j ? gi0 : -gi0;       // G_ji = conj(G_ij)
         bad = bad || !isfinite(gr) || !isfinite(gi);
         S[i][j] = gr;
@@ -221,8 +254,8 @@ __global__ __launch_bounds__(kLsqThreads) void k_clsq(const LsqArgs a, double om
         S[i + l][j + l] = gr;
     }
     for (int i = tid; i < l; i += kLsqThreads) {
-        cvec[i] = a.gram_final[2 * (np + i)];
-        cvec[i + l] = a.gram_final[2 * (np + i) + 1];
+        cvec[i] = a.gram_final[np + i];
+        cvec[i + l] = a.gram_final[a.ne + np + i];
         bad = bad || !isfinite(cvec[i]) || !isfinite(cvec[i + l]);
     }
     bad = __any(bad);

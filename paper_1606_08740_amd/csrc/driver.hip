@@ -242,6 +242,7 @@ struct aar_solver_t {
     bool cplx = false;
     double shift_im = 0.0, omega_im = 0.0, beta_im = 0.0;
     Path<zd> pz;
+    int cgram_re_blocks = 0;   // workgroups of the real-part Gram pass (2N values)
 
     // general sparse system (aar_create_csr): CSR arrays, block bounds,
     // level schedules and ILU(0) factors on the device; vectors in p64
@@ -737,10 +738,21 @@ hipError_t enqueue_cycle_complex(aar_solver_t *S, const Path<zd> &P, hipStream_t
     g.m = pa.m;
     g.p = pa.p;
     g.nslots = pa.m + 1;
-    g.ne = 2 * S->ne;
-    if ((e = launch_cgram(g, P.gram_blocks, s)) != hipSuccess)
+    g.ne = S->ne;
+    // real parts: the real Gram products of the interleaved (re, im) vectors
+    GramArgs gr = g;
+    gr.N = 2 * P.N;
+    gr.slot_stride = 2 * P.slot_stride;
+    double *part_im = S->part_gram + (size_t)S->cgram_re_blocks * S->ne;
+    if ((e = launch_gram(Prec::F64, gr, S->cgram_re_blocks, s)) != hipSuccess)
         return e;
-    if ((e = launch_gram_finish(S->part_gram, P.gram_blocks, S->gram_final, 2 * S->ne, S->state, pa.p, s)) !=
+    g.partial = part_im;
+    if ((e = launch_cgram_im(g, P.gram_blocks, s)) != hipSuccess)
+        return e;
+    if ((e = launch_gram_finish(S->part_gram, S->cgram_re_blocks, S->gram_final, S->ne, S->state, pa.p, s)) !=
+        hipSuccess)
+        return e;
+    if ((e = launch_gram_finish(part_im, P.gram_blocks, S->gram_final + S->ne, S->ne, S->state, pa.p, s)) !=
         hipSuccess)
         return e;
     LsqArgs l;
@@ -2809,7 +2821,11 @@ aar_status aar_create_complex(aar_solver *out, const aar_problem *problem, const
     S->state = S->alloc<InstState>(1, &st);
     S->part_rho = S->alloc<double>(z.max_stencil_blocks, &st);
     S->part_rho_cap = z.max_stencil_blocks;
-    S->part_gram = S->alloc<double>((size_t)std::max(z.gram_blocks, z.max_stencil_blocks) * 2 * z.ne, &st);
+    // Gram partials: the real-part pass over 2N values, then the imaginary-part pass
+    S->cgram_re_blocks = gram_blocks(2 * z.maxN, params->m);
+    S->part_gram = S->alloc<double>(
+        std::max((size_t)(S->cgram_re_blocks + gram_blocks(z.maxN, params->m)), (size_t)z.max_stencil_blocks) * z.ne,
+        &st);
     S->part_norm = S->alloc<double>(z.gram_blocks, &st);
     S->gram_final = S->alloc<double>(2 * z.ne, &st);
     S->scal = S->alloc<double>(8, &st);
