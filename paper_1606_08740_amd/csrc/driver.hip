@@ -1993,7 +1993,7 @@ aar_status batch_setup(aar_solver_t *S)
     AAR_HIP(hipMemcpyAsync(B.d_ntiles, B.ntiles.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
     AAR_HIP(hipMemcpyAsync(B.d_nchunks, B.nchunks.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
     AAR_HIP(hipMemcpyAsync(B.d_invshift, invshift.data(), sizeof(double) * count, hipMemcpyHostToDevice, s));
-    AAR_HIP(hipHostMalloc((void **)&B.h_remaining, sizeof(int), hipHostMallocDefault));
+    AAR_HIP(hipHostMalloc((void **)&B.h_remaining, 2 * sizeof(int), hipHostMallocDefault));
     AAR_HIP(hipStreamSynchronize(s));
     return AAR_OK;
 }
@@ -2379,6 +2379,14 @@ aar_status batch_solve(aar_solver_t *S, const double *b, double *x, const int64_
         (void)hipGraphDestroy(g);
         AAR_HIP(ce3);
     }
+    // Each round: the active systems' cycles (one graph replay), then the
+    // selection that counts the systems still running.  The count of round
+    // i is read only after round i + 1 has been queued behind it (two pinned
+    // slots, one event each), so the stream never drains between rounds.
+    // Work of a finished system is skipped by every kernel, so the one round
+    // queued after the last system finished changes nothing.
+    int slot = 0;
+    bool pending = false;
     for (;;) {
         AAR_HIPE(launch_compact(batch_compact_args(S, 0, true), s));
         if (use_graph) {
@@ -2389,12 +2397,17 @@ aar_status batch_solve(aar_solver_t *S, const double *b, double *x, const int64_
         }
         if ((e = select()) != AAR_OK)
             return e;
-        AAR_HIP(hipMemcpyAsync(B.h_remaining, B.remaining, sizeof(int), hipMemcpyDeviceToHost, s));
-        AAR_HIP(hipStreamSynchronize(s));
-        if (*B.h_remaining == 0)
-            break;
+        AAR_HIP(hipMemcpyAsync(B.h_remaining + slot, B.remaining, sizeof(int), hipMemcpyDeviceToHost, s));
+        AAR_HIP(hipEventRecord(S->poll_ev[slot], s));
+        if (pending) {
+            AAR_HIP(hipEventSynchronize(S->poll_ev[slot ^ 1]));
+            if (B.h_remaining[slot ^ 1] == 0)
+                break;   // every system had finished before this round
+        }
+        pending = true;
         if (S->mixed && (e = refine_body(false)) != AAR_OK)
             return e;
+        slot ^= 1;
     }
     // write the answers back in the caller's layout
     AAR_HIPE(launch_compact(batch_compact_args(S, 2, false), s));
