@@ -233,3 +233,32 @@ def test_large_reservoir_in_blocks():
     assert res["status"] == aar.AAR_OK and ref["status"] == oracle.OK
     assert abs(res["iterations"] - ref["iterations"]) <= 16
     assert oracle.relative_residual_csr(A, b, x) < 1e-6
+
+
+def test_bench_configuration_at_full_size():
+    """The bench's sparse workload at full size: the 128^3 reservoir matrix
+    (2097152 rows) with 1024 blocks.  The product and the preconditioner
+    equal the oracle's bit for bit on a random vector, and a short solve from
+    x0 = 1 (two cycles of the paper's parameters) follows the oracle's
+    iterate within the bound its own sensitivity sets."""
+    A = inputs.reservoir_matrix(128, seed=40)
+    r = inputs.normal(11, 1, A.n)
+    say("csr full size 128^3 apply / precondition")
+    prm = params(m=9, p=8, tol=1e-30, max_iter=16)
+    s = aar.CsrSolver(A, prm, aar.AAR_PRECOND_ILU0, 1024)
+    rt = to_dev(r)
+    np.testing.assert_array_equal(s.apply(rt).cpu().numpy(), oracle.csr_apply(A, r))
+    np.testing.assert_array_equal(s.precondition(rt).cpu().numpy(), oracle.precondition(A, r, 1, 1024))
+    b = inputs.normal(31, 1, A.n)
+    x0 = np.ones(A.n)
+    say("csr full size 128^3 solve to K=16")
+    xt = to_dev(x0)
+    res = s.solve(to_dev(b), xt)
+    x = xt.cpu().numpy()
+    s.close()
+    okw = dict(precond=1, nblocks=1024, m=9, p=8, max_iter=16)
+    ref = oracle.aar_solve_csr(A, b, x0=x0, tol=1e-30, **okw)
+    assert res["iterations"] == ref["iterations"] == 16
+    tol = step_tol(A, b, x0, ref, **okw)
+    assert tol < 1e-3, tol
+    np.testing.assert_allclose(x, ref["x"], rtol=0, atol=tol * np.abs(ref["x"]).max())
