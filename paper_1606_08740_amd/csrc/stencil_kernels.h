@@ -539,9 +539,12 @@ __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, 
     // ahead of its step, into register set i mod NB.  With an FP64 iterate and
     // ring NB = 2: they go two plane steps ahead, so each has two steps of taps
     // to arrive (the z loop is unrolled by two so that both sets keep fixed
-    // registers); the narrower types, which rely on more resident workgroups
+    // registers).  So do the FP32 sweeps over an FP32 ring (the recursion
+    // steps of the FP32-ring and mixed modes), whose registers leave room for
+    // it; the other narrower passes, which rely on more resident workgroups
     // instead, go one step ahead into one set.
-    constexpr int NB = sizeof(T) == 8 && sizeof(H) == 8 ? 2 : 1;
+    constexpr int NB =
+        (sizeof(T) == 8 && sizeof(H) == 8) || (sizeof(T) == 4 && sizeof(H) == 4 && MODE == kSweep) ? 2 : 1;
     V front[NB][RY], bv[NB][RY];
     T hv[NB][NH];
     auto fetch = [&](int i, int u) {
