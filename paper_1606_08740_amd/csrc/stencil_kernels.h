@@ -543,8 +543,10 @@ __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, 
     // steps of the FP32-ring and mixed modes), whose registers leave room for
     // it; the other narrower passes, which rely on more resident workgroups
     // instead, go one step ahead into one set.
-    constexpr int NB =
-        (sizeof(T) == 8 && sizeof(H) == 8) || (sizeof(T) == 4 && sizeof(H) == 4 && MODE == kSweep) ? 2 : 1;
+    constexpr int NB = (sizeof(T) == 8 && sizeof(H) == 8) ||
+                               (sizeof(H) == 4 && GM == 0 && (MODE == kSweep || MODE == kFk))
+                           ? 2
+                           : 1;
     V front[NB][RY], bv[NB][RY];
     T hv[NB][NH];
     auto fetch = [&](int i, int u) {
