@@ -2379,11 +2379,11 @@ aar_status batch_solve(aar_solver_t *S, const double *b, double *x, const int64_
         (void)hipGraphDestroy(g);
         AAR_HIP(ce3);
     }
-    // Each round: the active systems' cycles (one graph replay), then the
-    // selection that counts the systems still running.  The count of round
-    // i is read only after round i + 1 has been queued behind it (two pinned
-    // slots, one event each), so the stream never drains between rounds.
-    // Work of a finished system is skipped by every kernel, so the one round
+    // Each replay: the active systems' cycles (one graph launch), then the
+    // selection that counts the systems still running.  The count of replay
+    // i is read only after replay i + 1 has been queued behind it (two pinned
+    // slots, one event each), so the stream never drains between replays.
+    // Work of a finished system is skipped by every kernel, so the one replay
     // queued after the last system finished changes nothing.
     int slot = 0;
     bool pending = false;
@@ -2402,7 +2402,7 @@ aar_status batch_solve(aar_solver_t *S, const double *b, double *x, const int64_
         if (pending) {
             AAR_HIP(hipEventSynchronize(S->poll_ev[slot ^ 1]));
             if (B.h_remaining[slot ^ 1] == 0)
-                break;   // every system had finished before this round
+                break;   // every system had finished before this replay
         }
         pending = true;
         if (S->mixed && (e = refine_body(false)) != AAR_OK)
