@@ -112,6 +112,9 @@ ITER_CASES = [
     ("convection_2d_20", 1, 4, dict(m=9, p=8, flags=aar.AAR_FLAG_FORCE_PINV)),
     ("convection_2d_20", 1, 1, dict(m=5, p=1)),
     ("wide_rows_600", 1, 3, dict(m=9, p=8)),
+    ("reservoir_11", 1, 5, dict(m=12, p=5)),
+    ("reservoir_8", 0, 1, dict(m=16, p=3)),
+    ("convection_2d_20", 1, 2, dict(m=9, p=8, flags=aar.AAR_FLAG_NO_GRAPH)),
 ]
 
 
