@@ -100,7 +100,10 @@ enum { AAR_BC_ZERO_DIRICHLET = 0, AAR_BC_PERIODIC = 1 };
  *   AAR_MIXED_FP32: FP32 sweeps, history and Gram products (accumulated in
  *     FP64), FP64 m x m solve, and an outer FP64 iterative refinement:
  *     r = b - A x (FP64), inner FP32 AAR on A d = r/||r|| to inner_tol,
- *     x += ||r|| d, until ||b - A x|| / ||b|| < tol.  The outer test and the
+ *     x += ||r|| d, until ||b - A x|| / ||b|| < tol.  With inner_tol = 0 each
+ *     step's inner tolerance is max(3e-4, tol / (2 rel)), rel the FP64
+ *     relative residual the step starts from (three steps reach 1e-10; a
+ *     deeper FP32 target runs into the FP32 accuracy floor).  The outer test and the
  *     reported rel_residual use r formed from x and b in FP64.
  *   AAR_MIXED_FP32_BF16HIST: as AAR_MIXED_FP32 with the history columns
  *     stored in bfloat16 (round to nearest even). */
@@ -164,7 +167,7 @@ typedef struct {
     double tol;              /* on r_k = ||b - A x|| / ||b||, > 0                            */
     int64_t max_iter;        /* cap on iterations (inner iterations in mixed mode), >= 1    */
     int32_t precision;       /* AAR_FP64, AAR_MIXED_FP32(_BF16HIST), AAR_FP64_*HIST           */
-    double inner_tol;        /* mixed: inner FP32 tolerance (0 selects 1e-5)                 */
+    double inner_tol;        /* mixed: inner FP32 tolerance (0: per step, see AAR_MIXED_FP32) */
     int32_t max_outer;       /* mixed: cap on refinement steps (0 selects 30)                */
     uint32_t flags;          /* AAR_FLAG_*                                                   */
 } aar_params;

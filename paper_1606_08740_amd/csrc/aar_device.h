@@ -242,6 +242,22 @@ template <typename T> struct BatchStencilArgs {
 // ---- batched driver ----
 enum : int32_t { kPhaseStart = 0, kPhaseInner = 1, kPhaseDone = 2 };
 
+// Inner FP32 tolerance of one refinement step when none is given: each step
+// reduces the FP64 residual by at least kInnerTolDefault (three steps reach
+// 1e-10), and the last one only by what remains, half of tol / rel, where rel
+// is the FP64 relative residual the step starts from.  A deeper inner target
+// runs the FP32 solve into its accuracy floor, kappa(A) u_32, where its
+// iterations stop paying.
+constexpr double kInnerTolDefault = 3e-4;
+__host__ __device__ inline double inner_tolerance(double given, double tol, double rel)
+{
+    if (given > 0.0)
+        return given;
+    const double need = 0.5 * tol / rel;
+    const double eta = need > kInnerTolDefault ? need : kInnerTolDefault;
+    return eta < 0.5 ? eta : 0.5;
+}
+
 struct BatchCtl {            // per-system control of a batched solve
     int32_t phase;
     int32_t status;          // final aar status of the system

@@ -659,7 +659,7 @@ __global__ __launch_bounds__(64) void k_ctl_batched(const BatchCtlArgs a)
         st.cycle = 0;
         st.iters = 0;
         st.max_iter = a.max_iter - c.used;
-        st.tol = a.mixed ? a.inner_tol : a.tol;
+        st.tol = a.mixed ? inner_tolerance(a.inner_tol, a.tol, c.rel) : a.tol;
         st.status = kRunning;
         st.rank = 0;
         st.nb = sqrt(s);

@@ -1695,7 +1695,6 @@ aar_status solve_one(aar_solver_t *S, int idx, const double *b, double *x, aar_r
         S->last_log_count[idx] = 0;
         return AAR_OK;
     }
-    const double inner_tol = pa.inner_tol > 0.0 ? pa.inner_tol : 1e-5;
     const int max_outer = pa.max_outer > 0 ? pa.max_outer : 30;
     const bool recycle = (pa.flags & AAR_FLAG_RECYCLE_HISTORY) != 0;
     int64_t used = 0;
@@ -1734,6 +1733,7 @@ aar_status solve_one(aar_solver_t *S, int idx, const double *b, double *x, aar_r
             break;
         }
         // inner FP32 AAR on A d = r / ||r||, d_0 = 0
+        const double inner_tol = inner_tolerance(pa.inner_tol, pa.tol, rel);
         AAR_HIP(launch_cast_f64_to_f32(S->r64, P.b, N, S->scal, s));
         AAR_HIP(launch_zero_f32(P.xa, N, s));
         AAR_HIP(launch_norm_partial(false, P.b, N, S->part_norm, nb_blocks, s));
@@ -2049,7 +2049,7 @@ BatchCtlArgs batch_ctl(aar_solver_t *S, int step, const double *partial, bool de
     c.max_outer = pa.max_outer > 0 ? pa.max_outer : 30;
     c.max_iter = pa.max_iter;
     c.tol = pa.tol;
-    c.inner_tol = pa.inner_tol > 0.0 ? pa.inner_tol : 1e-5;
+    c.inner_tol = pa.inner_tol;   // 0: the per-step rule of inner_tolerance
     c.ctl = B.ctl;
     c.state = B.state;
     c.refine = B.refine;

@@ -122,7 +122,7 @@ class Params:
     tol: float = 1e-10
     max_iter: int = 1_000_000
     precision: int = 0          # 0 fp64, 1 mixed fp32, 2 mixed fp32 + bf16 history, 3/4 fp64 + fp32/bf16 history
-    inner_tol: float = 1e-5
+    inner_tol: float = 0.0      # 0: the library's per-step rule
     max_outer: int = 30
     flags: int = 0
 
