@@ -84,9 +84,10 @@ __device__ __attribute__((always_inline)) inline void load_packed(const int16_t 
 // One triangular sweep over packed records, level by level.  A thread's
 // records for its first row of level lv are loaded D levels ahead into a
 // register ring (they do not depend on the values being computed), and the
-// level bounds come from LDS when they fit, so a level costs an LDS round
-// trip and a barrier once the loads are in flight early enough.  Deeper
-// rings hold more registers; the driver picks D per matrix by timing.
+// level bounds come from LDS when they fit, so no level waits on a global
+// load once the ring is deep enough; what remains per level is its chain of
+// LDS reads, dependent FP64 updates and the LDS write.  Deeper rings hold
+// more registers; the driver picks D per matrix by timing.
 // UPPER: divide by u_ii (diag) after the subtractions.
 
 // ptr[lv - pbase] is the first record of level lv.
@@ -178,9 +179,8 @@ __device__ __attribute__((always_inline)) inline void substitute_packed(const Cs
     }
 }
 
-// TPB threads per workgroup: 256 for Jacobi row chunks, 64 (one wave) for
-// block ILU(0), whose levels hold few rows each and whose per-level barrier
-// then costs one wave nothing.
+// TPB threads per workgroup: 256, or 64 (one wave) for block ILU(0) with
+// many small blocks (launch_one gives the rule).
 template <int MODE, bool ILU, int TPB> __global__ __launch_bounds__(TPB) void k_csr(const CsrArgs a)
 {
 #pragma clang fp contract(off)
