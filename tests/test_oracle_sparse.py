@@ -248,3 +248,37 @@ def test_zero_rhs_and_bad_matrices():
     with pytest.raises(ZeroDivisionError):
         oracle.ilu0(singular, 1)
     assert oracle.aar_solve_csr(singular, np.ones(2))["status"] == oracle.BREAKDOWN
+
+
+def random_pattern(n: int, per_row: int, seed: int) -> inputs.CsrMatrix:
+    """A random nonsymmetric pattern (per_row off-diagonal entries per row
+    at seeded positions), strictly diagonally dominant so that no pivot
+    vanishes."""
+    u = inputs.uniform(seed, 1, n * per_row).reshape(n, per_row)
+    v = inputs.normal(seed, 2, n * per_row).reshape(n, per_row)
+    D = np.zeros((n, n))
+    for i in range(n):
+        for s in range(per_row):
+            D[i, min(n - 1, int(u[i, s] * n))] += v[i, s]
+        D[i, i] = 0.0
+        D[i, i] = np.abs(D[i]).sum() + 1.0
+    return csr_from_dense(D)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_ilu0_defining_property_on_random_patterns(seed):
+    """(L U)_ij = a_ij on every block's pattern, and z = M^-1 (M z), for
+    random nonsymmetric patterns and block counts."""
+    rng = inputs.uniform(200 + seed, 0, 3)
+    n = 20 + int(rng[0] * 40)
+    A = random_pattern(n, 1 + int(rng[1] * 5), 300 + seed)
+    nblocks = 1 + int(rng[2] * 6)
+    lu = oracle.ilu0(A, nblocks)
+    L, U = factors(A, lu, nblocks)
+    M = L @ U
+    D = A.to_dense()
+    P = in_block_pattern(A, nblocks)
+    np.testing.assert_allclose(M[P], D[P], rtol=0, atol=1e-12 * np.abs(D).max())
+    z = inputs.normal(400 + seed, 0, n)
+    np.testing.assert_allclose(oracle.precondition(A, M @ z, oracle.PRECOND_ILU0, nblocks), z, rtol=1e-10,
+                               atol=1e-10 * np.abs(z).max())
