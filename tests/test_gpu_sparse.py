@@ -115,6 +115,7 @@ ITER_CASES = [
     ("reservoir_11", 1, 5, dict(m=12, p=5)),
     ("reservoir_8", 0, 1, dict(m=16, p=3)),
     ("convection_2d_20", 1, 2, dict(m=9, p=8, flags=aar.AAR_FLAG_NO_GRAPH)),
+    ("reservoir_11", 1, 3, dict(m=2, p=8)),   # a ring shorter than a cycle
 ]
 
 
