@@ -4,7 +4,9 @@ For each evaluation workload at full size, the FP64 oracle (Jacobi AAR,
 Eqs. 2-6) is run to its tolerance; the file keeps the iteration count, the
 final relative residual, the oracle's wall time and thread count, and the
 solution at 64 seeded sample points (mean-free for singular periodic
-Poisson systems).  GPU tests compare full-size solves against these values.
+Poisson systems).  The same is kept for the complex OF-DFT Helmholtz
+workloads and the sparse reservoir matrix (Jacobi and block ILU(0)).  GPU
+tests and the benchmark compare full-size solves against these values.
 
 Usage: python tests/golden/make_golden.py [name ...]
 """
@@ -32,6 +34,18 @@ CASES = {
 }
 
 
+# the complex OF-DFT Helmholtz workloads (Eq. 7) and the sparse reservoir
+# matrix (CSR, Jacobi and block ILU(0)) the benchmark times
+COMPLEX_CASES = {
+    "ofdft_helmholtz_72": lambda: inputs.ofdft_helmholtz(72, cells=1),
+    "ofdft_helmholtz_144": lambda: inputs.ofdft_helmholtz(144, cells=2),
+}
+SPARSE_CASES = {
+    "reservoir_128_jacobi": (oracle.PRECOND_JACOBI, 1),
+    "reservoir_128_block_ilu0_1024": (oracle.PRECOND_ILU0, 1024),
+}
+
+
 def sample_indices(size, count=64, seed=77):
     u = inputs.uniform(seed, 0, count)
     return sorted(set(int(v * size) for v in u))
@@ -55,11 +69,45 @@ def run(name):
             "x_norm": float(np.linalg.norm(x)), "seconds": dt, "threads": oracle.threads()}
 
 
+def run_complex(name):
+    prob, s_im, b, prm = COMPLEX_CASES[name]()
+    t0 = time.time()
+    out = oracle.aar_solve_complex(prob, b, s_im, m=prm.m, p=prm.p, tol=prm.tol, omega=prm.omega, beta=prm.beta)
+    dt = time.time() - t0
+    x = out["x"]
+    idx = sample_indices(prob.size)
+    return {"workload": name, "n": list(prob.n), "radius": prob.radius, "m": prm.m, "p": prm.p,
+            "tol": prm.tol, "status": out["status"], "iterations": out["iterations"], "relres": out["relres"],
+            "sample_index": idx, "sample_re": [float(x[i].real) for i in idx],
+            "sample_im": [float(x[i].imag) for i in idx], "x_rms": float(np.sqrt(np.mean(np.abs(x) ** 2))),
+            "seconds": dt, "threads": oracle.threads()}
+
+
+def run_sparse(name):
+    """The benchmark's sparse system: the 128^3 reservoir matrix (seed 40),
+    b ~ N(0,1) (seed 31, stream 1), x0 = 1, the paper's omega = beta = 0.6,
+    m = 9, p = 8, tol 1e-6."""
+    precond, nblocks = SPARSE_CASES[name]
+    A = inputs.reservoir_matrix(128, seed=40)
+    b = inputs.normal(31, 1, A.n)
+    t0 = time.time()
+    out = oracle.aar_solve_csr(A, b, x0=np.ones(A.n), precond=precond, nblocks=nblocks, omega=0.6, beta=0.6,
+                               m=9, p=8, tol=1e-6)
+    dt = time.time() - t0
+    x = out["x"]
+    idx = sample_indices(A.n)
+    return {"workload": name, "rows": A.n, "nnz": A.nnz, "m": 9, "p": 8, "tol": 1e-6, "status": out["status"],
+            "iterations": out["iterations"], "relres": out["relres"], "sample_index": idx,
+            "sample_x": [float(x[i]) for i in idx], "x_rms": float(np.sqrt(np.mean(x ** 2))), "seconds": dt,
+            "threads": oracle.threads()}
+
+
 def main(names):
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
-    for name in names or list(CASES):
+    for name in names or list(CASES) + list(COMPLEX_CASES) + list(SPARSE_CASES):
         print(f"running {name}", flush=True)
-        data[name] = run(name)
+        data[name] = (run_complex(name) if name in COMPLEX_CASES else
+                      run_sparse(name) if name in SPARSE_CASES else run(name))
         print(f"  {data[name]['iterations']} iterations, relres {data[name]['relres']:.3e}, "
               f"{data[name]['seconds']:.1f} s", flush=True)
         with open(OUT, "w") as f:
