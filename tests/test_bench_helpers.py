@@ -76,3 +76,14 @@ def test_csr_sweep_bytes():
     import bench
     assert bench.csr_sweep_bytes(10, 50) == 12 * 50 + 8 * 11 + 32 * 10
     assert bench.csr_sweep_bytes(10, 50, 40) == bench.csr_sweep_bytes(10, 50) + 12 * 40
+
+
+@pytest.mark.parametrize("key", ["ofdft_helmholtz_72", "ofdft_helmholtz_144", "reservoir_128_jacobi",
+                                 "reservoir_128_block_ilu0_1024", "periodic_poisson_r6_256"])
+def test_stored_oracle_solutions_are_converged(key):
+    """Every stored full-size oracle solution the benchmark compares against
+    converged to its tolerance and keeps 64 seeded sample points."""
+    g = json.load(open(GOLDEN))[key]
+    assert g["status"] == 0 and g["relres"] < g["tol"]
+    assert len(g["sample_index"]) == 64
+    assert g["iterations"] > 0
