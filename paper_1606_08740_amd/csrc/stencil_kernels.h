@@ -25,7 +25,8 @@
 // Tiling (2.5D): a workgroup of 64 x 4 threads owns a 64 x (4 RY) tile of one
 // xy-plane and marches through `cz` planes along z.  Each thread keeps its
 // column's 2r+1 z-values in registers (a queue advanced once per plane), and
-// the current plane plus an r-wide halo sits in LDS for the x and y taps.  So
+// the current plane plus an r-wide halo sits in LDS for the x and y taps (two
+// plane buffers used in turn, so each plane step needs one barrier).  So
 // every interior value is fetched from global memory once per pass; halos
 // are re-fetched from L2.  The loads of the next plane steps are in flight
 // while plane z is computed, so memory latency overlaps the taps.  Tiles are
@@ -69,7 +70,8 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs<T> &a, int lin, d
     constexpr int kHaloRows = 2 * R * LX;
     constexpr int kHalo = kHaloRows + TY * 2 * R;
     constexpr int NH = (kHalo + kThreads - 1) / kThreads;
-    __shared__ T sh[LY][LX];
+    // two plane buffers: step i writes buffer i & 1 (see the step below)
+    __shared__ T sh[2][LY][LX];
     __shared__ double red[kWY];
 
     const StencilDev<T> &st = a.st;
@@ -235,14 +237,18 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs<T> &a, int lin, d
 #pragma unroll
         for (int ry = 0; ry < RY; ++ry)
             q[ry][2 * R] = front[u][ry];
-        __syncthreads();   // the previous plane's taps have been read
+        // Plane i goes to LDS buffer i & 1.  Its last readers were the taps
+        // of step i - 2, which every thread finished before the barrier of
+        // step i - 1, so one barrier per step suffices.
+        // (with two register sets, steps of set u have i & 1 == u)
+        T(&sp)[LY][LX] = sh[kDepth == 2 ? u : (i & 1)];
 #pragma unroll
         for (int ry = 0; ry < RY; ++ry)
-            sh[R + ty + ry * kWY][R + tx] = q[ry][R];
+            sp[R + ty + ry * kWY][R + tx] = q[ry][R];
 #pragma unroll
         for (int j = 0; j < NH; ++j)
             if (hlds[j] >= 0)
-                (&sh[0][0])[hlds[j]] = hv[u][j];
+                (&sp[0][0])[hlds[j]] = hv[u][j];
         __syncthreads();
         T bcur[RY], vcur[CONV ? 3 * RY : 1];
 #pragma unroll
@@ -265,16 +271,16 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs<T> &a, int lin, d
                 ax = st.diag * c;
 #pragma unroll
                 for (int s = 1; s <= R; ++s) {
-                    ax += st.c0[s] * (sh[ly][lx + s] + sh[ly][lx - s]);
-                    ax += st.c1[s] * (sh[ly + s][lx] + sh[ly - s][lx]);
+                    ax += st.c0[s] * (sp[ly][lx + s] + sp[ly][lx - s]);
+                    ax += st.c1[s] * (sp[ly + s][lx] + sp[ly - s][lx]);
                     ax += st.c2[s] * (q[ry][R + s] + q[ry][R - s]);
                 }
             } else {
                 ax = st.sigma * c;
 #pragma unroll
                 for (int s = 1; s <= R; ++s) {
-                    ax += st.c0[s] * ((sh[ly][lx + s] - c) + (sh[ly][lx - s] - c));
-                    ax += st.c1[s] * ((sh[ly + s][lx] - c) + (sh[ly - s][lx] - c));
+                    ax += st.c0[s] * ((sp[ly][lx + s] - c) + (sp[ly][lx - s] - c));
+                    ax += st.c1[s] * ((sp[ly + s][lx] - c) + (sp[ly - s][lx] - c));
                     ax += st.c2[s] * ((q[ry][R + s] - c) + (q[ry][R - s] - c));
                 }
             }
@@ -284,8 +290,8 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs<T> &a, int lin, d
             T dg = st.jdiag;
             if constexpr (CONV) {
                 const T v0 = vcur[3 * ry], v1 = vcur[3 * ry + 1], v2 = vcur[3 * ry + 2];
-                ax += v0 > T(0) ? -v0 * st.ih0 * (sh[ly][lx - 1] - c) : v0 * st.ih0 * (sh[ly][lx + 1] - c);
-                ax += v1 > T(0) ? -v1 * st.ih1 * (sh[ly - 1][lx] - c) : v1 * st.ih1 * (sh[ly + 1][lx] - c);
+                ax += v0 > T(0) ? -v0 * st.ih0 * (sp[ly][lx - 1] - c) : v0 * st.ih0 * (sp[ly][lx + 1] - c);
+                ax += v1 > T(0) ? -v1 * st.ih1 * (sp[ly - 1][lx] - c) : v1 * st.ih1 * (sp[ly + 1][lx] - c);
                 const T zm = dir > 0 ? q[ry][R - 1] : q[ry][R + 1];   // plane z - 1
                 const T zp = dir > 0 ? q[ry][R + 1] : q[ry][R - 1];   // plane z + 1
                 ax += v2 > T(0) ? -v2 * st.ih2 * (zm - c) : v2 * st.ih2 * (zp - c);
@@ -389,7 +395,8 @@ __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, 
     constexpr int kHalo = kHaloRows + TY * 2 * R;
     constexpr int NH = (kHalo + kThr - 1) / kThr;
     constexpr int Q = 2 * R + 1;
-    __shared__ __align__(16) T sh[LY][LX];
+    // two plane buffers: step i writes buffer i & 1 (see the z loop)
+    __shared__ __align__(16) T sh[2][LY][LX];
     __shared__ double red[NW];
     constexpr int GNE = GM > 0 ? GM * (GM + 1) / 2 + GM : 1;
     __shared__ double gred[GM > 0 ? NW : 1][GNE];
@@ -590,18 +597,22 @@ __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, 
 #pragma unroll
         for (int r = 0; r < RY; ++r)
             bcur[r] = bv[u][r];
-        __syncthreads();   // the previous plane's taps have been read
+        // Plane i goes to LDS buffer i & 1.  Its last readers were the taps
+        // of step i - 2, which every thread finished before the barrier of
+        // step i - 1, so one barrier per step suffices.
+        // (with an even number of register sets, i & 1 == u & 1)
+        const int bi = NB % 2 == 0 ? (u & 1) : (i & 1);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             V c;
             c.x = q[r][0][R];
             c.y = q[r][1][R];
-            *reinterpret_cast<V *>(&sh[R + lr * RY + r][RP + 2 * lx2]) = c;
+            *reinterpret_cast<V *>(&sh[bi][R + lr * RY + r][RP + 2 * lx2]) = c;
         }
 #pragma unroll
         for (int j = 0; j < NH; ++j)
             if (hlds[j] >= 0)
-                (&sh[0][0])[hlds[j]] = hv[u][j];
+                (&sh[bi][0][0])[hlds[j]] = hv[u][j];
         __syncthreads();
         if (i + NB < nz)
             fetch(i + NB, u);   // set u's plane is in the queue, LDS and bcur now
@@ -614,7 +625,7 @@ __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, 
             T v[2 * RP + 2];
 #pragma unroll
             for (int t = 0; t <= RP; ++t) {
-                const V w = *reinterpret_cast<const V *>(&sh[ly][2 * lx2 + 2 * t]);
+                const V w = *reinterpret_cast<const V *>(&sh[bi][ly][2 * lx2 + 2 * t]);
                 v[2 * t] = w.x;
                 v[2 * t + 1] = w.y;
             }
@@ -645,7 +656,7 @@ __device__ __forceinline__ void stencil_tile2(const StencilArgs<T> &a, int lin, 
                     col[t].x = q[t - R][0][R];
                     col[t].y = q[t - R][1][R];
                 } else {
-                    col[t] = *reinterpret_cast<const V *>(&sh[lr * RY + t][RP + 2 * lx2]);
+                    col[t] = *reinterpret_cast<const V *>(&sh[bi][lr * RY + t][RP + 2 * lx2]);
                 }
             }
 #pragma unroll
