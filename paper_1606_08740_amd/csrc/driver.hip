@@ -2775,6 +2775,98 @@ aar_status aar_solve_noalloc(const aar_problem *problem, const aar_params *param
     return solve_noalloc(problem, params, b, x, r, hip_stream);
 }
 
+// Tile of the complex sweep (one-point layout, at most 2 rows per thread):
+// the tile file's line for the grid with precision field 2, else the fastest
+// candidate (rows per thread 1 or 2, z depths 2 .. 32, every tile order)
+// timed on the solver's own buffers, which every solve overwrites.  A small
+// grid needs short z chunks to fill the chip.  The choice is kept per grid
+// for the process.
+aar_status tune_complex_tile(aar_solver_t *S, const aar_problem &pr, Path<zd> &P)
+{
+    const auto key = std::make_tuple(2, pr.radius, 0, pr.n[0], pr.n[1], pr.n[2]);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        load_tune_file();
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end() && it->second.pair == 0 && it->second.tb == 0) {
+            P.ts = it->second;
+            P.ts.ry = std::min(P.ts.ry, 2);
+            return AAR_OK;
+        }
+    }
+    hipStream_t s = S->stream;
+    const int64_t N = P.N;
+    AAR_HIP(launch_fill_pattern_f64(reinterpret_cast<double *>(P.xa), 2 * N, s));
+    AAR_HIP(launch_fill_pattern_f64(reinterpret_cast<double *>(P.b), 2 * N, s));
+    const int nb_blocks = stream_blocks(N);
+    AAR_HIP(launch_cnorm_partial(P.b, N, S->part_norm, nb_blocks, s));
+    AAR_HIP(launch_init_state(S->state, S->part_norm, nb_blocks, (int64_t)1 << 40, 1.0, s));
+    StencilArgs<zd> a;
+    std::memset(&a, 0, sizeof(a));
+    a.st = P.st;
+    a.b = P.b;
+    a.fring = P.fring;
+    a.state = S->state;
+    a.slot_stride = P.slot_stride;
+    a.p = S->params.p;
+    a.nslots = S->params.m + 1;
+    a.omega = zd(S->params.omega, S->omega_im);
+    a.j = 0;
+    a.x = P.xa;
+    a.out = P.xb;
+    std::vector<TileShape> cands;
+    for (int ry : {1, 2}) {
+        int prev_tz = -1;
+        for (int cz : {2, 4, 6, 8, 12, 16, 24, 32}) {
+            int tx, ty, tz, blocks;
+            stencil_grid(pr.n[0], pr.n[1], pr.n[2], TileShape{ry, cz, 0}, &tx, &ty, &tz, &blocks);
+            if (tz == prev_tz || blocks > S->part_rho_cap)
+                continue;
+            prev_tz = tz;
+            for (int order = 0; order < (tz > 1 ? 4 : 1); ++order)
+                cands.push_back(TileShape{ry, cz, order, 0});
+        }
+    }
+    hipEvent_t e0, e1;
+    AAR_HIP(hipEventCreate(&e0));
+    AAR_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    TileShape best = P.ts;
+    hipError_t e = hipSuccess;
+    for (const TileShape &ts : cands) {
+        for (int w = 0; w < 3 && e == hipSuccess; ++w)
+            e = launch_stencil_complex(kSweep, P.radius, ts, a, nullptr, s);
+        if (e == hipSuccess)
+            e = hipEventRecord(e0, s);
+        for (int w = 0; w < 10 && e == hipSuccess; ++w)
+            e = launch_stencil_complex(kSweep, P.radius, ts, a, nullptr, s);
+        if (e == hipSuccess)
+            e = hipEventRecord(e1, s);
+        if (e == hipSuccess)
+            e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess)
+            break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = ts;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess)
+        return fail(AAR_ERR_DEVICE, std::string("complex tile timing: ") + hipGetErrorString(e));
+    P.ts = best;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        g_tune_cache[key] = best;
+    }
+    append_tune_file(key, best);
+    return AAR_OK;
+}
+
 aar_status aar_create_complex(aar_solver *out, const aar_problem *problem, const aar_params *params,
                               double shift_imag, double omega_imag, double beta_imag, void *hip_stream)
 {
@@ -2860,9 +2952,6 @@ aar_status aar_create_complex(aar_solver *out, const aar_problem *problem, const
     P.radius = problem->radius;
     P.conv = false;
     P.ts = op.ts[0];
-    int tx, ty, tz, blocks;
-    stencil_grid(problem->n[0], problem->n[1], problem->n[2], P.ts, &tx, &ty, &tz, &blocks);
-    P.rho_blocks = blocks;
     P.gram_blocks = gram_blocks(op.N, params->m);
     P.upd_blocks = stream_blocks(op.N);
     P.slot_stride = N;
@@ -2873,6 +2962,12 @@ aar_status aar_create_complex(aar_solver *out, const aar_problem *problem, const
     P.st.diag = zd(op.diag, shift_imag);
     P.st.jdiag = zd(op.jdiag, shift_imag);
     P.st.inv_diag = zd(1.0) / P.st.jdiag;
+    if ((st = tune_complex_tile(S.get(), *problem, P)) != AAR_OK)
+        return st;
+    S->ops[0].ts[0] = P.ts;
+    int tx, ty, tz, blocks;
+    stencil_grid(problem->n[0], problem->n[1], problem->n[2], P.ts, &tx, &ty, &tz, &blocks);
+    P.rho_blocks = blocks;
     if (P.rho_blocks > S->part_rho_cap)
         return fail(AAR_ERR_DEVICE, "stencil grid exceeds the partial-sum workspace");
     *out = S.release();

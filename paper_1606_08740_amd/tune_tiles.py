@@ -29,8 +29,9 @@ import tempfile
 import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-HEADER = ("# prec radius conv n0 n1 n2 rows_per_thread z_depth order pair depth  (prec 0 = FP64, 1 = FP32; "
-          "grid 0 0 0: the batched engine; depth: temporal block of recursion steps, 0 = one pass per step)\n")
+HEADER = ("# prec radius conv n0 n1 n2 rows_per_thread z_depth order pair depth  (prec 0 = FP64, 1 = FP32, "
+          "2 = complex FP64 sweep, timed at creation; grid 0 0 0: the batched engine; depth: temporal block of "
+          "recursion steps, 0 = one pass per step)\n")
 
 
 def workloads():

@@ -10,7 +10,9 @@ through the C ABI:
     sixth-order periodic FD): residual by the oracle's operator, iteration
     count, answer and the first Anderson-step residuals;
   * a Fourier-mode right-hand side (parallel history columns): the Hermitian
-    pseudoinverse truncates and the extrapolation is exact.
+    pseudoinverse truncates and the extrapolation is exact;
+  * every tile shape the creation-time timing of the complex sweep can pick,
+    forced through a tile file: operator and iterates.
 """
 import numpy as np
 import pytest
@@ -135,3 +137,35 @@ def test_fourier_mode_truncates_and_is_exact():
     assert log[1] < 1e-12 * log[0]
     lam = oracle.apply_complex(prob, s_im, b)[0] / b[0]
     np.testing.assert_allclose(x, b / lam, rtol=0, atol=1e-11 * abs(1 / lam))
+
+
+TILE_CASES = [(1, 2, 0), (1, 4, 2), (2, 2, 3), (1, 6, 1), (2, 32, 0)]
+
+
+@pytest.mark.parametrize("shape", TILE_CASES, ids=[f"ry{s[0]}_cz{s[1]}_order{s[2]}" for s in TILE_CASES])
+def test_complex_tile_shapes_match_oracle(shape, tmp_path, monkeypatch):
+    """The complex sweep's tile is timed at creation unless the tile file
+    lists the grid (precision field 2); every shape the timing can pick
+    (rows per thread, short z chunks with a ragged last one, tile numbering
+    and z direction) gives the oracle's operator and iterates."""
+    ry, cz, order = shape
+    prob = inputs.Problem(n=(70, 13, 23), h=(0.1, 0.2, 0.15), bc=(1, 1, 1), radius=3, diffusion=1 / (4 * np.pi),
+                          shift=-0.135)
+    s_im = -0.07
+    tile = tmp_path / "tiles.txt"
+    tile.write_text(f"2 {prob.radius} 0 {prob.n[0]} {prob.n[1]} {prob.n[2]} {ry} {cz} {order} 0 0\n")
+    monkeypatch.setenv("AAR_TUNE_CACHE", str(tile))
+    say(f"complex tile shape {shape} n={prob.n}")
+    x = cnormal(21, prob.size)
+    s = aar.ComplexSolver(prob, params(), s_im)
+    y = s.apply(to_dev_c(x)).cpu().numpy()
+    s.close()
+    ref = oracle.apply_complex(prob, s_im, x)
+    scale = (np.abs(oracle.diagonal(prob)).max() + abs(s_im)) * np.abs(x).max()
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-13 * scale)
+    b = cnormal(5, prob.size)
+    for K in (5, 7, 13):
+        xs, res, _, _ = csolve(prob, params(max_iter=K, tol=1e-30, m=7, p=6), s_im, b, 0.6, 0.6)
+        refx = oracle.aar_solve_complex(prob, b, s_im, omega=0.6, beta=0.6, m=7, p=6, tol=1e-30, max_iter=K)["x"]
+        assert res["iterations"] == K
+        np.testing.assert_allclose(xs, refx, rtol=0, atol=1e-10 * np.abs(refx).max(), err_msg=f"K={K}")
