@@ -1141,8 +1141,10 @@ void append_tune_file(const std::tuple<int, int, int, int, int, int> &key, const
 
 // Tile of the FP32 passes from the tile file, without timing candidates
 // (the FP32 recursion passes of an FP64 iteration over an FP32 ring, whose
-// solver holds no FP32 vectors to time them on); keeps the default shape
-// when the grid is not listed.
+// solver holds no FP32 vectors to time them on).  A grid the file does not
+// list takes the FP64 shape timed for it (every FP64 shape is a valid FP32
+// one; temporal blocks are not used for these passes), which fills the chip
+// as the fixed default shape may not on a small grid.
 void cached_tile32(Operator &op)
 {
     const auto key = std::make_tuple(1, op.prob.radius, op.prob.velocity != nullptr ? 1 : 0, op.prob.n[0],
@@ -1150,8 +1152,12 @@ void cached_tile32(Operator &op)
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     load_tune_file();
     auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end())
+    if (it != g_tune_cache.end()) {
         op.ts[1] = it->second;
+    } else if (paired_shape_ok(op.ts[0], false)) {
+        op.ts[1] = op.ts[0];
+        op.ts[1].tb = 0;
+    }
 }
 
 template <typename T> aar_status autotune(aar_solver_t *S, int idx)
