@@ -1160,6 +1160,28 @@ void cached_tile32(Operator &op)
     }
 }
 
+// Tile of the FP64 passes of a mixed-precision solver (the refinement
+// residual, the operator apply): the tile file's FP64 line for the grid, else
+// the FP32 shape timed for it, with the paired flag dropped where FP64 has no
+// such tile.  The fixed default shape may leave most of the chip idle on a
+// small grid.
+void cached_tile64(Operator &op)
+{
+    const auto key = std::make_tuple(0, op.prob.radius, op.prob.velocity != nullptr ? 1 : 0, op.prob.n[0],
+                                     op.prob.n[1], op.prob.n[2]);
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    load_tune_file();
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+        op.ts[0] = it->second;
+    } else {
+        op.ts[0] = op.ts[1];
+        op.ts[0].tb = 0;
+        if (!paired_shape_ok(op.ts[0], true))
+            op.ts[0].pair = 0;
+    }
+}
+
 template <typename T> aar_status autotune(aar_solver_t *S, int idx)
 {
     const bool f64 = std::is_same<T, double>::value;
@@ -1716,12 +1738,19 @@ aar_status solve_one(aar_solver_t *S, int idx, const double *b, double *x, aar_r
         ra.b = S->b64;
         ra.out = S->r64;
         ra.partial = S->part_rho;
-        AAR_HIP(launch_stencil_f64(kResid, Prec::F64, R64.radius, R64.conv, R64.ts, ra, nullptr, s));
+        // one partial per workgroup of this launch: the residual pass always
+        // runs the one-point layout, whose grid differs from the paired one
+        // that R64.rho_blocks counts when the tile has the paired flag
+        int rtx, rty, rtz, resid_blocks = 0;
+        stencil_grid(op.prob.n[0], op.prob.n[1], op.prob.n[2], R64.ts, &rtx, &rty, &rtz, &resid_blocks);
+        if (resid_blocks > S->part_rho_cap)
+            return fail(AAR_ERR_DEVICE, "residual grid exceeds the partial-sum workspace");
+        AAR_HIP(launch_stencil_f64(kResid, Prec::F64, R64.radius, R64.conv, R64.ts, ra, &resid_blocks, s));
         if (pa.flags & AAR_FLAG_DEFLATE_CONSTANT) {
             AAR_HIP(launch_deflate(S->x64, S->r64, N, 1.0 / op.prob.shift, S->part_norm, nb_blocks, S->scal, s));
             AAR_HIP(launch_finish_norm(S->scal, S->part_norm, nb_blocks, s));
         } else {
-            AAR_HIP(launch_finish_norm(S->scal, S->part_rho, R64.rho_blocks, s));
+            AAR_HIP(launch_finish_norm(S->scal, S->part_rho, resid_blocks, s));
         }
         AAR_HIP(hipMemcpyAsync(host_scal, S->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         AAR_HIP(hipStreamSynchronize(s));
@@ -2768,6 +2797,8 @@ aar_status aar_create(aar_solver *out, const aar_problem *problems, int32_t coun
             return st;
         if (!S->mixed && S->hist == Prec::F32)
             cached_tile32(S->ops[0]);
+        if (S->mixed)
+            cached_tile64(S->ops[0]);
         AAR_HIP(hipStreamSynchronize(S->stream));
     }
     *out = S.release();
