@@ -589,7 +589,7 @@ hipError_t launch_stencil_complex(int mode, int radius, const TileShape &ts, Ste
                                   hipStream_t s);
 // Imaginary parts of the Hermitian Gram products (the real parts come from
 // launch_gram over the interleaved vectors).
-hipError_t launch_cgram_im(const GramArgs &a, int blocks, hipStream_t s);
+hipError_t launch_cgram(const GramArgs &a, int blocks, hipStream_t s);
 hipError_t launch_clsq(const LsqArgs &a, double omega_im, double beta_im, hipStream_t s);
 hipError_t launch_cupdate(const UpdateArgs<zd> &a, int blocks, hipStream_t s);
 hipError_t launch_cnorm_partial(const zd *v, int64_t N, double *partial, int blocks, hipStream_t s);

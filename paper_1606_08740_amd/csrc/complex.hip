@@ -11,12 +11,11 @@
 //   stencil passes   the one-point 2.5D tile of the real passes, instantiated
 //                    for the complex type (sweep, Anderson-step residual with
 //                    the |b - A x|^2 partials, operator apply);
-//   Gram products   G = F^H F (upper triangle) and c = F^H f_k, columns of F
+//   k_cgram          G = F^H F (upper triangle) and c = F^H f_k, columns of F
 //                    formed as differences of consecutive history slots,
-//                    products accumulated in FP64: the real parts by the real
-//                    k_gram over the interleaved vectors, the imaginary parts
-//                    by k_cgram_im; per-workgroup partials, summed in a fixed
-//                    order by k_gram_finish into [Re G, Re c | Im G, Im c];
+//                    real and imaginary parts accumulated in FP64 in one pass;
+//                    per-workgroup partials, summed in a fixed order by
+//                    k_gram_finish into [Re G, Re c | Im G, Im c];
 //   k_clsq           one wave: convergence test, gamma = G^+ c through the real
 //                    form [[Re G, -Im G], [Im G, Re G]] of the Hermitian G (the
 //                    one-wave Jacobi pseudoinverse of the real solve, with the
@@ -81,22 +80,26 @@ hipError_t launch_stencil_complex(int mode, int radius, const TileShape &ts, Ste
 // ---------------------------------------------------------------------------
 // Hermitian Gram products
 // ---------------------------------------------------------------------------
-// Imaginary parts of G = F^H F and c = F^H f_k.  The real parts,
-// Re(conj(a) b) = a_re b_re + a_im b_im summed over the points, are the real
-// Gram products of the history viewed as interleaved (re, im) vectors of
-// twice the length, which the real k_gram forms; this pass forms the rest:
-// Im G_cc2 = sum (dr_c di_c2 - di_c dr_c2) for c < c2 (the diagonal of a
-// Hermitian matrix is real: those entries stay exactly 0), and
-// Im c_c = sum (dr_c fi_k - di_c fr_k).  Entries in the real pass's order;
-// per-workgroup partials in the entry-major table k_gram_finish sums.  With a
-// full history the loads of the next point are issued before the products
-// of the current one.
+// G = F^H F and c = F^H f_k in one pass over the history, with d_c the
+// column differences and (fr, fi) = f_k:
+//   Re G_cc2 = sum (dr_c dr_c2 + di_c di_c2)  (c <= c2),
+//   Im G_cc2 = sum (dr_c di_c2 - di_c dr_c2)  (c < c2; the diagonal of a
+//              Hermitian matrix is real, those entries stay exactly 0),
+//   Re c_c = sum (dr_c fr + di_c fi),  Im c_c = sum (dr_c fi - di_c fr),
+// entries in the real Gram's order (upper triangle by rows, then c).
+// Per-workgroup partials: the real table (NE entries x the grid,
+// entry-major), then the imaginary table, each summed by k_gram_finish.
+// With a full history the loads of the next point are issued before the
+// products of the current one.  Complex values are kept as separate re and
+// im doubles, so no run-time selection of a value touches private memory.
+// One pass reads the history slots once for both parts.
 template <int MC>
-__global__ __launch_bounds__(kThreads) void k_cgram_im(const GramArgs a)
+__global__ __launch_bounds__(kThreads) void k_cgram(const GramArgs a)
 {
     constexpr int NP = MC * (MC + 1) / 2;
     constexpr int NE = NP + MC;
-    __shared__ double red[kThreads / 64][NE];
+    __shared__ double red_re[kThreads / 64][NE];
+    __shared__ double red_im[kThreads / 64][NE];
     const InstState *s = a.state;
     if (s->status != kRunning)
         return;
@@ -111,70 +114,93 @@ __global__ __launch_bounds__(kThreads) void k_cgram_im(const GramArgs a)
         const int tt = t <= l ? t : l;
         slot[t] = ring + (int64_t)((k - l + tt) % a.nslots) * a.slot_stride;
     }
-    double acc[NE];
+    double are[NE], aim[NE];
 #pragma unroll
-    for (int e = 0; e < NE; ++e)
-        acc[e] = 0.0;
-    // products of one point: fv[0..MC] the history values, f_k at position
-    // fkpos, differences past the history length l are zero
-    auto accumulate = [&](const zd *fv, int lh) {
-        zd fk = zd();
+    for (int e = 0; e < NE; ++e) {
+        are[e] = 0.0;
+        aim[e] = 0.0;
+    }
+    // products of one point: history values (vr, vi)[0..MC], f_k at position
+    // lh, differences past the history length are zero
+    auto accumulate = [&](const double *vr, const double *vi, int lh) {
+        double fr = 0.0, fi = 0.0;
 #pragma unroll
-        for (int t = 0; t <= MC; ++t)
-            fk = t == lh ? fv[t] : fk;
-        zd d[MC];
+        for (int t = 0; t <= MC; ++t) {
+            fr = t == lh ? vr[t] : fr;
+            fi = t == lh ? vi[t] : fi;
+        }
+        double dr[MC], di[MC];
 #pragma unroll
-        for (int c = 0; c < MC; ++c)
-            d[c] = c < lh ? fv[c + 1] - fv[c] : zd();
+        for (int c = 0; c < MC; ++c) {
+            dr[c] = c < lh ? vr[c + 1] - vr[c] : 0.0;
+            di[c] = c < lh ? vi[c + 1] - vi[c] : 0.0;
+        }
         int e = 0;
 #pragma unroll
         for (int c = 0; c < MC; ++c) {
-            ++e;   // diagonal: real
 #pragma unroll
-            for (int c2 = c + 1; c2 < MC; ++c2)
-                acc[e++] += d[c].re * d[c2].im - d[c].im * d[c2].re;
+            for (int c2 = c; c2 < MC; ++c2) {
+                are[e] += dr[c] * dr[c2] + di[c] * di[c2];
+                if (c2 > c)
+                    aim[e] += dr[c] * di[c2] - di[c] * dr[c2];
+                ++e;
+            }
         }
 #pragma unroll
-        for (int c = 0; c < MC; ++c)
-            acc[NP + c] += d[c].re * fk.im - d[c].im * fk.re;
+        for (int c = 0; c < MC; ++c) {
+            are[NP + c] += dr[c] * fr + di[c] * fi;
+            aim[NP + c] += dr[c] * fi - di[c] * fr;
+        }
     };
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l == MC) {
-        zd cur[MC + 1], nxt[MC + 1];
+        double cr[MC + 1], ci[MC + 1], nr[MC + 1], ni[MC + 1];
         if (i < a.N) {
 #pragma unroll
-            for (int t = 0; t <= MC; ++t)
-                cur[t] = slot[t][i];
+            for (int t = 0; t <= MC; ++t) {
+                const zd v = slot[t][i];
+                cr[t] = v.re;
+                ci[t] = v.im;
+            }
         }
         for (; i < a.N; i += stride) {
             const int64_t in = i + stride;
             if (in < a.N) {
 #pragma unroll
-                for (int t = 0; t <= MC; ++t)
-                    nxt[t] = slot[t][in];
+                for (int t = 0; t <= MC; ++t) {
+                    const zd v = slot[t][in];
+                    nr[t] = v.re;
+                    ni[t] = v.im;
+                }
             }
-            accumulate(cur, MC);
+            accumulate(cr, ci, MC);
 #pragma unroll
-            for (int t = 0; t <= MC; ++t)
-                cur[t] = nxt[t];
+            for (int t = 0; t <= MC; ++t) {
+                cr[t] = nr[t];
+                ci[t] = ni[t];
+            }
         }
     } else {
         for (; i < a.N; i += stride) {
-            zd fv[MC + 1];
+            double vr[MC + 1], vi[MC + 1];
 #pragma unroll
-            for (int t = 0; t <= MC; ++t)
-                fv[t] = slot[t][i];
-            accumulate(fv, l);
+            for (int t = 0; t <= MC; ++t) {
+                const zd v = slot[t][i];
+                vr[t] = v.re;
+                vi[t] = v.im;
+            }
+            accumulate(vr, vi, l);
         }
     }
     const int w = threadIdx.x >> 6;
-    wave_sums_to<NE>(acc, red[w]);
+    wave_sums_to<NE>(are, red_re[w]);
+    wave_sums_to<NE>(aim, red_im[w]);
     __syncthreads();
-    for (int e = threadIdx.x; e < NE; e += kThreads) {
+    for (int e = threadIdx.x; e < 2 * NE; e += kThreads) {
         double v = 0.0;
         for (int ww = 0; ww < kThreads / 64; ++ww)
-            v += red[ww][e];
+            v += e < NE ? red_re[ww][e] : red_im[ww][e - NE];
         a.partial[(int64_t)e * gridDim.x + blockIdx.x] = v;
     }
 }
@@ -183,22 +209,22 @@ __global__ __launch_bounds__(kThreads) void k_cgram_im(const GramArgs a)
 // m x m solve has order 2m <= kMaxM)
 constexpr int kMaxComplexM = 8;
 
-hipError_t launch_cgram_im(const GramArgs &a, int blocks, hipStream_t s)
+hipError_t launch_cgram(const GramArgs &a, int blocks, hipStream_t s)
 {
     switch (a.m) {
-#define AAR_CGI(M)                                                                         \
+#define AAR_CG(M)                                                                          \
     case M:                                                                                \
-        hipLaunchKernelGGL((k_cgram_im<M>), dim3(blocks), dim3(kThreads), 0, s, a);        \
+        hipLaunchKernelGGL((k_cgram<M>), dim3(blocks), dim3(kThreads), 0, s, a);           \
         return hipGetLastError();
-        AAR_CGI(1)
-        AAR_CGI(2)
-        AAR_CGI(3)
-        AAR_CGI(4)
-        AAR_CGI(5)
-        AAR_CGI(6)
-        AAR_CGI(7)
-        AAR_CGI(8)
-#undef AAR_CGI
+        AAR_CG(1)
+        AAR_CG(2)
+        AAR_CG(3)
+        AAR_CG(4)
+        AAR_CG(5)
+        AAR_CG(6)
+        AAR_CG(7)
+        AAR_CG(8)
+#undef AAR_CG
     default:
         return hipErrorInvalidValue;
     }

@@ -242,7 +242,6 @@ struct aar_solver_t {
     bool cplx = false;
     double shift_im = 0.0, omega_im = 0.0, beta_im = 0.0;
     Path<zd> pz;
-    int cgram_re_blocks = 0;   // workgroups of the real-part Gram pass (2N values)
 
     // general sparse system (aar_create_csr): CSR arrays, block bounds,
     // level schedules and ILU(0) factors on the device; vectors in p64
@@ -739,17 +738,12 @@ hipError_t enqueue_cycle_complex(aar_solver_t *S, const Path<zd> &P, hipStream_t
     g.p = pa.p;
     g.nslots = pa.m + 1;
     g.ne = S->ne;
-    // real parts: the real Gram products of the interleaved (re, im) vectors
-    GramArgs gr = g;
-    gr.N = 2 * P.N;
-    gr.slot_stride = 2 * P.slot_stride;
-    double *part_im = S->part_gram + (size_t)S->cgram_re_blocks * S->ne;
-    if ((e = launch_gram(Prec::F64, gr, S->cgram_re_blocks, s)) != hipSuccess)
+    // real and imaginary parts in one pass: two partial tables, each summed
+    // into its half of gram_final
+    double *part_im = S->part_gram + (size_t)P.gram_blocks * S->ne;
+    if ((e = launch_cgram(g, P.gram_blocks, s)) != hipSuccess)
         return e;
-    g.partial = part_im;
-    if ((e = launch_cgram_im(g, P.gram_blocks, s)) != hipSuccess)
-        return e;
-    if ((e = launch_gram_finish(S->part_gram, S->cgram_re_blocks, S->gram_final, S->ne, S->state, pa.p, s)) !=
+    if ((e = launch_gram_finish(S->part_gram, P.gram_blocks, S->gram_final, S->ne, S->state, pa.p, s)) !=
         hipSuccess)
         return e;
     if ((e = launch_gram_finish(part_im, P.gram_blocks, S->gram_final + S->ne, S->ne, S->state, pa.p, s)) !=
@@ -2963,11 +2957,9 @@ aar_status aar_create_complex(aar_solver *out, const aar_problem *problem, const
     S->state = S->alloc<InstState>(1, &st);
     S->part_rho = S->alloc<double>(z.max_stencil_blocks, &st);
     S->part_rho_cap = z.max_stencil_blocks;
-    // Gram partials: the real-part pass over 2N values, then the imaginary-part pass
-    S->cgram_re_blocks = gram_blocks(2 * z.maxN, params->m);
+    // Gram partials: the real-part table, then the imaginary-part table
     S->part_gram = S->alloc<double>(
-        std::max((size_t)(S->cgram_re_blocks + gram_blocks(z.maxN, params->m)), (size_t)z.max_stencil_blocks) * z.ne,
-        &st);
+        std::max(2 * (size_t)gram_blocks(z.maxN, params->m), (size_t)z.max_stencil_blocks) * z.ne, &st);
     S->part_norm = S->alloc<double>(z.gram_blocks, &st);
     S->gram_final = S->alloc<double>(2 * z.ne, &st);
     S->scal = S->alloc<double>(8, &st);
