@@ -738,15 +738,12 @@ hipError_t enqueue_cycle_complex(aar_solver_t *S, const Path<zd> &P, hipStream_t
     g.p = pa.p;
     g.nslots = pa.m + 1;
     g.ne = S->ne;
-    // real and imaginary parts in one pass: two partial tables, each summed
-    // into its half of gram_final
-    double *part_im = S->part_gram + (size_t)P.gram_blocks * S->ne;
+    // real and imaginary parts in one pass: two entry-major partial tables
+    // back to back, which one finishing launch over 2 ne entries sums into
+    // [Re G, Re c | Im G, Im c]
     if ((e = launch_cgram(g, P.gram_blocks, s)) != hipSuccess)
         return e;
-    if ((e = launch_gram_finish(S->part_gram, P.gram_blocks, S->gram_final, S->ne, S->state, pa.p, s)) !=
-        hipSuccess)
-        return e;
-    if ((e = launch_gram_finish(part_im, P.gram_blocks, S->gram_final + S->ne, S->ne, S->state, pa.p, s)) !=
+    if ((e = launch_gram_finish(S->part_gram, P.gram_blocks, S->gram_final, 2 * S->ne, S->state, pa.p, s)) !=
         hipSuccess)
         return e;
     LsqArgs l;
