@@ -176,3 +176,32 @@ def test_csr_create_rejects(matrix, pc, nblocks, change, status):
     with pytest.raises(aar.AarError) as ei:
         aar.aar_create_csr(*matrix, pc, nblocks, aar.make_params(prm))
     assert ei.value.status == status
+
+
+def test_tile_file_lines_pass_the_loader_rules():
+    """Every line of the committed tile file passes the rules the library's
+    loader applies (a line that fails them is skipped without an error, so
+    its grid would silently lose its tuned shape): precision 0 (FP64),
+    1 (FP32) or 2 (complex sweep), rows per thread 1, 2 or 4, a positive z
+    depth, order bits 0..3, temporal depth 0..5 only for one-point tiles,
+    paired shapes that are compiled (FP64: 4 waves x 1-2 rows or 8 waves x 1
+    row; FP32 adds 8 waves x 2 rows and 16 waves x 1 row), and complex tiles
+    one-point with at most 2 rows.  Each grid and precision appears once."""
+    path = os.path.join(os.path.dirname(aar.LIB_PATH), "tuned_tiles.txt")
+    seen = set()
+    lines = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert lines
+    for f in lines:
+        assert len(f) == 11, f
+        prec, radius, conv, n0, n1, n2, ry, cz, order, pair, tb = map(int, f)
+        assert prec in (0, 1, 2) and 1 <= radius <= 6 and conv in (0, 1), f
+        assert ry in (1, 2, 4) and cz >= 1 and 0 <= order <= 3 and 0 <= tb <= 5, f
+        assert tb < 2 or pair == 0, f
+        f64 = prec != 1
+        ok = {0: True, 1: ry in (1, 2), 2: ry == 1 or (not f64 and ry == 2), 3: not f64 and ry == 1}.get(pair, False)
+        assert ok, f
+        if prec == 2:
+            assert pair == 0 and tb == 0 and ry <= 2 and conv == 0, f
+        key = (prec, radius, conv, n0, n1, n2)
+        assert key not in seen, f
+        seen.add(key)
