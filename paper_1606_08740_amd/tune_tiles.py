@@ -9,16 +9,16 @@ A sweep-only objective can pick a shape that is slower over a whole cycle
 paired layout, and the update depend on it too), so this script times whole
 solves instead: for each evaluation grid and precision it writes each
 candidate as the grid's only tile line, solves the workload's system once to
-warm up and then `--reps` times, and keeps the fastest.  The winners are
-written to the output tile file (one line per grid and precision:
-"prec radius conv n0 n1 n2 rows_per_thread z_depth order pair depth"),
-which the library reads next to itself, so committed choices are
-reproducible.
+warm up and then `--reps` times, and keeps the fastest.  The winners replace
+their grids' lines in the output tile file (one line per grid and precision:
+"prec radius conv n0 n1 n2 rows_per_thread z_depth order pair depth"); the
+file's other lines are kept.  The library reads the file next to itself, so
+committed choices are reproducible.
 
 The batched engine uses one tile shape for all systems of a batch; with
 --batched the shape is chosen by timing whole batched solves of the
 512-system Helmholtz workload for rows per thread {1, 2, 4} x z depth
-{4, 8, 16, 32}, and the winner is appended as a batch line (grid fields
+{4, 8, 16, 32}, and the winner replaces the batch line (grid fields
 0 0 0).
 
 Usage: python -m paper_1606_08740_amd.tune_tiles [--batched] [--reps K] [--grids c1,c2,c3,c4] [output path]
@@ -69,6 +69,18 @@ def candidates(prob, f64):
     return out
 
 
+def merge_lines(old_text, new_lines):
+    """The tile file after tuning: the header, then the old file's lines
+    whose grid and precision (the first six fields) were not tuned again, in
+    their order, then the new lines.  Batch and complex lines, and grids left
+    out of this run, are kept."""
+    key = lambda line: tuple(line.split()[:6])
+    fresh = {key(line) for line in new_lines}
+    kept = [line if line.endswith("\n") else line + "\n" for line in old_text.splitlines()
+            if line.strip() and not line.startswith("#") and key(line) not in fresh]
+    return HEADER + "".join(kept) + "".join(new_lines)
+
+
 def time_solve(prob, b, params, reps):
     import torch
     from paper_1606_08740_amd import aar
@@ -112,9 +124,9 @@ def main(path, reps, grids):
                     best = (dt, line)
             lines.append(best[1])
             print(f"{label} prec={prec} best: {best[1].strip()} ({best[0] * 1e3:.3f} ms)", flush=True)
+    old = open(path).read() if os.path.exists(path) else ""
     with open(path, "w") as f:
-        f.write(HEADER)
-        f.writelines(lines)
+        f.write(merge_lines(old, lines))
     print(open(path).read())
 
 
@@ -151,8 +163,9 @@ def tune_batched(path):
                 if best is None or dt < best[0]:
                     best = (dt, ry, cz)
         lines.append(f"{prec} {radius} 0 0 0 0 {best[1]} {best[2]} 0 0 0\n")
-    with open(path, "a") as f:
-        f.writelines(lines)
+    old = open(path).read() if os.path.exists(path) else ""
+    with open(path, "w") as f:
+        f.write(merge_lines(old, lines))
     print("".join(lines))
 
 

@@ -36,3 +36,16 @@ def test_workload_shapes():
     assert min(ns) >= 16 and max(ns) <= 96
     assert all(0 < p.shift < 10 for p in wb.problems)
     assert all(p.radius == 4 and p.bc == (1, 1, 1) for p in wb.problems)
+
+
+def test_tile_tuner_keeps_lines_it_did_not_tune():
+    """Re-tuning some grids rewrites their lines and keeps every other line
+    of the tile file (batch lines, complex lines, other grids) in order."""
+    from paper_1606_08740_amd import tune_tiles
+    old = ("# header\n0 6 0 192 192 192 1 28 0 2 0\n1 6 0 192 192 192 1 16 1 2 0\n"
+           "0 4 0 0 0 0 2 32 0 0 0\n2 3 0 72 72 72 1 4 2 0 0\n")
+    new = ["1 6 0 192 192 192 1 16 0 2 0\n", "0 1 0 32 32 32 1 2 1 1 0\n"]
+    out = tune_tiles.merge_lines(old, new).splitlines()
+    assert out[0].startswith("#")
+    assert out[1:] == ["0 6 0 192 192 192 1 28 0 2 0", "0 4 0 0 0 0 2 32 0 0 0", "2 3 0 72 72 72 1 4 2 0 0",
+                       "1 6 0 192 192 192 1 16 0 2 0", "0 1 0 32 32 32 1 2 1 1 0"]
